@@ -1,0 +1,200 @@
+"""Seeded synthetic inputs for the porous-media lattice Boltzmann solver.
+
+This module only builds input fields (porosity eps, permeability kappa, Forchheimer coefficient
+C_F, solid mask) and run settings; it holds none of the method's arithmetic.  The tests feed the
+same arrays to the GPU library and to the CPU oracle.  Arrays are shaped [nz, ny, nx] (x
+fastest); two-dimensional cases use nz = 1.
+
+Recipes (each states the workload it stands for):
+
+* ``channel_step_2d`` -- D2Q9 FP64 128x64 channel, periodic in x, solid rows y = 0 and y = 63,
+  porosity 1 for x < 64 and 0.4 for x >= 64 with permeability 1e-3 and Forchheimer coefficient
+  0.55/sqrt(K) in the porous half, nu = 1/6 with nu_eff = nu/phi, body force 1e-6 along x.
+* ``random_porosity_3d`` -- D3Q27 periodic box with a seeded Gaussian random porosity field:
+  white noise from numpy's PCG64(seed), periodic FFT filter with a Gaussian kernel whose
+  covariance is exp(-r^2 / (2 l^2)) with l the correlation length (16 cells), standardised and
+  mapped through the normal CDF onto phi in (phi_min, 1); Kozeny-Carman permeability
+  K = d^2 phi^3 / (180 (1 - phi)^2) with d = 2 cells, C_F = 0.55 / sqrt(K); nu = 0.01; body force
+  1e-6 along x.
+* ``sphere_duct_3d`` -- D3Q27 duct with solid walls on the y and z faces and a porous sphere.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+from scipy.special import ndtr
+
+FORCH_F = 0.55          # Forchheimer constant of the workloads: C_F = 0.55 / sqrt(K)
+
+
+@dataclass
+class Workload:
+    """Fields and settings of one run; ``lattice`` is 9 (D2Q9) or 27 (D3Q27)."""
+    name: str
+    lattice: int
+    eps: np.ndarray
+    kappa: np.ndarray
+    forch: np.ndarray
+    mask: Optional[np.ndarray]
+    nu_f: float
+    nu_eff_ref: float
+    nu_eff_pow: int
+    b: tuple
+    rho0: float = 1.0
+    RT: float = 1.0 / 3.0
+    eta_eff: float = math.nan
+    steps: int = 0
+    rho_init: Optional[np.ndarray] = None
+    v_init: Optional[np.ndarray] = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def D(self) -> int:
+        return 2 if self.lattice == 9 else 3
+
+    @property
+    def shape(self):
+        return self.eps.shape
+
+    @property
+    def cells(self) -> int:
+        return int(np.prod(self.eps.shape))
+
+
+def kozeny_carman(phi: np.ndarray, d: float = 2.0) -> np.ndarray:
+    """K = d^2 phi^3 / (180 (1 - phi)^2); phi = 1 gives +inf."""
+    with np.errstate(divide="ignore"):
+        return d * d * phi ** 3 / (180.0 * (1.0 - phi) ** 2)
+
+
+def forchheimer(K: np.ndarray, F: float = FORCH_F) -> np.ndarray:
+    """C_F = F / sqrt(K); K = +inf gives 0."""
+    with np.errstate(divide="ignore"):
+        return F / np.sqrt(K)
+
+
+def gaussian_random_field(shape, ell: float, seed: int) -> np.ndarray:
+    """Standardised periodic Gaussian random field with covariance exp(-r^2 / (2 ell^2))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    noise = rng.standard_normal(shape)
+    s = ell / math.sqrt(2.0)              # kernel width: cov of filtered noise has width ell
+    ks = [np.fft.fftfreq(n) * 2.0 * math.pi for n in shape[:-1]]
+    ks.append(np.fft.rfftfreq(shape[-1]) * 2.0 * math.pi)
+    k2 = np.zeros([len(k) for k in ks])
+    for ax, k in enumerate(ks):
+        sh = [1] * len(shape)
+        sh[ax] = len(k)
+        k2 = k2 + (k.reshape(sh)) ** 2
+    axes = list(range(len(shape)))
+    g = np.fft.irfftn(np.fft.rfftn(noise) * np.exp(-0.5 * k2 * s * s), s=shape, axes=axes)
+    g -= g.mean()
+    g /= g.std()
+    return g
+
+
+def random_porosity_3d(n=256, seed=0, ell=16.0, phi_min=0.3, d=2.0, nu=0.01, b=1e-6,
+                       steps=1000, shape=None) -> Workload:
+    shape = tuple(shape) if shape is not None else (n, n, n)
+    g = gaussian_random_field(shape, ell, seed)
+    phi = phi_min + (1.0 - phi_min) * ndtr(g)
+    K = kozeny_carman(phi, d)
+    return Workload(name=f"random-porosity D3Q27 {shape[2]}x{shape[1]}x{shape[0]} seed {seed}",
+                    lattice=27, eps=phi, kappa=K, forch=forchheimer(K), mask=None,
+                    nu_f=nu, nu_eff_ref=nu, nu_eff_pow=0, b=(b, 0.0, 0.0), steps=steps,
+                    meta={"seed": seed, "ell": ell, "phi_min": phi_min, "d": d})
+
+
+def random_porosity_2d(nx=96, ny=64, seed=0, ell=8.0, phi_min=0.3, d=2.0, nu=0.05,
+                       b=1e-6) -> Workload:
+    g = gaussian_random_field((1, ny, nx), ell, seed)
+    phi = phi_min + (1.0 - phi_min) * ndtr(g)
+    K = kozeny_carman(phi, d)
+    return Workload(name=f"random-porosity D2Q9 {nx}x{ny} seed {seed}", lattice=9, eps=phi,
+                    kappa=K, forch=forchheimer(K), mask=None, nu_f=nu, nu_eff_ref=nu,
+                    nu_eff_pow=0, b=(b, 0.0, 0.0), meta={"seed": seed})
+
+
+def channel_step_2d(nx=128, ny=64, x_step=64, phi_porous=0.4, K=1e-3, nu=1.0 / 6.0, g=1e-6,
+                    steps=10000) -> Workload:
+    eps = np.ones((1, ny, nx))
+    eps[:, :, x_step:] = phi_porous
+    kappa = np.full_like(eps, np.inf)
+    kappa[:, :, x_step:] = K
+    mask = np.zeros(eps.shape, dtype=np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, ny - 1, :] = 1
+    return Workload(name=f"step channel D2Q9 {nx}x{ny}", lattice=9, eps=eps, kappa=kappa,
+                    forch=forchheimer(kappa), mask=mask, nu_f=nu, nu_eff_ref=nu,
+                    nu_eff_pow=-1, b=(g, 0.0, 0.0), steps=steps)
+
+
+def sphere_duct_3d(nx=768, ny=384, nz=384, radius=96.0, center=None, phi=0.5, K=5e-3,
+                   nu=0.052, dp=1e-4, rho0=1.0, RT=1.0 / 3.0, steps=20000) -> Workload:
+    """Duct with solid walls on the y and z faces and a porous sphere; the pressure drop dp is
+    carried by an equivalent body force b_x = dp / (rho0 L_x) with p = rho RT."""
+    center = center or (nx / 4.0, ny / 2.0, nz / 2.0)
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5,
+                          indexing="ij")
+    inside = ((x - center[0]) ** 2 + (y - center[1]) ** 2 + (z - center[2]) ** 2) < radius ** 2
+    eps = np.where(inside, phi, 1.0)
+    kappa = np.where(inside, K, np.inf)
+    mask = np.zeros(eps.shape, dtype=np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, -1, :] = 1
+    mask[0, :, :] = 1
+    mask[-1, :, :] = 1
+    return Workload(name=f"porous sphere in duct D3Q27 {nx}x{ny}x{nz}", lattice=27, eps=eps,
+                    kappa=kappa, forch=forchheimer(kappa), mask=mask, nu_f=nu, nu_eff_ref=nu,
+                    nu_eff_pow=0, b=(dp / (rho0 * nx), 0.0, 0.0), rho0=rho0, RT=RT,
+                    steps=steps)
+
+
+def uniform_box(D=2, n=8, eps=0.5, K=0.1, cf=0.0, nu=0.05, b=(1e-4, 0.0, 0.0)) -> Workload:
+    shape = (1, n, n) if D == 2 else (n, n, n)
+    return Workload(name=f"uniform box D{D}", lattice=9 if D == 2 else 27,
+                    eps=np.full(shape, eps), kappa=np.full(shape, K), forch=np.full(shape, cf),
+                    mask=None, nu_f=nu, nu_eff_ref=nu, nu_eff_pow=0, b=tuple(b))
+
+
+def smoothstep_cinf(psi: np.ndarray) -> np.ndarray:
+    """C-infinity smoothstep S(psi): 0 for psi <= 0, 1 for psi >= 1, exp-ratio in between."""
+    psi = np.asarray(psi, dtype=np.float64)
+    out = np.where(psi >= 1.0, 1.0, 0.0)
+    inner = (psi > 0.0) & (psi < 1.0)
+    p = psi[inner]
+    a = np.exp(-1.0 / p)
+    c = np.exp(-1.0 / (1.0 - p))
+    out[inner] = a / (a + c)
+    return out
+
+
+def heterogeneous_channel_setup1(H: int, eps_bot=1.0, eps_top=0.5, phi_bot=0.1, phi_top=0.1):
+    """Wall-normal two-plateau porosity with a smoothstep transition, sampled at the fluid rows
+    of a channel with halfway walls at y = 0 and y = H (row j sits at y = j - 1/2)."""
+    y = np.arange(1, H + 1) - 0.5
+    psi = ((y / H) - phi_bot) / (1.0 - phi_top - phi_bot)
+    return y, eps_bot + (eps_top - eps_bot) * smoothstep_cinf(psi)
+
+
+def request_stream(n_requests=512, seed=0):
+    """Serving stream: per request a seeded lattice choice, sides, phi_min and nu."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    reqs = []
+    for r in range(n_requests):
+        rr = np.random.Generator(np.random.PCG64(seed * 100003 + r))
+        lattice = 9 if rr.random() < 0.5 else 27
+        if lattice == 9:
+            sides = (1, int(rr.integers(64, 1025)), int(rr.integers(64, 1025)))
+        else:
+            sides = tuple(int(s) for s in rr.integers(32, 193, size=3))
+        reqs.append({"id": r, "seed": r, "lattice": lattice, "shape": sides,
+                     "phi_min": float(rr.uniform(0.2, 0.6)), "nu": float(rr.uniform(0.005, 0.05)),
+                     "arrival": float(rng.exponential(1.0))})
+    t = 0.0
+    for q in reqs:
+        t += q["arrival"]
+        q["arrival_time"] = t
+    return reqs

@@ -1,0 +1,295 @@
+"""Pins of the oracle's dynamics against closed forms, invariants and the paper's linear theory.
+
+Each test names the passage it checks.  Expected values come from closed-form solutions, from a
+boundary-value problem solved with SciPy (as the paper does), from conservation laws or from the
+paper's dispersion analysis; none comes from the oracle itself.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import solve_bvp
+from scipy.optimize import brentq
+
+import oracle
+from paper_2606_29619_amd import workloads
+from tests import oracle_cases as oc
+
+
+# --------------------------------------------------------------------------------------------
+# Uniform periodic box: the scheme reduces to the trapezoidal rule for dv/dt = a(v)
+# --------------------------------------------------------------------------------------------
+def _trapezoid_reference(eps, b, muD, muF, steps):
+    """dv/dt = a(v) = eps b - mu_D v - mu_F |v| v integrated with the trapezoidal rule
+    v_{n+1} - a(v_{n+1})/2 = v_n + a(v_n)/2, each implicit step solved by bracketing."""
+    b = np.asarray(b, float)
+    a = lambda v: eps * b - muD * v - muF * np.linalg.norm(v) * v
+    v = np.zeros_like(b)
+    out = [v.copy()]
+    for _ in range(steps):
+        rhs = v + 0.5 * a(v)
+        # unknown w solves w - a(w)/2 = rhs, i.e. w (1 + muD/2) + (muF/2)|w| w = rhs + eps b/2
+        g = rhs + 0.5 * eps * b
+        gn = np.linalg.norm(g)
+        if gn == 0:
+            v = np.zeros_like(b)
+        else:
+            s = brentq(lambda s: (1 + 0.5 * muD) * s + 0.5 * muF * s * s - gn, 0.0, gn,
+                       xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=500)
+            v = s * g / gn
+        out.append(v.copy())
+    return np.array(out)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_uniform_box_is_trapezoidal_rule(D):
+    """Eqs. (dicrete_scheme), (transformed_momentum_moment), (accel): in a uniform periodic box
+    collision adds exactly rho a to the transformed momentum, so v follows the trapezoidal rule
+    of dv/dt = a(v); its fixed point is the Darcy-Forchheimer balance."""
+    eps, K, cf, nu = 0.5, 0.2, 1.5, 0.05
+    b = (2e-3, -1e-3, 5e-4)[:D]
+    n = 4
+    shape = (1, n, n) if D == 2 else (n, n, n)
+    o = oracle.Oracle(oracle.OracleConfig(
+        D=D, eps=np.full(shape, eps), kappa=np.full(shape, K), cf=np.full(shape, cf),
+        nu_f=nu, nu_eff_ref=nu, b=tuple(b) + (0.0,) * (3 - D)))
+    muD, muF = eps * nu / K, eps * cf
+    ref = _trapezoid_reference(eps, b, muD, muF, 400)
+    got = []
+    for _ in range(401):
+        _, v, _ = o.moments()
+        vv = v.reshape(D, -1)
+        assert np.ptp(vv, axis=1).max() == 0.0          # the state stays exactly uniform
+        got.append(vv[:, 0])
+        o.step(1)
+    got = np.array(got)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < 1e-13, err
+    bn = np.linalg.norm(b)
+    vstar = 2 * eps * bn / (muD + math.sqrt(muD * muD + 4 * muF * eps * bn))
+    o.step(3000)
+    _, v, _ = o.moments()
+    np.testing.assert_allclose(v.reshape(D, -1)[:, 0], vstar * np.asarray(b) / bn, rtol=1e-12)
+
+
+def test_darcy_limit_of_uniform_box():
+    """Darcy limit (mu_F = 0): the steady superficial velocity is kappa b / nu_f."""
+    eps, K, nu = 0.3, 0.05, 0.02
+    shape = (1, 3, 3)
+    o = oracle.Oracle(oracle.OracleConfig(
+        D=2, eps=np.full(shape, eps), kappa=np.full(shape, K), cf=np.zeros(shape), nu_f=nu,
+        nu_eff_ref=nu, b=(1e-5, 0.0, 0.0)))
+    o.step(20000)
+    _, v, _ = o.moments()
+    np.testing.assert_allclose(v[0], K * 1e-5 / nu, rtol=1e-10)
+
+
+# --------------------------------------------------------------------------------------------
+# Conservation
+# --------------------------------------------------------------------------------------------
+def test_mass_conservation_heterogeneous_2d():
+    """Eq. (transformed_density_moment_2): collision conserves sum_i f-bar and streaming with
+    halfway bounce-back only moves populations, so the total mass is invariant."""
+    w = workloads.random_porosity_2d(nx=40, ny=24, seed=5, ell=4.0, nu=0.05, b=1e-4)
+    mask = np.zeros(w.shape, dtype=np.uint8)
+    mask[:, 0, :] = mask[:, -1, :] = 1
+    mask[:, 8:12, 15:19] = 1                                       # a solid block
+    o = oracle.Oracle(oracle.OracleConfig(
+        D=2, eps=w.eps, kappa=w.kappa, cf=w.forch, mask=mask, nu_f=w.nu_f,
+        nu_eff_ref=w.nu_eff_ref, nu_eff_pow=-1, b=w.b))
+    m0 = o.stats()["mass"]
+    o.step(1500)
+    s = o.stats()
+    assert abs(s["mass"] - m0) / m0 < 1e-12
+    assert s["vmax"] > 1e-6 and s["nonfinite"] == 0
+
+
+def test_mass_conservation_heterogeneous_3d():
+    w = workloads.random_porosity_3d(shape=(10, 12, 14), seed=2, ell=3.0, nu=0.05, b=2e-4)
+    mask = np.zeros(w.shape, dtype=np.uint8)
+    mask[3:6, 4:8, 5:9] = 1
+    o = oracle.Oracle(oracle.OracleConfig(
+        D=3, eps=w.eps, kappa=w.kappa, cf=w.forch, mask=mask, nu_f=w.nu_f,
+        nu_eff_ref=w.nu_eff_ref, b=w.b, eta_eff=0.03))
+    m0 = o.stats()["mass"]
+    o.step(150)
+    assert abs(o.stats()["mass"] - m0) / m0 < 1e-13
+
+
+def test_momentum_budget_uniform_porosity():
+    """Eq. (transformed_momentum_moment_2): with uniform porosity (Delta_nu = 0) the velocity of
+    (v_(0))-(v_(1)) solves the implicit relation exactly, so in a periodic box one step changes
+    the total transformed momentum by exactly sum_x rho a."""
+    n = 12
+    shape = (1, n, n)
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    v0 = np.stack([0.02 * np.sin(2 * np.pi * y / n), 0.01 * np.cos(2 * np.pi * x / n)])[:, None]
+    rho0 = (1 + 0.01 * np.cos(2 * np.pi * (x + y) / n))[None]
+    o = oracle.Oracle(oracle.OracleConfig(
+        D=2, eps=np.full(shape, 0.6), kappa=np.full(shape, 0.3), cf=np.full(shape, 0.8),
+        nu_f=0.04, nu_eff_ref=0.04, b=(3e-4, -1e-4, 0.0), v_init=v0, rho_init=rho0,
+        eta_eff=0.02))
+    c, _ = oracle.lattice(2)
+    for _ in range(5):
+        o.step(3)
+        f = o.populations()
+        pi_before = np.einsum("ia,izyx->a", c[:, :2].astype(float), f)
+        rho, _, _ = o.moments()
+        acc = o.forcing_fields()["a"]
+        force = np.einsum("zyx,azyx->a", rho, acc)
+        o.step(1)
+        pi_after = np.einsum("ia,izyx->a", c[:, :2].astype(float), o.populations())
+        np.testing.assert_allclose(pi_after - pi_before, force, rtol=1e-10, atol=1e-16)
+
+
+# --------------------------------------------------------------------------------------------
+# Channels between halfway walls
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("D", [2, 3])
+def test_free_poiseuille_second_order(D):
+    """Free fluid (eps = 1, kappa = inf): the steady profile is the parabola
+    u = b/(2 nu) y (H - y) between the halfway walls, reached at second order in the spacing."""
+    nu, errs = 0.1, []
+    for H in (8, 16, 32):
+        b = 1e-4 / H ** 2
+        o = oc.channel(D, H, np.ones(H), np.full(H, np.inf), nu=nu, b=b)
+        oc.run_to_steady(o, tol=1e-10, chunk=400)
+        _, u = oc.profile(o)
+        y = np.arange(1, H + 1) - 0.5
+        ua = b / (2 * nu) * y * (H - y)
+        errs.append(np.abs(u - ua).max() / ua.max())
+    assert errs[-1] < 3e-3, errs
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+
+
+def _brinkman(y, H, eps, b, muD, nu):
+    """Eq. (Poiseuille_v_Darcy_analyt)."""
+    r = math.sqrt(muD / nu)
+    return eps * b / muD * (1 - np.cosh(r * (y - H / 2)) / np.cosh(r * H / 2))
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_brinkman_channel_closed_form(D):
+    """Homogeneous porous channel, Darcy limit (mu_F = 0): eq. (Poiseuille_v_Darcy_analyt),
+    with a resolved Brinkman layer (r H = 6); second-order convergence under refinement."""
+    eps, nu, errs = 0.5, 0.1, []
+    for H in (16, 32, 64):
+        r = 6.0 / H
+        kappa = eps / r ** 2                                       # mu_D = eps nu / kappa
+        b = 1e-5 * 6.0 ** 2 / H ** 2
+        o = oc.channel(D, H, np.full(H, eps), np.full(H, kappa), nu=nu, b=b)
+        oc.run_to_steady(o, tol=1e-10, chunk=400)
+        _, v = oc.profile(o)
+        y = np.arange(1, H + 1) - 0.5
+        va = _brinkman(y, H, eps, b, eps * nu / kappa, nu)
+        errs.append(np.abs(v - va).max() / va.max())
+    assert errs[-1] < 1e-3, errs
+    assert errs[0] / errs[1] > 3.2 and errs[1] / errs[2] > 3.5, errs
+
+
+def _solve_channel_bvp(H, eps_f, muD_f, muF_f, b, nu, intrinsic=False, deps_f=None):
+    """Reference profile from SciPy's collocation BVP solver, as in Sec. 5.2:
+    target model, eq. (Poiseuille_v_BVP): v'' + (eps b - mu_D v - mu_F |v| v)/nu = 0;
+    intrinsic-stress model, eq. (Poiseuille_u_BVP_wrong_visc_stress):
+    u'' + (eps'/eps) u' + (b - mu_D u - eps mu_F |u| u)/nu = 0, returned as v = eps u."""
+    ys = np.linspace(0, H, 1001)
+
+    def rhs(y, Y):
+        v, dv = Y
+        e, mD, mF = eps_f(y), muD_f(y), muF_f(y)
+        if intrinsic:
+            return np.vstack([dv, -(deps_f(y) / e) * dv - (b - mD * v - e * mF * np.abs(v) * v) / nu])
+        return np.vstack([dv, -(e * b - mD * v - mF * np.abs(v) * v) / nu])
+
+    bc = lambda Ya, Yb: np.array([Ya[0], Yb[0]])
+    sol = solve_bvp(rhs, bc, ys, np.zeros((2, ys.size)), tol=1e-10, max_nodes=200000)
+    assert sol.success
+    return lambda y: sol.sol(y)[0] * (eps_f(y) if intrinsic else 1.0)
+
+
+def test_forchheimer_channel_bvp():
+    """Homogeneous porous channel with Forchheimer drag: eq. (Poiseuille_v_BVP) solved with SciPy."""
+    H, eps, nu, kappa = 32, 0.4, 0.1, 40.0        # Brinkman layer of ~10 cells
+    cf = 1.5
+    b = 4e-6
+    o = oc.channel(2, H, np.full(H, eps), np.full(H, kappa), np.full(H, cf), nu=nu, b=b)
+    oc.run_to_steady(o, tol=1e-10, chunk=400)
+    _, v = oc.profile(o)
+    y = np.arange(1, H + 1) - 0.5
+    muD, muF = eps * nu / kappa, eps * cf
+    ref = _solve_channel_bvp(H, lambda y: eps + 0 * y, lambda y: muD + 0 * y,
+                             lambda y: muF + 0 * y, b, nu)(y)
+    lin = _brinkman(y, H, eps, b, muD, nu)
+    assert np.abs(v - ref).max() / ref.max() < 2e-3
+    assert np.abs(lin - ref).max() / ref.max() > 0.05        # the Forchheimer term matters here
+
+
+def _eps_cont(yy, H, eps_bot=1.0, eps_top=0.5, phi_bot=0.1, phi_top=0.1):
+    psi = ((np.asarray(yy) / H) - phi_bot) / (1.0 - phi_top - phi_bot)
+    return eps_bot + (eps_top - eps_bot) * workloads.smoothstep_cinf(psi)
+
+
+@pytest.mark.parametrize("visc_corr", [1, 0])
+def test_heterogeneous_channel_matches_bvp(visc_corr):
+    """Sec. 5.2.2, Setup I with fixed Darcy number: with the full correction Delta_nu the
+    steady profile solves the target problem (Poiseuille_v_BVP); with its viscous part omitted it
+    solves the intrinsic-stress problem (Poiseuille_u_BVP_wrong_visc_stress) instead.  The
+    pressure correction RT grad eps keeps the density nearly uniform across the porosity
+    gradient (Sec. 3.3: it turns -grad(eps p) into -eps grad p)."""
+    H, nu = 48, 0.1
+    y, eps_rows = workloads.heterogeneous_channel_setup1(H)
+    kappa = 1e-2 * H * H                                            # Da = 1e-2
+    b = 8 * nu * 0.01 / H ** 2                                      # V0 = 0.01
+    o = oc.channel(2, H, eps_rows, np.full(H, kappa), nu=nu, b=b, visc_corr=visc_corr)
+    oc.run_to_steady(o, tol=1e-10, chunk=500)
+    rho, v = oc.profile(o)
+    eps_f = lambda yy: _eps_cont(yy, H)
+    h = 1e-6
+    deps_f = lambda yy: (_eps_cont(yy + h, H) - _eps_cont(yy - h, H)) / (2 * h)
+    muD_f = lambda yy: eps_f(yy) * nu / kappa
+    zero = lambda yy: 0.0 * yy
+    target = _solve_channel_bvp(H, eps_f, muD_f, zero, b, nu)(y)
+    wrong = _solve_channel_bvp(H, eps_f, muD_f, zero, b, nu, intrinsic=True, deps_f=deps_f)(y)
+    gap = np.abs(target - wrong).max() / target.max()
+    assert gap > 0.03                                  # the two models are distinguishable
+    ref = target if visc_corr else wrong
+    err = np.abs(v - ref).max() / ref.max()
+    assert err < gap / 10 and err < 3e-3, (err, gap)
+    # without the pressure correction RT grad eps the steady state would have eps rho uniform,
+    # i.e. a 2:1 density contrast; what remains is the O(dt^2) forcing effect (RT eps')^2
+    assert np.ptp(rho) / rho.mean() < 5e-3     # measured 2.3e-3, falling as 1/H^2
+
+
+# --------------------------------------------------------------------------------------------
+# Dispersion and dissipation (Sec. 4): Phi^ext, Phi^eta, nu_eff and the drag linearisation
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("case", [
+    dict(setup="I", Ma0=0.3),
+    dict(setup="II", Ma0=0.3),
+    dict(setup="III", Ma0=0.4),
+    dict(setup="IV", JT=0.6),
+    dict(setup="IV", JT=1.5),
+    dict(setup="IV", Jeta=2.0),
+    dict(setup="IV", Jnu=1.5, Jeta=0.5),
+])
+def test_decay_rates_match_linear_theory(case):
+    """Sec. 4.2, setups (I)-(IV): shear and acoustic decay rates of small plane waves on an
+    advected base flow agree with the normal-mode rates (r_sh, r_ac) when Phi^ext is on, at any
+    temperature, and the bulk viscosity follows eta_eff through Phi^eta."""
+    L = 48
+    o, rate = oc.wave_setup(L=L, **case)
+    r = oc.measure_decay(o, case["setup"], 2000, L)
+    assert abs(r / rate - 1) < 0.01, r / rate
+
+
+@pytest.mark.parametrize("case", [
+    dict(setup="II", Ma0=0.3),
+    dict(setup="IV", JT=0.6),
+])
+def test_decay_rates_detect_missing_ext_correction(case):
+    """Without Phi^ext (eq. ex_corr) the diagonal anomaly of the product-form third moment
+    (prod_deviation) shows in the acoustic rate: the pins above would catch its omission."""
+    L = 48
+    o, rate = oc.wave_setup(L=L, ext=0, **case)
+    r = oc.measure_decay(o, case["setup"], 2000, L)
+    assert abs(r / rate - 1) > 0.05, r / rate
