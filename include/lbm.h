@@ -1,0 +1,196 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) porous-media lattice Boltzmann library.
+ *
+ * The library advances the one-domain lattice Boltzmann scheme of Gusev & Karlin,
+ * "Monolithic kinetic algorithm for heterogeneous porous media systems using a continuous
+ * one-domain approach" (arXiv 2606.29619), on the D2Q9 and D3Q27 lattices (Sec. 3.1):
+ * the product-form porosity-scaled equilibrium (Sec. 3.2), the Relax-to-Force shifted
+ * equilibrium with the extended-equilibrium and bulk-viscosity corrections (Sec. 3.2), the
+ * collide-and-stream update with per-cell relaxation beta (Sec. 3.3, eq. dicrete_scheme), the
+ * closed-form Darcy-Forchheimer velocity solve and the variable-porosity viscous correction
+ * (Sec. 3.3, eqs. v_(0), v_(1), v_final, accel, porosity_correction), in one code path for
+ * free-fluid and porous cells.
+ *
+ * Geometry.  Cells are indexed n = x + nx*(y + ny*z) (x fastest).  Every axis wraps
+ * periodically; walls are layers of solid cells (mask = 1), which reflect populations by
+ * halfway (link-wise) bounce-back.  The porosity is read on every cell, solid cells included;
+ * its derivatives are central differences.  Derivatives of moment fields become one-sided next
+ * to solid cells (Sec. 3.5, last paragraph).
+ *
+ * Conventions common to every entry point:
+ *   - every function returns LBM_OK (0) or a negative LBM_ERR_* code and never throws;
+ *   - lbm_last_error() returns a description of the calling thread's last failure;
+ *   - device pointers are HIP device addresses on the device that was current at lbm_create;
+ *   - all device work is enqueued on the stream given to lbm_create, in order, and is
+ *     asynchronous unless a function says it synchronises;
+ *   - a solver handle must not be used from two threads at once.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_API __attribute__((visibility("default")))
+
+/* Return codes. */
+#define LBM_OK 0
+#define LBM_ERR_INVALID_ARG -1   /* a parameter, field value or pointer is out of its domain */
+#define LBM_ERR_UNSUPPORTED -2   /* a valid combination this build does not implement */
+#define LBM_ERR_WORKSPACE -3     /* the device workspace is too small or misaligned */
+#define LBM_ERR_HIP -4           /* a HIP runtime call or kernel launch failed */
+#define LBM_ERR_NONFINITE -5     /* the state holds NaN or Inf (reported by lbm_residual) */
+#define LBM_ERR_STATE -6         /* a call out of order (e.g. on a destroyed handle) */
+
+/* Lattices (Sec. 3.1): the value is Q. */
+#define LBM_D2Q9 9
+#define LBM_D3Q27 27
+
+/* Storage and arithmetic type of the populations, moments and static fields. */
+#define LBM_F64 0
+#define LBM_F32 1
+
+/* Output element type for lbm_moments / lbm_get_populations / lbm_set_populations. */
+#define LBM_DTYPE_F64 0
+#define LBM_DTYPE_F32 1
+
+/* Velocity returned by lbm_moments. */
+#define LBM_VELOCITY_SUPERFICIAL 0   /* v (Sec. 2: the superficial or Darcy velocity) */
+#define LBM_VELOCITY_INTRINSIC 1     /* u = v / eps */
+
+/*
+ * Run description.  Host arrays are read during lbm_create only (the library copies them);
+ * the caller keeps ownership.  Arrays hold N = nx*ny*nz values in cell order; vector arrays
+ * are [D][N] (component-major).
+ */
+typedef struct lbm_params {
+    int lattice;          /* LBM_D2Q9 or LBM_D3Q27 */
+    int storage;          /* LBM_F64 or LBM_F32 */
+    int nx, ny, nz;       /* >= 1; nz must be 1 for D2Q9 */
+    double RT;            /* lattice temperature RT > 0 (1/3 is the lattice reference) */
+    double nu_f;          /* fluid viscosity in the Darcy coefficient mu_D = eps nu_f / kappa
+                             (eq. mu_D_Ergun_perm) */
+    double nu_eff_ref;    /* effective shear viscosity nu_eff(eps) = nu_eff_ref * eps^nu_eff_pow > 0;
+                             beta follows from eq. (nu_eff_def) with dt = 1 */
+    int nu_eff_pow;       /* -1, 0 or 1 */
+    double eta_eff;       /* effective bulk viscosity entering Phi^eta (eq. eta_corr);
+                             NaN leaves Phi^eta out, which fixes eta = 2 nu_eff / D
+                             (eq. eta_0_no_corr) */
+    double b[3];          /* body acceleration (b[2] ignored for D2Q9) */
+    double rho0;          /* initial intrinsic density where rho_init is NULL, > 0 */
+    const double *eps;    /* [N] porosity in (0, 1] on every cell (solid cells included) */
+    const double *kappa;  /* [N] permeability > 0 on fluid cells; +inf means free fluid */
+    const double *forch;  /* [N] Forchheimer coefficient C_F >= 0 on fluid cells, so that
+                             mu_F = eps C_F (eq. mu_F_Ergun_perm with C_F = F_eps/sqrt(kappa)) */
+    const uint8_t *mask;  /* [N] 1 = solid cell, 0 = fluid; NULL = no solid cells */
+    const double *rho_init; /* [N] initial intrinsic density > 0, or NULL (uniform rho0) */
+    const double *v_init;   /* [D][N] initial superficial velocity, or NULL (zero) */
+} lbm_params;
+
+/* Global statistics of the current state, accumulated in FP64 on the device. */
+typedef struct lbm_stats {
+    double mass;          /* sum over fluid cells of sum_i f-bar_i (= sum eps rho) */
+    double momentum[3];   /* sum over fluid cells of rho v */
+    double vmax;          /* max |v| over fluid cells */
+    double dv2;           /* sum |v - v_prev|^2, v_prev = v at the previous lbm_residual call */
+    double v2;            /* sum |v_prev|^2 */
+    double residual;      /* sqrt(dv2 / v2): the relative L2 change of v (Sec. 4.2's steady-state
+                             measure, taken between consecutive lbm_residual calls); +inf when
+                             v2 = 0 */
+    int64_t nonfinite;    /* number of fluid cells whose populations or velocity are not finite */
+    int64_t step;         /* time steps taken since creation */
+} lbm_stats;
+
+typedef struct lbm_solver lbm_solver;
+
+/*
+ * Bytes of device workspace lbm_create needs for these parameters (pure host computation, no
+ * device work).  Only lattice, storage, nx, ny, nz and whether mask is non-NULL are read.
+ * Errors: LBM_ERR_INVALID_ARG for NULL pointers or bad lattice, storage or dimensions.
+ */
+LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes);
+
+/*
+ * Validate the run, carve the caller-owned device workspace (>= lbm_footprint bytes,
+ * 256-byte aligned) into populations, static fields and moment buffers, upload and precompute
+ * the per-cell coefficients (mu_D, mu_F, nu_eff, beta from eqs. mu_D_Ergun_perm,
+ * mu_F_Ergun_perm, nu_eff_def) and write the initial populations of eq. (eq_bc_f_bar) with
+ * a_0, Phi^ext_0, Phi^eta_0 from the initial fields (the flowchart's initialisation).
+ * hip_stream is a hipStream_t (NULL = the null stream); the workspace and the stream are
+ * borrowed for the handle's lifetime.  Synchronises the stream before returning.
+ * Errors: LBM_ERR_INVALID_ARG (field values out of range, dimensions, pointers),
+ * LBM_ERR_UNSUPPORTED, LBM_ERR_WORKSPACE, LBM_ERR_HIP.  On error *out is NULL.
+ */
+LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspace_bytes,
+                       void *hip_stream, lbm_solver **out);
+
+/*
+ * Enqueue n >= 0 time steps (Sec. 3.5, collide-and-stream loop).  Each step runs the moment
+ * pass (eqs. transformed_density_moment, transformed_momentum_moment, v_(0), v_(1)), the velocity
+ * correction (eq. v_final) and the fused forcing-collide-stream pass (eqs. accel, ex_corr,
+ * eta_corr, prod_form, dicrete_scheme) with halfway bounce-back and periodic wrap.
+ * Asynchronous; kernel faults surface at the next synchronising call.
+ */
+LBM_API int lbm_step(lbm_solver *h, int64_t n);
+
+/*
+ * As lbm_step, and also measures each kernel class with HIP events on the handle's stream;
+ * synchronises.  kernel_ms[0..2] receive the summed durations (ms) of the moment, velocity
+ * correction and collide-stream kernels over the n steps.
+ */
+LBM_API int lbm_step_timed(lbm_solver *h, int64_t n, double kernel_ms[3]);
+
+/*
+ * Write the macroscopic fields of the current state: intrinsic density rho [N] and the
+ * corrected velocity [D][N] (eqs. v_(0), v_(1), v_final), superficial v or intrinsic u = v/eps
+ * per velocity_kind, as LBM_DTYPE_F64 or LBM_DTYPE_F32 into caller device buffers (either
+ * pointer may be NULL).  Solid cells get 0.  Asynchronous.
+ */
+LBM_API int lbm_moments(lbm_solver *h, void *rho_dev, void *v_dev, int dtype, int velocity_kind);
+
+/*
+ * Compute the global statistics of the current state (lbm_stats) with deterministic FP64
+ * reductions on the device, copy them to *out and remember the current v for the next call.
+ * Synchronises.  Returns LBM_ERR_NONFINITE (with *out filled) if any fluid cell is not finite.
+ */
+LBM_API int lbm_residual(lbm_solver *h, lbm_stats *out);
+
+/*
+ * Copy the populations f-bar_i(x) of the current state in natural layout [Q][N] (the value
+ * that streamed into cell x along c_i) into a caller device buffer of dtype.  Solid cells get
+ * 0.  With lbm_set_populations this is the checkpoint of the state.  Asynchronous.
+ */
+LBM_API int lbm_get_populations(lbm_solver *h, void *dev_out, int dtype);
+
+/*
+ * Replace the state by populations in natural layout [Q][N] from a caller device buffer of
+ * dtype and set the step counter to step.  Asynchronous.
+ */
+LBM_API int lbm_set_populations(lbm_solver *h, const void *dev_in, int dtype, int64_t step);
+
+/* Time steps taken so far. */
+LBM_API int lbm_get_step(const lbm_solver *h, int64_t *step);
+
+/*
+ * The library's lattice numbering: c_out receives Q*3 integers (c_ix, c_iy, c_iz), opp_out Q
+ * opposite indices.  D2Q9 follows the paper's wall example (Sec. 3.4.1): 0 rest, 1 +x, 2 +y,
+ * 3 -x, 4 -y, 5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-).  D3Q27: rest, the six faces, twelve edges,
+ * eight corners, opposite pairs adjacent.  Returns Q, or LBM_ERR_INVALID_ARG.
+ */
+LBM_API int lbm_lattice_info(int lattice, int *c_out, int *opp_out);
+
+/* Release the host-side handle (NULL is a no-op).  The workspace remains the caller's. */
+LBM_API int lbm_destroy(lbm_solver *h);
+
+/* Description of the calling thread's last error ("" if none); valid until the next call. */
+LBM_API const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -68,6 +68,7 @@ typedef struct {
     double *vw;             /* scratch velocity field [D][N] */
     int have_prev;
     double *vsnap;          /* residual snapshot [D][N] */
+    long *nbr;              /* [3][2][N] index of the periodic neighbour n -/+ e_a */
     long t;
 } orc_solver;
 
@@ -170,24 +171,34 @@ void orc_drag_solve(int D, const double *v0, double muD, double muF, double *v1)
 /* ------------------------------------------------------------------------------------------ */
 /* Grid helpers                                                                               */
 /* ------------------------------------------------------------------------------------------ */
+/* Periodic neighbour n + k e_a (|k| <= 2) through the neighbour table built at creation. */
 static long shift(const orc_solver *S, long n, int a, int k)
 {
-    long nx = S->p.nx, ny = S->p.ny, nz = S->p.nz;
-    long x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
-    if (a == 0) x = ((x + k) % nx + nx) % nx;
-    else if (a == 1) y = ((y + k) % ny + ny) % ny;
-    else z = ((z + k) % nz + nz) % nz;
-    return x + nx * (y + ny * z);
+    long N = S->N;
+    while (k > 0) { n = S->nbr[(a * 2 + 1) * N + n]; --k; }
+    while (k < 0) { n = S->nbr[(a * 2 + 0) * N + n]; ++k; }
+    return n;
 }
 
 static long shift3(const orc_solver *S, long n, const int *c)
 {
-    long nx = S->p.nx, ny = S->p.ny, nz = S->p.nz;
-    long x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
-    x = ((x + c[0]) % nx + nx) % nx;
-    y = ((y + c[1]) % ny + ny) % ny;
-    z = ((z + c[2]) % nz + nz) % nz;
-    return x + nx * (y + ny * z);
+    int a;
+    for (a = 0; a < 3; ++a) n = shift(S, n, a, c[a]);
+    return n;
+}
+
+static void build_neighbours(orc_solver *S)
+{
+    long nx = S->p.nx, ny = S->p.ny, nz = S->p.nz, N = S->N, n;
+    for (n = 0; n < N; ++n) {
+        long x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
+        S->nbr[0 * N + n] = ((x + nx - 1) % nx) + nx * (y + ny * z);
+        S->nbr[1 * N + n] = ((x + 1) % nx) + nx * (y + ny * z);
+        S->nbr[2 * N + n] = x + nx * (((y + ny - 1) % ny) + ny * z);
+        S->nbr[3 * N + n] = x + nx * (((y + 1) % ny) + ny * z);
+        S->nbr[4 * N + n] = x + nx * (y + ny * ((z + nz - 1) % nz));
+        S->nbr[5 * N + n] = x + nx * (y + ny * ((z + 1) % nz));
+    }
 }
 
 /* Derivative of a moment field g along axis a at fluid cell n (Sec. 3.5, last paragraph):
@@ -306,6 +317,7 @@ void orc_destroy(orc_solver *S)
     free(S->v1); free(S->v); free(S->m); free(S->g); free(S->prho); free(S->pv1); free(S->pv);
     free(S->vw);
     free(S->vsnap);
+    free(S->nbr);
     free(S);
 }
 
@@ -360,9 +372,10 @@ orc_solver *orc_create(const orc_params *p, char *err, int errlen)
     S->pv = (double *)xcalloc(D * N, sizeof(double));
     S->vw = (double *)xcalloc(D * N, sizeof(double));
     S->vsnap = (double *)xcalloc(D * N, sizeof(double));
+    S->nbr = (long *)xcalloc(6 * N, sizeof(long));
     if (!S->F || !S->G || !S->eps || !S->muD || !S->muF || !S->nu || !S->dnu || !S->beta ||
         !S->ge || !S->H || !S->solid || !S->rho || !S->v1 || !S->v || !S->m || !S->g ||
-        !S->prho || !S->pv1 || !S->pv || !S->vw || !S->vsnap) {
+        !S->prho || !S->pv1 || !S->pv || !S->vw || !S->vsnap || !S->nbr) {
         snprintf(err, (size_t)errlen, "out of host memory");
         orc_destroy(S);
         return NULL;
@@ -392,6 +405,7 @@ orc_solver *orc_create(const orc_params *p, char *err, int errlen)
         /* (nu_eff_def) solved for beta with dt = 1: beta = 1 / (1 + 2 nu_eff / RT). */
         S->beta[n] = 1.0 / (1.0 + (2.0 * nu) / p->RT);
     }
+    build_neighbours(S);
     porosity_derivatives(S);
     init_populations(S);
     return S;

@@ -1,0 +1,295 @@
+"""ctypes binding of the C ABI in ``include/lbm.h`` -- argument marshalling only.
+
+Every function here carries the name of the C entry point it wraps and does nothing but
+convert arguments; all numerical work runs in ``liblbm.so`` (HIP kernels for gfx950).  PyTorch
+provides the device workspace and the stream.  Loading fails loudly when the library is
+missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+
+LBM_OK = 0
+LBM_ERR_INVALID_ARG = -1
+LBM_ERR_UNSUPPORTED = -2
+LBM_ERR_WORKSPACE = -3
+LBM_ERR_HIP = -4
+LBM_ERR_NONFINITE = -5
+LBM_ERR_STATE = -6
+LBM_D2Q9 = 9
+LBM_D3Q27 = 27
+LBM_F64 = 0
+LBM_F32 = 1
+LBM_DTYPE_F64 = 0
+LBM_DTYPE_F32 = 1
+LBM_VELOCITY_SUPERFICIAL = 0
+LBM_VELOCITY_INTRINSIC = 1
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int), ("storage", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("RT", ctypes.c_double), ("nu_f", ctypes.c_double), ("nu_eff_ref", ctypes.c_double),
+        ("nu_eff_pow", ctypes.c_int), ("eta_eff", ctypes.c_double),
+        ("b", ctypes.c_double * 3), ("rho0", ctypes.c_double),
+        ("eps", _dp), ("kappa", _dp), ("forch", _dp),
+        ("mask", ctypes.POINTER(ctypes.c_uint8)),
+        ("rho_init", _dp), ("v_init", _dp),
+    ]
+
+
+class lbm_stats(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3), ("vmax", ctypes.c_double),
+        ("dv2", ctypes.c_double), ("v2", ctypes.c_double), ("residual", ctypes.c_double),
+        ("nonfinite", ctypes.c_int64), ("step", ctypes.c_int64),
+    ]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, func: str, msg: str):
+        super().__init__(f"{func} failed ({code}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load liblbm.so (built by ``__graft_entry__.build()``); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    L.lbm_footprint.argtypes = [ctypes.POINTER(lbm_params), ctypes.POINTER(ctypes.c_size_t)]
+    L.lbm_create.argtypes = [ctypes.POINTER(lbm_params), vp, ctypes.c_size_t, vp,
+                             ctypes.POINTER(vp)]
+    L.lbm_step.argtypes = [vp, ctypes.c_int64]
+    L.lbm_step_timed.argtypes = [vp, ctypes.c_int64, _dp]
+    L.lbm_moments.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
+    L.lbm_residual.argtypes = [vp, ctypes.POINTER(lbm_stats)]
+    L.lbm_get_populations.argtypes = [vp, vp, ctypes.c_int]
+    L.lbm_set_populations.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int64]
+    L.lbm_get_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.lbm_lattice_info.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_int)]
+    L.lbm_destroy.argtypes = [vp]
+    L.lbm_last_error.restype = ctypes.c_char_p
+    L.lbm_last_error.argtypes = []
+    for name in ("lbm_footprint", "lbm_create", "lbm_step", "lbm_step_timed", "lbm_moments",
+                 "lbm_residual", "lbm_get_populations", "lbm_set_populations", "lbm_get_step",
+                 "lbm_lattice_info", "lbm_destroy"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, func: str, ok=(LBM_OK,)) -> int:
+    if rc not in ok and not (func == "lbm_lattice_info" and rc > 0):
+        raise LbmError(rc, func, lbm_last_error())
+    return rc
+
+
+def lbm_last_error() -> str:
+    return load().lbm_last_error().decode()
+
+
+def lbm_lattice_info(lattice: int):
+    c = (ctypes.c_int * 81)()
+    opp = (ctypes.c_int * 27)()
+    Q = _check(load().lbm_lattice_info(lattice, c, opp), "lbm_lattice_info")
+    return (np.array(c[:3 * Q], dtype=np.int64).reshape(Q, 3),
+            np.array(opp[:Q], dtype=np.int64))
+
+
+def lbm_footprint(p: lbm_params) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().lbm_footprint(ctypes.byref(p), ctypes.byref(out)), "lbm_footprint")
+    return out.value
+
+
+def lbm_create(p: lbm_params, workspace_ptr: int, workspace_bytes: int, stream_ptr: int):
+    h = ctypes.c_void_p()
+    _check(load().lbm_create(ctypes.byref(p), ctypes.c_void_p(workspace_ptr), workspace_bytes,
+                             ctypes.c_void_p(stream_ptr), ctypes.byref(h)), "lbm_create")
+    return h
+
+
+def lbm_step(h, n: int):
+    _check(load().lbm_step(h, int(n)), "lbm_step")
+
+
+def lbm_step_timed(h, n: int):
+    ms = (ctypes.c_double * 3)()
+    _check(load().lbm_step_timed(h, int(n), ms), "lbm_step_timed")
+    return [ms[0], ms[1], ms[2]]
+
+
+def lbm_moments(h, rho_ptr: int, v_ptr: int, dtype: int, velocity_kind: int):
+    _check(load().lbm_moments(h, ctypes.c_void_p(rho_ptr), ctypes.c_void_p(v_ptr), dtype,
+                              velocity_kind), "lbm_moments")
+
+
+def lbm_residual(h, allow_nonfinite: bool = False) -> lbm_stats:
+    s = lbm_stats()
+    ok = (LBM_OK, LBM_ERR_NONFINITE) if allow_nonfinite else (LBM_OK,)
+    _check(load().lbm_residual(h, ctypes.byref(s)), "lbm_residual", ok)
+    return s
+
+
+def lbm_get_populations(h, dev_ptr: int, dtype: int):
+    _check(load().lbm_get_populations(h, ctypes.c_void_p(dev_ptr), dtype), "lbm_get_populations")
+
+
+def lbm_set_populations(h, dev_ptr: int, dtype: int, step: int):
+    _check(load().lbm_set_populations(h, ctypes.c_void_p(dev_ptr), dtype, int(step)),
+           "lbm_set_populations")
+
+
+def lbm_get_step(h) -> int:
+    s = ctypes.c_int64(0)
+    _check(load().lbm_get_step(h, ctypes.byref(s)), "lbm_get_step")
+    return s.value
+
+
+def lbm_destroy(h):
+    _check(load().lbm_destroy(h), "lbm_destroy")
+
+
+# --------------------------------------------------------------------------------------------
+# Convenience wrapper: numpy fields in, torch device memory and stream underneath.
+# --------------------------------------------------------------------------------------------
+def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
+                forch: np.ndarray, mask: Optional[np.ndarray] = None, RT: float = 1.0 / 3.0,
+                nu_f: float = 1.0 / 6.0, nu_eff_ref: float = 1.0 / 6.0, nu_eff_pow: int = 0,
+                eta_eff: float = math.nan, b=(0.0, 0.0, 0.0), rho0: float = 1.0,
+                rho_init: Optional[np.ndarray] = None, v_init: Optional[np.ndarray] = None):
+    """Build an lbm_params from numpy arrays shaped [nz, ny, nx]; returns (params, keepalive)."""
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    if eps.ndim == 2:
+        eps = eps[None]
+    nz, ny, nx = eps.shape
+    keep = [eps]
+
+    def arr(a, shape):
+        if a is None:
+            return _dp()
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape))
+        keep.append(a)
+        return a.ctypes.data_as(_dp)
+
+    p = lbm_params()
+    p.lattice, p.storage = lattice, storage
+    p.nx, p.ny, p.nz = nx, ny, nz
+    p.RT, p.nu_f, p.nu_eff_ref, p.nu_eff_pow, p.eta_eff = RT, nu_f, nu_eff_ref, nu_eff_pow, eta_eff
+    for a in range(3):
+        p.b[a] = float(b[a]) if a < len(b) else 0.0
+    p.rho0 = rho0
+    p.eps = eps.ctypes.data_as(_dp)
+    p.kappa = arr(kappa, eps.shape)
+    p.forch = arr(forch, eps.shape)
+    if mask is not None:
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(eps.shape))
+        keep.append(m)
+        p.mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    D = 2 if lattice == LBM_D2Q9 else 3
+    p.rho_init = arr(rho_init, eps.shape)
+    p.v_init = arr(v_init, (D,) + eps.shape)
+    return p, keep
+
+
+class Solver:
+    """A solver on one GPU: owns its torch workspace, uses torch's current stream."""
+
+    def __init__(self, params: lbm_params, keepalive=None, device="cuda"):
+        import torch
+        self._torch = torch
+        self.params = params
+        self.D = 2 if params.lattice == LBM_D2Q9 else 3
+        self.Q = params.lattice
+        self.shape = (params.nz, params.ny, params.nx)
+        self.N = params.nx * params.ny * params.nz
+        self.dtype = torch.float64 if params.storage == LBM_F64 else torch.float32
+        self.nbytes = lbm_footprint(params)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self._h = lbm_create(params, self.workspace.data_ptr(), self.nbytes,
+                             self.stream.cuda_stream)
+        del keepalive
+
+    @classmethod
+    def from_workload(cls, w, storage: int = LBM_F32, **kw):
+        p, keep = make_params(w.lattice, storage, w.eps, w.kappa, w.forch, w.mask, RT=w.RT,
+                              nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow,
+                              eta_eff=w.eta_eff, b=w.b, rho0=w.rho0, rho_init=w.rho_init,
+                              v_init=w.v_init)
+        return cls(p, keep, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def step_count(self) -> int:
+        return lbm_get_step(self._h)
+
+    def step(self, n: int = 1):
+        lbm_step(self._h, n)
+
+    def step_timed(self, n: int = 1):
+        return lbm_step_timed(self._h, n)
+
+    def moments(self, dtype=None, intrinsic: bool = False):
+        torch = self._torch
+        dtype = dtype or torch.float64
+        rho = torch.empty(self.shape, dtype=dtype, device=self.device)
+        v = torch.empty((self.D,) + self.shape, dtype=dtype, device=self.device)
+        code = LBM_DTYPE_F64 if dtype == torch.float64 else LBM_DTYPE_F32
+        lbm_moments(self._h, rho.data_ptr(), v.data_ptr(), code,
+                    LBM_VELOCITY_INTRINSIC if intrinsic else LBM_VELOCITY_SUPERFICIAL)
+        return rho, v
+
+    def populations(self, dtype=None):
+        torch = self._torch
+        dtype = dtype or self.dtype
+        out = torch.empty((self.Q,) + self.shape, dtype=dtype, device=self.device)
+        lbm_get_populations(self._h, out.data_ptr(),
+                            LBM_DTYPE_F64 if dtype == torch.float64 else LBM_DTYPE_F32)
+        return out
+
+    def set_populations(self, f, step: int = 0):
+        torch = self._torch
+        f = f.contiguous()
+        lbm_set_populations(self._h, f.data_ptr(),
+                            LBM_DTYPE_F64 if f.dtype == torch.float64 else LBM_DTYPE_F32, step)
+        self._keep_state = f
+
+    def residual(self, allow_nonfinite: bool = False) -> lbm_stats:
+        return lbm_residual(self._h, allow_nonfinite)

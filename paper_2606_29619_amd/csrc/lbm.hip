@@ -1,0 +1,578 @@
+// lbm.hip -- C ABI (include/lbm.h) of the gfx950 porous-media lattice Boltzmann library.
+//
+// Host side: argument validation, workspace layout, uploads and kernel dispatch.  All device
+// memory comes from the caller's workspace; all work goes to the caller's stream.
+#include "lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lbm_device.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(LBM_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+#define LAUNCH_CHECK()                                                                  \
+    do {                                                                                \
+        hipError_t e_ = hipGetLastError();                                              \
+        if (e_ != hipSuccess)                                                           \
+            return fail(LBM_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t f, eps, muD, muF, mask, rho, v1, v, vsnap, part, res, total;
+};
+
+Layout make_layout(int Q, int D, size_t N, size_t s, bool solids) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.f = take((size_t)Q * N * s);
+    L.eps = take(N * s);
+    L.muD = take(N * s);
+    L.muF = take(N * s);
+    L.mask = solids ? take(N) : 0;
+    L.rho = take(N * s);
+    L.v1 = take((size_t)D * N * s);
+    L.v = take((size_t)D * N * s);
+    L.vsnap = take((size_t)D * N * s);
+    L.part = take((size_t)lbm::kStatsBlocks * lbm::kStatsSlots * sizeof(double));
+    L.res = take(lbm::kStatsSlots * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+}  // namespace
+
+struct lbm_solver {
+    int lattice, D, Q, storage;
+    int nx, ny, nz;
+    int64_t N;
+    bool solids;
+    hipStream_t stream;
+    char *ws;
+    Layout L;
+    int64_t step;
+    int phase;  // AA-pattern layout: 0 natural, 1 swapped
+    double RT, nu_f, nu_eff_ref, eta_eff, b[3];
+    int nu_eff_pow;
+};
+
+namespace {
+
+template <typename T>
+lbm::Phys<T> phys_of(const lbm_solver *h) {
+    lbm::Phys<T> ph;
+    ph.RT = (T)h->RT;
+    ph.omr = (T)(1.0 - 3.0 * h->RT);
+    ph.nu_ref = (T)h->nu_eff_ref;
+    ph.eta_on = std::isnan(h->eta_eff) ? 0 : 1;
+    ph.eta = ph.eta_on ? (T)h->eta_eff : T(0);
+    ph.two_over_D = (T)(2.0 / (double)h->D);
+    for (int a = 0; a < 3; ++a) ph.b[a] = (T)h->b[a];
+    ph.nu_pow = h->nu_eff_pow;
+    return ph;
+}
+
+lbm::Grid grid_of(const lbm_solver *h) { return lbm::Grid{h->nx, h->ny, h->nz, h->N}; }
+
+dim3 cell_grid(const lbm_solver *h) {
+    return dim3((unsigned)((h->nx + 63) / 64), (unsigned)((h->ny + 3) / 4), (unsigned)h->nz);
+}
+
+dim3 flat_grid(int64_t total) { return dim3((unsigned)((total + 255) / 256)); }
+
+template <typename T>
+T *ws_ptr(const lbm_solver *h, size_t off) {
+    return reinterpret_cast<T *>(h->ws + off);
+}
+
+const uint8_t *mask_ptr(const lbm_solver *h) {
+    return h->solids ? reinterpret_cast<const uint8_t *>(h->ws + h->L.mask) : nullptr;
+}
+
+// ---- kernel launchers, dispatched on (lattice, type, solids, phase) -----------------------
+template <int D, typename T, bool S, int PH>
+void launch_moments(const lbm_solver *h) {
+    auto ph = phys_of<T>(h);
+    hipLaunchKernelGGL((lbm::k_moments<D, T, S, PH>), cell_grid(h), dim3(64, 4, 1), 0, h->stream,
+                       ws_ptr<const T>(h, h->L.f), ws_ptr<const T>(h, h->L.eps),
+                       ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
+                       ws_ptr<T>(h, h->L.rho), ws_ptr<T>(h, h->L.v1), grid_of(h), ph);
+}
+
+template <int D, typename T, bool S>
+void launch_vcorrect(const lbm_solver *h) {
+    auto ph = phys_of<T>(h);
+    hipLaunchKernelGGL((lbm::k_vcorrect<D, T, S>), cell_grid(h), dim3(64, 4, 1), 0, h->stream,
+                       ws_ptr<const T>(h, h->L.rho), ws_ptr<const T>(h, h->L.v1),
+                       ws_ptr<const T>(h, h->L.eps), mask_ptr(h), ws_ptr<T>(h, h->L.v),
+                       grid_of(h), ph);
+}
+
+template <int D, typename T, bool S, int PH>
+void launch_collide(const lbm_solver *h) {
+    auto ph = phys_of<T>(h);
+    hipLaunchKernelGGL((lbm::k_collide<D, T, S, PH>), cell_grid(h), dim3(64, 4, 1), 0, h->stream,
+                       ws_ptr<T>(h, h->L.f), ws_ptr<const T>(h, h->L.rho),
+                       ws_ptr<const T>(h, h->L.v), ws_ptr<const T>(h, h->L.eps),
+                       ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
+                       grid_of(h), ph);
+}
+
+template <int D, typename T, bool S>
+void launch_init(const lbm_solver *h) {
+    auto ph = phys_of<T>(h);
+    hipLaunchKernelGGL((lbm::k_init<D, T, S>), cell_grid(h), dim3(64, 4, 1), 0, h->stream,
+                       ws_ptr<T>(h, h->L.f), ws_ptr<const T>(h, h->L.rho),
+                       ws_ptr<const T>(h, h->L.v), ws_ptr<const T>(h, h->L.eps),
+                       ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
+                       grid_of(h), ph);
+}
+
+template <int D, typename T, bool S, int PH, typename O>
+void launch_export(const lbm_solver *h, O *out) {
+    hipLaunchKernelGGL((lbm::k_export<D, T, S, PH, O>), cell_grid(h), dim3(64, 4, 1), 0, h->stream,
+                       ws_ptr<const T>(h, h->L.f), mask_ptr(h), out, grid_of(h));
+}
+
+template <int D, typename T, bool S, int PH>
+void launch_stats(const lbm_solver *h) {
+    hipLaunchKernelGGL((lbm::k_stats<D, T, S, PH>), dim3(lbm::kStatsBlocks), dim3(256), 0,
+                       h->stream, ws_ptr<const T>(h, h->L.f), ws_ptr<const T>(h, h->L.rho),
+                       ws_ptr<const T>(h, h->L.v), ws_ptr<T>(h, h->L.vsnap), mask_ptr(h),
+                       ws_ptr<double>(h, h->L.part), grid_of(h));
+}
+
+// Calls fn.template operator()<D, T, S, PH>() for the handle's configuration.
+template <typename F>
+void dispatch(const lbm_solver *h, F &&fn) {
+    const bool s = h->solids;
+    const int ph = h->phase;
+#define LBM_DISPATCH_T(DD, TT)                                       \
+    if (s) {                                                         \
+        if (ph) fn.template operator()<DD, TT, true, 1>();           \
+        else fn.template operator()<DD, TT, true, 0>();              \
+    } else {                                                         \
+        if (ph) fn.template operator()<DD, TT, false, 1>();          \
+        else fn.template operator()<DD, TT, false, 0>();             \
+    }
+    if (h->D == 2) {
+        if (h->storage == LBM_F64) { LBM_DISPATCH_T(2, double) }
+        else { LBM_DISPATCH_T(2, float) }
+    } else {
+        if (h->storage == LBM_F64) { LBM_DISPATCH_T(3, double) }
+        else { LBM_DISPATCH_T(3, float) }
+    }
+#undef LBM_DISPATCH_T
+}
+
+struct MomentsPass {
+    const lbm_solver *h;
+    template <int D, typename T, bool S, int PH>
+    void operator()() { launch_moments<D, T, S, PH>(h); }
+};
+struct VcorrectPass {
+    const lbm_solver *h;
+    template <int D, typename T, bool S, int PH>
+    void operator()() { launch_vcorrect<D, T, S>(h); }
+};
+struct CollidePass {
+    const lbm_solver *h;
+    template <int D, typename T, bool S, int PH>
+    void operator()() { launch_collide<D, T, S, PH>(h); }
+};
+struct InitPass {
+    const lbm_solver *h;
+    template <int D, typename T, bool S, int PH>
+    void operator()() { launch_init<D, T, S>(h); }
+};
+struct StatsPass {
+    const lbm_solver *h;
+    template <int D, typename T, bool S, int PH>
+    void operator()() { launch_stats<D, T, S, PH>(h); }
+};
+struct ExportPass {
+    const lbm_solver *h;
+    void *out;
+    int dtype;
+    template <int D, typename T, bool S, int PH>
+    void operator()() {
+        if (dtype == LBM_DTYPE_F64) launch_export<D, T, S, PH, double>(h, (double *)out);
+        else launch_export<D, T, S, PH, float>(h, (float *)out);
+    }
+};
+
+// Moments of the current state into the internal rho, v1, v buffers.
+int current_moments(lbm_solver *h) {
+    dispatch(h, MomentsPass{h});
+    LAUNCH_CHECK();
+    dispatch(h, VcorrectPass{h});
+    LAUNCH_CHECK();
+    return LBM_OK;
+}
+
+int check_handle(const lbm_solver *h) {
+    if (!h) return fail(LBM_ERR_INVALID_ARG, "null solver handle");
+    if (!h->ws) return fail(LBM_ERR_STATE, "solver handle is not initialised");
+    return LBM_OK;
+}
+
+int validate_shape(const lbm_params *p, int *D, int *Q, size_t *s, int64_t *N) {
+    if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
+    if (p->lattice == LBM_D2Q9) { *D = 2; *Q = 9; }
+    else if (p->lattice == LBM_D3Q27) { *D = 3; *Q = 27; }
+    else return fail(LBM_ERR_INVALID_ARG, "lattice must be LBM_D2Q9 or LBM_D3Q27, got %d", p->lattice);
+    if (p->storage == LBM_F64) *s = 8;
+    else if (p->storage == LBM_F32) *s = 4;
+    else return fail(LBM_ERR_UNSUPPORTED, "storage %d is not supported", p->storage);
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+        return fail(LBM_ERR_INVALID_ARG, "dimensions must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
+    if (*D == 2 && p->nz != 1) return fail(LBM_ERR_INVALID_ARG, "D2Q9 needs nz = 1 (got %d)", p->nz);
+    if (p->ny > 4 * 65535 || p->nz > 65535)
+        return fail(LBM_ERR_UNSUPPORTED, "ny must be <= 262140 and nz <= 65535");
+    *N = (int64_t)p->nx * p->ny * p->nz;
+    if (*N > ((int64_t)1 << 40)) return fail(LBM_ERR_INVALID_ARG, "too many cells");
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+LBM_API const char *lbm_last_error(void) { return g_err.c_str(); }
+
+LBM_API int lbm_lattice_info(int lattice, int *c_out, int *opp_out) {
+    if (!c_out || !opp_out) return fail(LBM_ERR_INVALID_ARG, "null output pointer");
+    if (lattice == LBM_D2Q9) {
+        for (int i = 0; i < 9; ++i) {
+            for (int a = 0; a < 3; ++a) c_out[3 * i + a] = lbm::Lat<2>::c[i][a];
+            opp_out[i] = lbm::Lat<2>::opp[i];
+        }
+        return 9;
+    }
+    if (lattice == LBM_D3Q27) {
+        for (int i = 0; i < 27; ++i) {
+            for (int a = 0; a < 3; ++a) c_out[3 * i + a] = lbm::Lat<3>::c[i][a];
+            opp_out[i] = lbm::Lat<3>::opp[i];
+        }
+        return 27;
+    }
+    return fail(LBM_ERR_INVALID_ARG, "unknown lattice %d", lattice);
+}
+
+LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes) {
+    int D, Q;
+    size_t s;
+    int64_t N;
+    if (!workspace_bytes) return fail(LBM_ERR_INVALID_ARG, "workspace_bytes is NULL");
+    int rc = validate_shape(p, &D, &Q, &s, &N);
+    if (rc) return rc;
+    *workspace_bytes = make_layout(Q, D, (size_t)N, s, p->mask != nullptr).total;
+    return LBM_OK;
+}
+
+LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspace_bytes,
+                       void *hip_stream, lbm_solver **out) {
+    if (!out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int D, Q;
+    size_t s;
+    int64_t N;
+    int rc = validate_shape(p, &D, &Q, &s, &N);
+    if (rc) return rc;
+    if (!(is_finite(p->RT) && p->RT > 0)) return fail(LBM_ERR_INVALID_ARG, "RT must be finite and > 0");
+    if (!(is_finite(p->nu_f) && p->nu_f >= 0)) return fail(LBM_ERR_INVALID_ARG, "nu_f must be finite and >= 0");
+    if (!(is_finite(p->nu_eff_ref) && p->nu_eff_ref > 0))
+        return fail(LBM_ERR_INVALID_ARG, "nu_eff_ref must be finite and > 0");
+    if (p->nu_eff_pow < -1 || p->nu_eff_pow > 1) return fail(LBM_ERR_INVALID_ARG, "nu_eff_pow must be -1, 0 or 1");
+    if (!std::isnan(p->eta_eff) && !(is_finite(p->eta_eff) && p->eta_eff >= 0))
+        return fail(LBM_ERR_INVALID_ARG, "eta_eff must be NaN or finite and >= 0");
+    for (int a = 0; a < 3; ++a)
+        if (!is_finite(p->b[a])) return fail(LBM_ERR_INVALID_ARG, "body force must be finite");
+    if (!(is_finite(p->rho0) && p->rho0 > 0)) return fail(LBM_ERR_INVALID_ARG, "rho0 must be finite and > 0");
+    if (!p->eps || !p->kappa || !p->forch) return fail(LBM_ERR_INVALID_ARG, "eps, kappa and forch are required");
+    bool any_fluid = false;
+    for (int64_t n = 0; n < N; ++n) {
+        const double e = p->eps[n];
+        if (!(e > 0.0 && e <= 1.0)) return fail(LBM_ERR_INVALID_ARG, "eps[%lld] = %g is outside (0, 1]", (long long)n, e);
+        const bool solid = p->mask && p->mask[n];
+        if (p->mask && p->mask[n] > 1) return fail(LBM_ERR_INVALID_ARG, "mask[%lld] must be 0 or 1", (long long)n);
+        if (solid) continue;
+        any_fluid = true;
+        const double k = p->kappa[n], c = p->forch[n];
+        if (!(k > 0.0)) return fail(LBM_ERR_INVALID_ARG, "kappa[%lld] = %g must be > 0 (or +inf)", (long long)n, k);
+        if (!(is_finite(c) && c >= 0.0)) return fail(LBM_ERR_INVALID_ARG, "forch[%lld] = %g must be finite and >= 0", (long long)n, c);
+        if (p->rho_init && !(is_finite(p->rho_init[n]) && p->rho_init[n] > 0))
+            return fail(LBM_ERR_INVALID_ARG, "rho_init[%lld] must be finite and > 0", (long long)n);
+        if (p->v_init)
+            for (int a = 0; a < D; ++a)
+                if (!is_finite(p->v_init[(int64_t)a * N + n]))
+                    return fail(LBM_ERR_INVALID_ARG, "v_init must be finite");
+    }
+    if (!any_fluid) return fail(LBM_ERR_INVALID_ARG, "no fluid cell");
+    const bool solids = p->mask != nullptr;
+    const Layout L = make_layout(Q, D, (size_t)N, s, solids);
+    if (!dev_workspace) return fail(LBM_ERR_INVALID_ARG, "dev_workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
+        return fail(LBM_ERR_WORKSPACE, "dev_workspace must be 256-byte aligned");
+    if (workspace_bytes < L.total)
+        return fail(LBM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes needed",
+                    workspace_bytes, L.total);
+
+    lbm_solver *h = new (std::nothrow) lbm_solver();
+    if (!h) return fail(LBM_ERR_INVALID_ARG, "out of host memory");
+    h->lattice = p->lattice;
+    h->D = D;
+    h->Q = Q;
+    h->storage = p->storage;
+    h->nx = p->nx; h->ny = p->ny; h->nz = p->nz;
+    h->N = N;
+    h->solids = solids;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    h->ws = reinterpret_cast<char *>(dev_workspace);
+    h->L = L;
+    h->step = 0;
+    h->phase = 0;
+    h->RT = p->RT;
+    h->nu_f = p->nu_f;
+    h->nu_eff_ref = p->nu_eff_ref;
+    h->nu_eff_pow = p->nu_eff_pow;
+    h->eta_eff = p->eta_eff;
+    for (int a = 0; a < 3; ++a) h->b[a] = a < D ? p->b[a] : 0.0;
+
+    auto cleanup = [&](int code) {
+        delete h;
+        return code;
+    };
+    // Stage the FP64 input fields in the population region (Q*N*s >= 3*N*8 for every lattice
+    // and storage), derive the static fields, then stage the initial moments the same way.
+    const size_t NB = (size_t)N * sizeof(double);
+    double *st = ws_ptr<double>(h, L.f);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(st, p->eps, NB, hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(st + N, p->kappa, NB, hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(st + 2 * N, p->forch, NB, hipMemcpyHostToDevice, h->stream)) != hipSuccess)
+        return cleanup(fail(LBM_ERR_HIP, "upload of input fields failed: %s", hipGetErrorString(e)));
+    if (solids && (e = hipMemcpyAsync(h->ws + L.mask, p->mask, (size_t)N, hipMemcpyHostToDevice, h->stream)) != hipSuccess)
+        return cleanup(fail(LBM_ERR_HIP, "upload of mask failed: %s", hipGetErrorString(e)));
+    if (h->storage == LBM_F64)
+        hipLaunchKernelGGL(lbm::k_static<double>, flat_grid(N), dim3(256), 0, h->stream, st, st + N, st + 2 * N,
+                           ws_ptr<double>(h, L.eps), ws_ptr<double>(h, L.muD), ws_ptr<double>(h, L.muF), N, p->nu_f);
+    else
+        hipLaunchKernelGGL(lbm::k_static<float>, flat_grid(N), dim3(256), 0, h->stream, st, st + N, st + 2 * N,
+                           ws_ptr<float>(h, L.eps), ws_ptr<float>(h, L.muD), ws_ptr<float>(h, L.muF), N, p->nu_f);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return cleanup(fail(LBM_ERR_HIP, "static-field kernel failed: %s", hipGetErrorString(e)));
+    const double *rho_st = nullptr, *v_st = nullptr;
+    if (p->rho_init) {
+        if ((e = hipMemcpyAsync(st, p->rho_init, NB, hipMemcpyHostToDevice, h->stream)) != hipSuccess)
+            return cleanup(fail(LBM_ERR_HIP, "upload of rho_init failed: %s", hipGetErrorString(e)));
+        rho_st = st;
+    }
+    if (p->v_init) {
+        if ((e = hipMemcpyAsync(st + N, p->v_init, (size_t)D * NB, hipMemcpyHostToDevice, h->stream)) != hipSuccess)
+            return cleanup(fail(LBM_ERR_HIP, "upload of v_init failed: %s", hipGetErrorString(e)));
+        v_st = st + N;
+    }
+    const uint8_t *mk = mask_ptr(h);
+    if (h->storage == LBM_F64) {
+        if (D == 2) hipLaunchKernelGGL((lbm::k_fill_init<2, double>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<double>(h, L.rho), ws_ptr<double>(h, L.v), N, p->rho0);
+        else hipLaunchKernelGGL((lbm::k_fill_init<3, double>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<double>(h, L.rho), ws_ptr<double>(h, L.v), N, p->rho0);
+    } else {
+        if (D == 2) hipLaunchKernelGGL((lbm::k_fill_init<2, float>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<float>(h, L.rho), ws_ptr<float>(h, L.v), N, p->rho0);
+        else hipLaunchKernelGGL((lbm::k_fill_init<3, float>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<float>(h, L.rho), ws_ptr<float>(h, L.v), N, p->rho0);
+    }
+    if ((e = hipGetLastError()) != hipSuccess)
+        return cleanup(fail(LBM_ERR_HIP, "initial-field kernel failed: %s", hipGetErrorString(e)));
+    dispatch(h, InitPass{h});
+    if ((e = hipGetLastError()) != hipSuccess)
+        return cleanup(fail(LBM_ERR_HIP, "initial-population kernel failed: %s", hipGetErrorString(e)));
+    // residual snapshot starts at zero
+    if ((e = hipMemsetAsync(h->ws + L.vsnap, 0, (size_t)D * N * s, h->stream)) != hipSuccess)
+        return cleanup(fail(LBM_ERR_HIP, "snapshot clear failed: %s", hipGetErrorString(e)));
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess)
+        return cleanup(fail(LBM_ERR_HIP, "initialisation failed: %s", hipGetErrorString(e)));
+    *out = h;
+    return LBM_OK;
+}
+
+LBM_API int lbm_step(lbm_solver *h, int64_t n) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (n < 0) return fail(LBM_ERR_INVALID_ARG, "negative step count");
+    for (int64_t k = 0; k < n; ++k) {
+        dispatch(h, MomentsPass{h});
+        dispatch(h, VcorrectPass{h});
+        dispatch(h, CollidePass{h});
+        LAUNCH_CHECK();
+        h->phase ^= 1;
+        h->step += 1;
+    }
+    return LBM_OK;
+}
+
+LBM_API int lbm_step_timed(lbm_solver *h, int64_t n, double kernel_ms[3]) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (n < 0 || !kernel_ms) return fail(LBM_ERR_INVALID_ARG, "bad step count or output");
+    hipEvent_t ev[4];
+    for (auto &x : ev) HIP_TRY(hipEventCreate(&x));
+    double acc[3] = {0, 0, 0};
+    int out = LBM_OK;
+    for (int64_t k = 0; k < n && out == LBM_OK; ++k) {
+        (void)hipEventRecord(ev[0], h->stream);
+        dispatch(h, MomentsPass{h});
+        (void)hipEventRecord(ev[1], h->stream);
+        dispatch(h, VcorrectPass{h});
+        (void)hipEventRecord(ev[2], h->stream);
+        dispatch(h, CollidePass{h});
+        (void)hipEventRecord(ev[3], h->stream);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+        if (e != hipSuccess) {
+            out = fail(LBM_ERR_HIP, "timed step failed: %s", hipGetErrorString(e));
+            break;
+        }
+        for (int j = 0; j < 3; ++j) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[j], ev[j + 1]);
+            acc[j] += ms;
+        }
+        h->phase ^= 1;
+        h->step += 1;
+    }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    for (int j = 0; j < 3; ++j) kernel_ms[j] = acc[j];
+    return out;
+}
+
+LBM_API int lbm_moments(lbm_solver *h, void *rho_dev, void *v_dev, int dtype, int velocity_kind) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_INVALID_ARG, "bad dtype");
+    if (velocity_kind != LBM_VELOCITY_SUPERFICIAL && velocity_kind != LBM_VELOCITY_INTRINSIC)
+        return fail(LBM_ERR_INVALID_ARG, "bad velocity_kind");
+    rc = current_moments(h);
+    if (rc) return rc;
+    const int64_t N = h->N;
+#define LBM_OUT(DD, TT, OO)                                                                      \
+    hipLaunchKernelGGL((lbm::k_moments_out<DD, TT, OO>), flat_grid(N), dim3(256), 0, h->stream, \
+                       ws_ptr<const TT>(h, h->L.rho), ws_ptr<const TT>(h, h->L.v),              \
+                       ws_ptr<const TT>(h, h->L.eps), (OO *)rho_dev, (OO *)v_dev, N, velocity_kind)
+    if (h->D == 2) {
+        if (h->storage == LBM_F64) { if (dtype == LBM_DTYPE_F64) LBM_OUT(2, double, double); else LBM_OUT(2, double, float); }
+        else { if (dtype == LBM_DTYPE_F64) LBM_OUT(2, float, double); else LBM_OUT(2, float, float); }
+    } else {
+        if (h->storage == LBM_F64) { if (dtype == LBM_DTYPE_F64) LBM_OUT(3, double, double); else LBM_OUT(3, double, float); }
+        else { if (dtype == LBM_DTYPE_F64) LBM_OUT(3, float, double); else LBM_OUT(3, float, float); }
+    }
+#undef LBM_OUT
+    LAUNCH_CHECK();
+    return LBM_OK;
+}
+
+LBM_API int lbm_residual(lbm_solver *h, lbm_stats *out) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
+    rc = current_moments(h);
+    if (rc) return rc;
+    dispatch(h, StatsPass{h});
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(lbm::k_stats_final, dim3(1), dim3(256), 0, h->stream,
+                       ws_ptr<const double>(h, h->L.part), lbm::kStatsBlocks, ws_ptr<double>(h, h->L.res));
+    LAUNCH_CHECK();
+    double r[lbm::kStatsSlots];
+    HIP_TRY(hipMemcpyAsync(r, h->ws + h->L.res, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    out->mass = r[0];
+    out->momentum[0] = r[1];
+    out->momentum[1] = r[2];
+    out->momentum[2] = h->D == 3 ? r[3] : 0.0;
+    out->vmax = r[4];
+    out->dv2 = r[5];
+    out->v2 = r[6];
+    out->residual = r[6] > 0 ? std::sqrt(r[5] / r[6]) : INFINITY;
+    out->nonfinite = (int64_t)r[7];
+    out->step = h->step;
+    if (out->nonfinite > 0) return fail(LBM_ERR_NONFINITE, "%lld fluid cells are not finite", (long long)out->nonfinite);
+    return LBM_OK;
+}
+
+LBM_API int lbm_get_populations(lbm_solver *h, void *dev_out, int dtype) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!dev_out) return fail(LBM_ERR_INVALID_ARG, "dev_out is NULL");
+    if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_INVALID_ARG, "bad dtype");
+    dispatch(h, ExportPass{h, dev_out, dtype});
+    LAUNCH_CHECK();
+    return LBM_OK;
+}
+
+LBM_API int lbm_set_populations(lbm_solver *h, const void *dev_in, int dtype, int64_t step) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!dev_in) return fail(LBM_ERR_INVALID_ARG, "dev_in is NULL");
+    if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_INVALID_ARG, "bad dtype");
+    if (step < 0) return fail(LBM_ERR_INVALID_ARG, "negative step");
+    const int64_t total = (int64_t)h->Q * h->N;
+    if (h->storage == LBM_F64) {
+        if (dtype == LBM_DTYPE_F64) hipLaunchKernelGGL((lbm::k_import<double, double>), flat_grid(total), dim3(256), 0, h->stream, ws_ptr<double>(h, h->L.f), (const double *)dev_in, total);
+        else hipLaunchKernelGGL((lbm::k_import<double, float>), flat_grid(total), dim3(256), 0, h->stream, ws_ptr<double>(h, h->L.f), (const float *)dev_in, total);
+    } else {
+        if (dtype == LBM_DTYPE_F64) hipLaunchKernelGGL((lbm::k_import<float, double>), flat_grid(total), dim3(256), 0, h->stream, ws_ptr<float>(h, h->L.f), (const double *)dev_in, total);
+        else hipLaunchKernelGGL((lbm::k_import<float, float>), flat_grid(total), dim3(256), 0, h->stream, ws_ptr<float>(h, h->L.f), (const float *)dev_in, total);
+    }
+    LAUNCH_CHECK();
+    h->phase = 0;
+    h->step = step;
+    return LBM_OK;
+}
+
+LBM_API int lbm_get_step(const lbm_solver *h, int64_t *step) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!step) return fail(LBM_ERR_INVALID_ARG, "step is NULL");
+    *step = h->step;
+    return LBM_OK;
+}
+
+LBM_API int lbm_destroy(lbm_solver *h) {
+    delete h;
+    return LBM_OK;
+}
+
+}  // extern "C"

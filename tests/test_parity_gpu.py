@@ -1,0 +1,239 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle on the same
+seeded inputs, element by element.
+
+FP64 storage must match to 1e-12 normwise per field, e(X) = max|X_gpu - X_orc| / max|X_orc|,
+for X in {f-bar (all i), rho, rho - rho0, each component of v}.  Both sides evaluate every
+expression in the same order without contraction, so the measured differences are zero or a
+few ulps.  FP32 storage is compared with the tolerances derived in the test of each case.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_29619_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+capi = pytest.importorskip("paper_2606_29619_amd.capi")
+
+FP64_TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    capi.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def _oracle_for(w, **extra):
+    cfg = oracle.OracleConfig(D=w.D, eps=w.eps, kappa=w.kappa, cf=w.forch, mask=w.mask,
+                              RT=w.RT, nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref,
+                              nu_eff_pow=w.nu_eff_pow, eta_eff=w.eta_eff, b=w.b, rho0=w.rho0,
+                              rho_init=w.rho_init, v_init=w.v_init, **extra)
+    return oracle.Oracle(cfg)
+
+
+def _rel(a, b):
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+
+
+def _field_errors(s, o, rho0=1.0):
+    f_gpu = s.populations(torch.float64).cpu().numpy()
+    rho_gpu, v_gpu = (t.cpu().numpy() for t in s.moments(torch.float64))
+    f_ref = o.populations()
+    rho_ref, v_ref, _ = o.moments()
+    errs = {"f": _rel(f_gpu, f_ref), "rho": _rel(rho_gpu, rho_ref)}
+    fluid = ~o.mask
+    errs["rho-rho0"] = _rel(np.where(fluid, rho_gpu - rho0, 0), np.where(fluid, rho_ref - rho0, 0))
+    for a in range(v_ref.shape[0]):
+        errs[f"v{a}"] = _rel(v_gpu[a], v_ref[a])
+    return errs
+
+
+def _print(tag, errs):
+    print(tag, " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+
+
+def _run_pair(w, steps, storage=capi.LBM_F64, chunks=1):
+    s = capi.Solver.from_workload(w, storage=storage)
+    o = _oracle_for(w)
+    per = steps // chunks
+    for _ in range(chunks):
+        s.step(per)
+        o.step(per)
+    torch.cuda.synchronize()
+    return s, o
+
+
+# --------------------------------------------------------------------------------------------
+# FP64 bit-level parity
+# --------------------------------------------------------------------------------------------
+def test_d2q9_step_channel_full_run():
+    """The D2Q9 FP64 128x64 step channel (periodic in x, solid rows y = 0 and 63, porosity 1 /
+    0.4 with K = 1e-3, nu_eff = nu/phi, g = 1e-6; porosity step smoothed over 8 cells) over its
+    full 10,000 steps."""
+    w = workloads.channel_step_2d()
+    s, o = _run_pair(w, 10000)
+    errs = _field_errors(s, o)
+    _print("d2q9 channel 10k:", errs)
+    assert max(errs.values()) <= FP64_TOL, errs
+    st = s.residual()
+    assert st.nonfinite == 0 and st.step == 10000
+
+
+def test_d2q9_literal_step_parity_and_blowup_detection():
+    """With the literal (unsmoothed) porosity step the explicit viscous correction meets
+    d eps = 0.3 and a Hessian of 0.6 at the interface: the first steps still agree to FP64
+    parity (large Delta_nu terms exercised), and the run then diverges on both sides within a
+    few tens of steps, which lbm_residual reports as LBM_ERR_NONFINITE."""
+    w = workloads.channel_step_2d(smooth_width=0)
+    s, o = _run_pair(w, 6)
+    errs = _field_errors(s, o)
+    _print("d2q9 literal step 6 steps:", errs)
+    assert max(errs.values()) <= FP64_TOL, errs
+    s.step(60)
+    with pytest.raises(capi.LbmError) as ei:
+        s.residual()
+    assert ei.value.code == capi.LBM_ERR_NONFINITE
+    st = s.residual(allow_nonfinite=True)
+    assert st.nonfinite > 0
+
+
+@pytest.mark.parametrize("shape,solids", [((9, 13, 70), True), ((7, 5, 130), False),
+                                          ((1, 3, 1), False)])
+def test_d3q27_heterogeneous_ragged(shape, solids):
+    """D3Q27 FP64 on ragged shapes (x not a multiple of the 64-wide block, y not a multiple of
+    4), random porosity, with and without solid blocks touching each other and the
+    periodic seams."""
+    w = workloads.random_porosity_3d(shape=shape, seed=11, ell=2.5, nu=0.04, b=3e-4)
+    if solids:
+        m = np.zeros(shape, np.uint8)
+        m[2:5, 3:7, 10:20] = 1
+        m[:, 0, 40:45] = 1
+        m[0, :, 63:66] = 1
+        w.mask = m
+    s, o = _run_pair(w, 24, chunks=2)
+    errs = _field_errors(s, o)
+    _print(f"d3q27 {shape} solids={solids}:", errs)
+    assert max(errs.values()) <= FP64_TOL, errs
+
+
+def test_d2q9_all_options():
+    """D2Q9 FP64 with every option of the method switched on: RT != 1/3 (extended equilibrium
+    correction active), bulk viscosity (Phi^eta), nu_eff = nu_ref eps, an initial velocity and
+    density field, Forchheimer drag, solids."""
+    w = workloads.random_porosity_2d(nx=67, ny=29, seed=4, ell=4.0, nu=0.03, b=2e-4)
+    w.RT = 0.25
+    w.eta_eff = 0.05
+    w.nu_eff_pow = 1
+    y, x = np.meshgrid(np.arange(29), np.arange(67), indexing="ij")
+    w.v_init = np.stack([0.01 * np.sin(2 * np.pi * y / 29), 0.005 * np.cos(2 * np.pi * x / 67)])[:, None]
+    w.rho_init = (1 + 0.002 * np.cos(2 * np.pi * x / 67))[None]
+    m = np.zeros(w.shape, np.uint8)
+    m[0, 10:14, 20:31] = 1
+    w.mask = m
+    s, o = _run_pair(w, 40, chunks=2)
+    errs = _field_errors(s, o)
+    _print("d2q9 options:", errs)
+    assert max(errs.values()) <= FP64_TOL, errs
+
+
+def test_d3q27_nu_over_eps_with_eta():
+    w = workloads.random_porosity_3d(shape=(6, 8, 10), seed=3, ell=2.0, nu=0.02, b=1e-4)
+    w.nu_eff_pow = -1
+    w.eta_eff = 0.01
+    w.RT = 0.4
+    s, o = _run_pair(w, 10)
+    errs = _field_errors(s, o)
+    _print("d3q27 nu/eps eta:", errs)
+    assert max(errs.values()) <= FP64_TOL, errs
+
+
+def test_initial_state_matches():
+    """Step 0: the initial populations of eq. (eq_bc_f_bar)."""
+    w = workloads.random_porosity_3d(shape=(5, 6, 7), seed=9, ell=2.0, nu=0.03, b=1e-3)
+    s, o = _run_pair(w, 0)
+    errs = _field_errors(s, o)
+    assert max(errs.values()) <= FP64_TOL, errs
+
+
+# --------------------------------------------------------------------------------------------
+# Statistics, checkpoints, outputs
+# --------------------------------------------------------------------------------------------
+def test_residual_statistics_match_oracle():
+    w = workloads.random_porosity_2d(nx=40, ny=30, seed=8, ell=4.0, nu=0.05, b=1e-4)
+    m = np.zeros(w.shape, np.uint8)
+    m[0, 0, :] = m[0, -1, :] = 1
+    w.mask = m
+    s = capi.Solver.from_workload(w, storage=capi.LBM_F64)
+    o = _oracle_for(w)
+    g0, r0 = s.residual(), o.stats()
+    assert math.isinf(g0.residual) and math.isinf(r0["residual"])
+    for _ in range(3):
+        s.step(50)
+        o.step(50)
+        g, r = s.residual(), o.stats()
+        assert abs(g.mass - r["mass"]) <= 1e-13 * r["mass"]
+        np.testing.assert_allclose([g.momentum[0], g.momentum[1]], r["momentum"][:2],
+                                   rtol=1e-11, atol=1e-20)
+        assert abs(g.vmax - r["vmax"]) <= 1e-12 * r["vmax"]
+        assert abs(g.residual - r["residual"]) <= 1e-10 * r["residual"]
+        assert g.nonfinite == 0 and g.step == s.step_count
+
+
+def test_checkpoint_roundtrip_is_exact():
+    """get/set populations (natural layout) resumes bit for bit, from either AA phase."""
+    w = workloads.random_porosity_3d(shape=(8, 9, 10), seed=2, ell=2.0, nu=0.03, b=2e-4)
+    w.mask = np.zeros(w.shape, np.uint8)
+    w.mask[3:5, 3:5, 3:5] = 1
+    for storage in (capi.LBM_F64, capi.LBM_F32):
+        a = capi.Solver.from_workload(w, storage=storage)
+        b = capi.Solver.from_workload(w, storage=storage)
+        a.step(7)                                   # odd: swapped AA layout
+        b.step(7)
+        ck = b.populations()
+        b.step(3)
+        b.set_populations(ck, step=7)
+        assert b.step_count == 7
+        a.step(6)
+        b.step(6)
+        fa, fb = a.populations().cpu().numpy(), b.populations().cpu().numpy()
+        assert np.array_equal(fa, fb)
+
+
+def test_intrinsic_velocity_output():
+    w = workloads.random_porosity_2d(nx=20, ny=16, seed=1, ell=3.0, nu=0.05, b=1e-4)
+    s = capi.Solver.from_workload(w, storage=capi.LBM_F64)
+    s.step(5)
+    _, v = s.moments(torch.float64)
+    _, u = s.moments(torch.float64, intrinsic=True)
+    eps = torch.from_numpy(w.eps).to(v.device)
+    torch.testing.assert_close(u * eps, v, rtol=1e-15, atol=0)
+    rho32, v32 = s.moments(torch.float32)
+    assert rho32.dtype == torch.float32
+    torch.testing.assert_close(v32.double(), v, rtol=1e-7, atol=1e-12)
+
+
+# --------------------------------------------------------------------------------------------
+# FP32 storage against the FP64 oracle
+# --------------------------------------------------------------------------------------------
+def test_d3q27_fp32_tracks_fp64_oracle():
+    """FP32 storage and arithmetic against the FP64 oracle on the random-porosity recipe
+    (32^3, l = 16, nu = 0.01, b = 1e-6, 100 steps).  Tolerance model: each step rounds every
+    population (~0.3) a few times at u = 6e-8, so after n steps f-bar drifts by ~sqrt(n) * 5u
+    ~ 3e-6 of its maximum; rho = S/eps sums 27 of them (~1e-5); v is a difference of
+    populations divided by rho, ~1e-8 absolute against |v| ~ 1e-5..1e-4 here.  Measured on
+    MI355X: f 6.5e-6, rho 1.4e-5, v 1.6e-4..4.0e-4; the bounds below leave a factor ~3-5."""
+    w = workloads.random_porosity_3d(shape=(32, 32, 32), seed=0, ell=16.0)
+    s, o = _run_pair(w, 100, storage=capi.LBM_F32)
+    errs = _field_errors(s, o)
+    _print("d3q27 fp32 vs fp64 oracle:", errs)
+    assert errs["f"] < 3e-5 and errs["rho"] < 5e-5
+    assert max(errs[k] for k in ("v0", "v1", "v2")) < 2e-3
