@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput of the porous-media lattice Boltzmann hot path on one MI355X.
+
+Workload: D3Q27, FP32 storage and arithmetic, 256^3 periodic box, porosity from a seeded
+Gaussian random field (correlation length 16 cells) mapped to phi in (0.3, 1), Kozeny-Carman
+permeability with d = 2 cells, Forchheimer coefficient 0.55/sqrt(K), nu = 0.01, body force
+1e-6 along x (synthetic inputs; see paper_2606_29619_amd/workloads.py).  A step is one full
+update of every cell: moment pass, velocity correction, forcing-collide-stream pass.
+
+Prints one JSON line: MLUPS (whole job), the roofline of the dominant kernel measured with HIP
+events on the library's stream over the timed region, and the FP64 CPU oracle timed on a
+bounded sample of the same recipe.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E, published
+METRIC = "MLUPS & % HBM roofline (D3Q27); served MLUPS + p50/p99 time-to-steady"
+
+
+def kernel_bytes_per_cell(Q, D, s):
+    """Algorithmic HBM bytes per cell of each kernel (values each kernel must move once):
+    moments: read Q pops + eps, mu_D, mu_F; write rho and v^(1) (D+1);
+    velocity correction: read rho, v^(1), eps; write v (D);
+    collide-stream: read Q pops, rho, v, eps, mu_D, mu_F; write Q pops."""
+    return {
+        "moments": (Q + 3 + (D + 1)) * s,
+        "vcorrect": ((D + 1) + 1 + D) * s,
+        "collide": (Q + (D + 1) + 3 + Q) * s,
+    }
+
+
+def method_bytes_per_cell(Q, D, s):
+    """Two-pass minimum of the faithful method: pass one reads Q pops + 3 static fields and
+    writes rho, v^(1); pass two reads Q pops, rho, v, 3 static fields and writes Q pops."""
+    return (Q + 3 + (D + 1)) * s + (Q + (D + 1) + 3 + Q) * s
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for rel in ("paper_2606_29619_amd/csrc/lbm_device.hpp", "paper_2606_29619_amd/csrc/lbm.hip"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, N, src_hash):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, when it was taken on
+    the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "pmc_d3q27_f32_256.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        pmc = json.load(fh)
+    if pmc.get("source_hash") != src_hash or kernel not in pmc.get("kernels", {}):
+        return None
+    k = pmc["kernels"][kernel]
+    return (k["fetch_kib"] * pmc["fetch_scale"] + k["write_kib"] * pmc["write_scale"]) * 1024.0
+
+
+def cpu_baseline(budget_s=15.0):
+    """The FP64 oracle, as it stands, on the 64^3 instance of the same recipe (seed 0):
+    one process, one thread; steps until about budget_s of stepping have elapsed."""
+    import oracle
+    from paper_2606_29619_amd import workloads
+    w = workloads.random_porosity_3d(n=64, seed=0, ell=16.0)
+    o = oracle.Oracle(oracle.OracleConfig(D=3, eps=w.eps, kappa=w.kappa, cf=w.forch,
+                                          nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref, b=w.b))
+    t0 = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t0
+    k = max(1, int(budget_s / max(one, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    o.step(k)
+    dt = time.perf_counter() - t0
+    cells = w.cells
+    return {"value": round(cells * k / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"FP64 oracle, D3Q27 64^3 instance of the same random-porosity recipe "
+                      f"(seed 0), {k} timed steps after 1 warm-up step, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="cells per side")
+    ap.add_argument("--storage", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed region, run one plain device copy of this many MiB "
+                         "(counter calibration for profiling runs)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only: the hot path is a single-GPU kernel and this "
+              f"build has no multi-GPU path (asked for --gpus {args.gpus}, WORLD_SIZE {world}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2606_29619_amd import capi, workloads
+
+    torch.cuda.set_device(0)
+    n = args.n
+    w = workloads.random_porosity_3d(n=n, seed=0, ell=16.0, steps=args.steps)
+    storage = capi.LBM_F32 if args.storage == "f32" else capi.LBM_F64
+    s_bytes = 4 if args.storage == "f32" else 8
+    solver = capi.Solver.from_workload(w, storage=storage)
+    N = w.cells
+    print(f"[bench] created {w.name}, {args.storage}, workspace {solver.nbytes / 2**30:.2f} GiB",
+          file=sys.stderr, flush=True)
+
+    solver.step(args.warmup)
+    torch.cuda.synchronize()
+    print(f"[bench] warm-up {args.warmup} steps done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = solver.step_timed(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = solver.residual()
+    wall = t1 - t0
+    mlups = N * args.steps / wall / 1e6
+    print(f"[bench] timed {args.steps} steps in {wall:.3f} s; mass {st.mass:.9e} "
+          f"vmax {st.vmax:.3e}", file=sys.stderr, flush=True)
+    assert st.nonfinite == 0
+
+    Q, D = 27, 3
+    kb = kernel_bytes_per_cell(Q, D, s_bytes)
+    avg_ms = {"moments": kms[0] / args.steps, "vcorrect": kms[1] / args.steps,
+              "collide": kms[2] / args.steps}
+    dom = max(avg_ms, key=avg_ms.get)
+    algo = kb[dom] * N
+    achieved = algo / (avg_ms[dom] * 1e-3) / 1e9
+    src = source_hash()
+    traffic = traffic_from_profiles(dom, N, src)
+    step_bytes = method_bytes_per_cell(Q, D, s_bytes)
+    kernels = {k: {"avg_ms": round(avg_ms[k], 4), "bytes_per_cell": kb[k],
+                   "achieved_GBps": round(kb[k] * N / (avg_ms[k] * 1e-3) / 1e9, 1)}
+               for k in avg_ms}
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": f"random-porosity D3Q27 {n}^3 periodic box, seed 0, "
+                               f"correlation length 16, phi in (0.3,1), Kozeny-Carman K (d=2), "
+                               f"C_F=0.55/sqrt(K), nu=0.01, b=1e-6 x", "lattice": "D3Q27",
+                   "cells": N, "storage": args.storage, "scheme": "faithful two-pass"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": None if traffic is None else round(traffic, 0),
+                     "algorithmic_bytes_per_launch": algo},
+        "step_hbm": {"method_bytes_per_cell": step_bytes,
+                     "effective_GBps": round(mlups * 1e6 * step_bytes / 1e9, 1),
+                     "frac_of_peak": round(mlups * 1e6 * step_bytes / 1e9 / HBM_PEAK_GBPS, 4)},
+        "kernels": kernels,
+        "source_hash": src,
+    }
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib * 2 ** 20
+        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = {"read": nb, "write": nb}
+        del a, b
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

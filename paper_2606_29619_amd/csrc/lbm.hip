@@ -12,6 +12,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "lbm_device.hpp"
 
@@ -448,31 +450,39 @@ LBM_API int lbm_step_timed(lbm_solver *h, int64_t n, double kernel_ms[3]) {
     int rc = check_handle(h);
     if (rc) return rc;
     if (n < 0 || !kernel_ms) return fail(LBM_ERR_INVALID_ARG, "bad step count or output");
-    hipEvent_t ev[4];
+    // Events bracket every kernel of a chunk of steps; the host waits once per chunk.
+    constexpr int64_t kChunk = 2048;
+    const int64_t nev = 3 * std::min<int64_t>(n, kChunk) + 1;
+    std::vector<hipEvent_t> ev((size_t)nev);
     for (auto &x : ev) HIP_TRY(hipEventCreate(&x));
     double acc[3] = {0, 0, 0};
     int out = LBM_OK;
-    for (int64_t k = 0; k < n && out == LBM_OK; ++k) {
-        (void)hipEventRecord(ev[0], h->stream);
-        dispatch(h, MomentsPass{h});
-        (void)hipEventRecord(ev[1], h->stream);
-        dispatch(h, VcorrectPass{h});
-        (void)hipEventRecord(ev[2], h->stream);
-        dispatch(h, CollidePass{h});
-        (void)hipEventRecord(ev[3], h->stream);
-        hipError_t e = hipGetLastError();
-        if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+    for (int64_t done = 0; done < n && out == LBM_OK;) {
+        const int64_t m = std::min<int64_t>(n - done, kChunk);
+        hipError_t e = hipEventRecord(ev[0], h->stream);
+        for (int64_t k = 0; k < m && e == hipSuccess; ++k) {
+            dispatch(h, MomentsPass{h});
+            e = hipEventRecord(ev[3 * k + 1], h->stream);
+            dispatch(h, VcorrectPass{h});
+            if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 2], h->stream);
+            dispatch(h, CollidePass{h});
+            if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 3], h->stream);
+            if (e == hipSuccess) e = hipGetLastError();
+            h->phase ^= 1;
+            h->step += 1;
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(ev[3 * m]);
         if (e != hipSuccess) {
             out = fail(LBM_ERR_HIP, "timed step failed: %s", hipGetErrorString(e));
             break;
         }
-        for (int j = 0; j < 3; ++j) {
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, ev[j], ev[j + 1]);
-            acc[j] += ms;
-        }
-        h->phase ^= 1;
-        h->step += 1;
+        for (int64_t k = 0; k < m; ++k)
+            for (int j = 0; j < 3; ++j) {
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, ev[3 * k + j], ev[3 * k + j + 1]);
+                acc[j] += ms;
+            }
+        done += m;
     }
     for (auto &x : ev) (void)hipEventDestroy(x);
     for (int j = 0; j < 3; ++j) kernel_ms[j] = acc[j];
