@@ -15,7 +15,8 @@ from typing import Optional
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "liblbm.so")
+# LBM_LIBRARY points the binding at another build of the same ABI (kernel-variant timing).
+LIB_PATH = os.environ.get("LBM_LIBRARY", os.path.join(_PKG, "liblbm.so"))
 
 LBM_OK = 0
 LBM_ERR_INVALID_ARG = -1

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 #include <string>
 #include <vector>
@@ -90,6 +91,7 @@ struct lbm_solver {
     int phase;  // AA-pattern layout: 0 natural, 1 swapped
     double RT, nu_f, nu_eff_ref, eta_eff, b[3];
     int nu_eff_pow;
+    lbm::Tiling tiles;  // 64 x 4 x 1 cell tiles in XCD-contiguous order
 };
 
 namespace {
@@ -108,13 +110,24 @@ lbm::Phys<T> phys_of(const lbm_solver *h) {
     return ph;
 }
 
-lbm::Grid grid_of(const lbm_solver *h) { return lbm::Grid{h->nx, h->ny, h->nz, h->N}; }
+lbm::Grid grid_of(const lbm_solver *h) { return lbm::Grid{h->nx, h->ny, h->nz, (uint32_t)h->N}; }
 
-dim3 cell_grid(const lbm_solver *h) {
-    return dim3((unsigned)((h->nx + 63) / 64), (unsigned)((h->ny + 3) / 4), (unsigned)h->nz);
-}
 
 dim3 flat_grid(int64_t total) { return dim3((unsigned)((total + 255) / 256)); }
+
+lbm::Tiling make_tiling(int nx, int ny, int nz) {
+    lbm::Tiling t;
+    t.tx = nx >= 192 ? 256 : (nx >= 96 ? 128 : 64);
+    t.ty = 256 / t.tx;
+    t.ntx = (nx + t.tx - 1) / t.tx;
+    t.nty = (ny + t.ty - 1) / t.ty;
+    t.ntz = nz;
+    const int64_t nt = (int64_t)t.ntx * t.nty * t.ntz;
+    t.per = (uint32_t)((nt + 7) / 8);
+    return t;
+}
+
+dim3 cell_tiles(const lbm_solver *h) { return dim3((unsigned)(8 * (int64_t)h->tiles.per)); }
 
 template <typename T>
 T *ws_ptr(const lbm_solver *h, size_t off) {
@@ -129,45 +142,45 @@ const uint8_t *mask_ptr(const lbm_solver *h) {
 template <int D, typename T, bool S, int PH>
 void launch_moments(const lbm_solver *h) {
     auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_moments<D, T, S, PH>), cell_grid(h), dim3(64, 4, 1), 0, h->stream,
+    hipLaunchKernelGGL((lbm::k_moments<D, T, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
                        ws_ptr<const T>(h, h->L.f), ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
-                       ws_ptr<T>(h, h->L.rho), ws_ptr<T>(h, h->L.v1), grid_of(h), ph);
+                       ws_ptr<T>(h, h->L.rho), ws_ptr<T>(h, h->L.v1), grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, bool S>
 void launch_vcorrect(const lbm_solver *h) {
     auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_vcorrect<D, T, S>), cell_grid(h), dim3(64, 4, 1), 0, h->stream,
+    hipLaunchKernelGGL((lbm::k_vcorrect<D, T, S>), cell_tiles(h), dim3(256), 0, h->stream,
                        ws_ptr<const T>(h, h->L.rho), ws_ptr<const T>(h, h->L.v1),
                        ws_ptr<const T>(h, h->L.eps), mask_ptr(h), ws_ptr<T>(h, h->L.v),
-                       grid_of(h), ph);
+                       grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, bool S, int PH>
 void launch_collide(const lbm_solver *h) {
     auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_collide<D, T, S, PH>), cell_grid(h), dim3(64, 4, 1), 0, h->stream,
+    hipLaunchKernelGGL((lbm::k_collide<D, T, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
                        ws_ptr<T>(h, h->L.f), ws_ptr<const T>(h, h->L.rho),
                        ws_ptr<const T>(h, h->L.v), ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
-                       grid_of(h), ph);
+                       grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, bool S>
 void launch_init(const lbm_solver *h) {
     auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_init<D, T, S>), cell_grid(h), dim3(64, 4, 1), 0, h->stream,
+    hipLaunchKernelGGL((lbm::k_init<D, T, S>), cell_tiles(h), dim3(256), 0, h->stream,
                        ws_ptr<T>(h, h->L.f), ws_ptr<const T>(h, h->L.rho),
                        ws_ptr<const T>(h, h->L.v), ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
-                       grid_of(h), ph);
+                       grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, bool S, int PH, typename O>
 void launch_export(const lbm_solver *h, O *out) {
-    hipLaunchKernelGGL((lbm::k_export<D, T, S, PH, O>), cell_grid(h), dim3(64, 4, 1), 0, h->stream,
-                       ws_ptr<const T>(h, h->L.f), mask_ptr(h), out, grid_of(h));
+    hipLaunchKernelGGL((lbm::k_export<D, T, S, PH, O>), cell_tiles(h), dim3(256), 0, h->stream,
+                       ws_ptr<const T>(h, h->L.f), mask_ptr(h), out, grid_of(h), h->tiles);
 }
 
 template <int D, typename T, bool S, int PH>
@@ -266,7 +279,10 @@ int validate_shape(const lbm_params *p, int *D, int *Q, size_t *s, int64_t *N) {
     if (p->ny > 4 * 65535 || p->nz > 65535)
         return fail(LBM_ERR_UNSUPPORTED, "ny must be <= 262140 and nz <= 65535");
     *N = (int64_t)p->nx * p->ny * p->nz;
-    if (*N > ((int64_t)1 << 40)) return fail(LBM_ERR_INVALID_ARG, "too many cells");
+    // every array plane is addressed with 32-bit byte offsets
+    if ((uint64_t)*N * *s >= ((uint64_t)1 << 32))
+        return fail(LBM_ERR_UNSUPPORTED, "%lld cells of %zu bytes exceed 4 GiB per field",
+                    (long long)*N, *s);
     return LBM_OK;
 }
 
@@ -366,6 +382,7 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     h->ws = reinterpret_cast<char *>(dev_workspace);
     h->L = L;
+    h->tiles = make_tiling(p->nx, p->ny, p->nz);
     h->step = 0;
     h->phase = 0;
     h->RT = p->RT;

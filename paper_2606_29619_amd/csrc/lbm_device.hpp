@@ -19,8 +19,15 @@
 // written back to slot (opp(i), n).  Every thread reads and writes the same set of slots, so
 // the update is race-free in place.  Every axis wraps periodically.
 //
-// Floating-point: the library is built with -ffp-contract=off and every expression below is
-// written in the evaluation order of the CPU reference, so FP64 results agree bit for bit.
+// Addressing: every array plane holds fewer than 2^32 bytes, so a thread addresses it with a
+// 32-bit byte offset added to a uniform 64-bit base (the scalar-base + vector-offset form of
+// the global memory instructions).  The periodic neighbours of a cell are precomputed once
+// per thread (three x positions, nine y/z row bases).
+//
+// Floating point: built with -ffp-contract=off.  In FP64 every expression is evaluated exactly
+// as written, in the order of the CPU reference, so FP64 results agree bit for bit.  In FP32 a
+// quotient a/b is a * rcp(b) and a square root is the hardware one (both within 1 ulp): the FP32
+// path is checked against the FP64 reference with a stated tolerance, not bitwise.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -66,7 +73,7 @@ __device__ __forceinline__ void unroll(F &&f) {
 
 struct Grid {
     int nx, ny, nz;
-    int64_t N;
+    uint32_t N;  // cells; N * sizeof(T) < 2^32
 };
 
 template <typename T>
@@ -81,6 +88,52 @@ struct Phys {
     int eta_on;    // Phi^eta switched on
 };
 
+// ---- arithmetic policy -------------------------------------------------------------------
+__device__ __forceinline__ double dv(double a, double b) { return a / b; }
+__device__ __forceinline__ float dv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double sq(double x) { return sqrt(x); }
+__device__ __forceinline__ float sq(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// ---- memory access -------------------------------------------------------------------------
+// Element `idx` of a plane starting at `base`: 32-bit byte offset on a uniform base.
+template <typename T>
+__device__ __forceinline__ const T *at(const T *base, uint32_t idx) {
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                       idx * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T *at(T *base, uint32_t idx) {
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T ld(const T *base, uint32_t idx) {
+    return *at(base, idx);
+}
+
+// Populations stream through once per kernel.  In the natural-layout phase each thread touches
+// only its own cell, and the accesses are non-temporal (the caches are left to the reused
+// moment and porosity fields).  In the swapped phase the x-shifted accesses of neighbouring
+// lanes share cache lines, so they go through the caches normally.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_pop(const T *base, uint32_t idx) {
+    if constexpr (NT) return __builtin_nontemporal_load(at(base, idx));
+    else return *at(base, idx);
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_pop(T *base, uint32_t idx, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, at(base, idx));
+    else *at(base, idx) = v;
+}
+
+template <typename T>
+__device__ __forceinline__ const T *plane(const T *f, int i, uint32_t N) {
+    return f + (size_t)i * N;
+}
+template <typename T>
+__device__ __forceinline__ T *plane(T *f, int i, uint32_t N) {
+    return f + (size_t)i * N;
+}
+
 __device__ __forceinline__ int wrap1(int x, int k, int n) {
     // x + k on a periodic axis of length n, for k in {-1, 0, 1}
     if (k > 0) return x + 1 == n ? 0 : x + 1;
@@ -93,63 +146,84 @@ __device__ __forceinline__ int wrapk(int x, int k, int n) {
     return r < 0 ? r + n : r;
 }
 
-__device__ __forceinline__ int64_t cell_index(const Grid &g, int x, int y, int z) {
-    return (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
-}
-
-// Neighbour of (x,y,z) displaced by k (|k| <= 2) along axis a.
-__device__ __forceinline__ int64_t axis_neighbor(const Grid &g, int x, int y, int z, int a, int k) {
-    if (k == 1 || k == -1) {
-        if (a == 0) x = wrap1(x, k, g.nx);
-        else if (a == 1) y = wrap1(y, k, g.ny);
-        else z = wrap1(z, k, g.nz);
-    } else {
-        if (a == 0) x = wrapk(x, k, g.nx);
-        else if (a == 1) y = wrapk(y, k, g.ny);
-        else z = wrapk(z, k, g.nz);
+// Periodic neighbourhood of one cell: cell index of (x + cx, y + cy, z + cz), |c| <= 1.
+template <int D>
+struct Nbr {
+    uint32_t xs[3];
+    uint32_t row[3][3];
+    int x, y, z;
+    __device__ __forceinline__ void init(const Grid &g, int x_, int y_, int z_) {
+        x = x_;
+        y = y_;
+        z = z_;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xs[k] = (uint32_t)wrap1(x, k - 1, g.nx);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const uint32_t yy = (uint32_t)wrap1(y, j - 1, g.ny);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (D == 2 && k != 1) continue;
+                const uint32_t zz = D == 3 ? (uint32_t)wrap1(z, k - 1, g.nz) : (uint32_t)z;
+                row[j][k] = (uint32_t)g.nx * (yy + (uint32_t)g.ny * zz);
+            }
+        }
     }
-    return cell_index(g, x, y, z);
-}
+    __device__ __forceinline__ uint32_t at(int cx, int cy, int cz) const {
+        return xs[cx + 1] + row[cy + 1][cz + 1];
+    }
+    __device__ __forceinline__ uint32_t self() const { return at(0, 0, 0); }
+    // Neighbour along axis a at offset k (|k| <= 2).
+    __device__ __forceinline__ uint32_t axis(const Grid &g, int a, int k) const {
+        if (k == 1 || k == -1) {
+            return a == 0 ? at(k, 0, 0) : (a == 1 ? at(0, k, 0) : at(0, 0, k));
+        }
+        int c[3] = {x, y, z};
+        const int n = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+        c[a] = wrapk(c[a], k, n);
+        return (uint32_t)c[0] + (uint32_t)g.nx * ((uint32_t)c[1] + (uint32_t)g.ny * (uint32_t)c[2]);
+    }
+};
 
 // ------------------------------------------------------------------------------------------
 // AA-pattern population access
 // ------------------------------------------------------------------------------------------
 template <int D, bool SOLIDS, int PH, int I, typename T>
 __device__ __forceinline__ T load_pop(const T *__restrict__ f, const uint8_t *__restrict__ mask,
-                                      const Grid &g, int x, int y, int z, int64_t n) {
+                                      const Grid &g, const Nbr<D> &nb) {
     using L = Lat<D>;
     constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+    const uint32_t n = nb.self();
+    constexpr bool NT = PH == 0;
     if constexpr (PH == 0 || (cx == 0 && cy == 0 && cz == 0)) {
-        return f[(int64_t)I * g.N + n];
+        return ld_pop<NT>(plane(f, I, g.N), n);
     } else {
-        const int sx = wrap1(x, -cx, g.nx), sy = wrap1(y, -cy, g.ny);
-        const int sz = D == 3 ? wrap1(z, -cz, g.nz) : z;
-        const int64_t s = cell_index(g, sx, sy, sz);
+        const uint32_t s = nb.at(-cx, -cy, -cz);
         if constexpr (SOLIDS) {
-            if (mask[s]) return f[(int64_t)I * g.N + n];
+            if (mask[s]) return ld_pop<NT>(plane(f, I, g.N), n);
         }
-        return f[(int64_t)L::opp[I] * g.N + s];
+        return ld_pop<NT>(plane(f, L::opp[I], g.N), s);
     }
 }
 
 template <int D, bool SOLIDS, int PH, int I, typename T>
 __device__ __forceinline__ void store_pop(T *__restrict__ f, const uint8_t *__restrict__ mask,
-                                          const Grid &g, int x, int y, int z, int64_t n, T val) {
+                                          const Grid &g, const Nbr<D> &nb, T val) {
     using L = Lat<D>;
     constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+    const uint32_t n = nb.self();
+    constexpr bool NT = PH == 0;
     if constexpr (PH == 0 || (cx == 0 && cy == 0 && cz == 0)) {
-        f[(int64_t)L::opp[I] * g.N + n] = val;
+        st_pop<NT>(plane(f, L::opp[I], g.N), n, val);
     } else {
-        const int dx = wrap1(x, cx, g.nx), dy = wrap1(y, cy, g.ny);
-        const int dz = D == 3 ? wrap1(z, cz, g.nz) : z;
-        const int64_t d = cell_index(g, dx, dy, dz);
+        const uint32_t d = nb.at(cx, cy, cz);
         if constexpr (SOLIDS) {
             if (mask[d]) {
-                f[(int64_t)L::opp[I] * g.N + n] = val;
+                st_pop<NT>(plane(f, L::opp[I], g.N), n, val);
                 return;
             }
         }
-        f[(int64_t)I * g.N + d] = val;
+        st_pop<NT>(plane(f, I, g.N), d, val);
     }
 }
 
@@ -166,8 +240,8 @@ template <typename T>
 __device__ __forceinline__ Visc<T> viscosity(const Phys<T> &ph, T e) {
     Visc<T> r;
     if (ph.nu_pow == -1) {
-        r.nu = ph.nu_ref / e;
-        r.dnu = -ph.nu_ref / (e * e);
+        r.nu = dv(ph.nu_ref, e);
+        r.dnu = dv(-ph.nu_ref, e * e);
     } else if (ph.nu_pow == 1) {
         r.nu = ph.nu_ref * e;
         r.dnu = ph.nu_ref;
@@ -175,19 +249,20 @@ __device__ __forceinline__ Visc<T> viscosity(const Phys<T> &ph, T e) {
         r.nu = ph.nu_ref;
         r.dnu = T(0);
     }
-    r.beta = T(1) / (T(1) + (T(2) * r.nu) / ph.RT);
+    r.beta = dv(T(1), T(1) + dv(T(2) * r.nu, ph.RT));
     return r;
 }
 
-// Porosity gradient and Hessian by central differences (eps is defined on every cell).
+// Porosity gradient and Hessian by central differences (eps is defined on every cell); the
+// mixed derivatives come from the four diagonal neighbours, computed once for a < b.
 template <int D, typename T>
-__device__ __forceinline__ void porosity_derivatives(const T *__restrict__ eps, const Grid &g,
-                                                     int x, int y, int z, T e0, T ge[3],
-                                                     T H[3][3]) {
+__device__ __forceinline__ void porosity_derivatives(const T *__restrict__ eps, const Nbr<D> &nb,
+                                                     T e0, T ge[3], T H[3][3]) {
     unroll<0, D>([&](auto ia) {
         constexpr int a = decltype(ia)::value;
-        const T ep = eps[axis_neighbor(g, x, y, z, a, 1)];
-        const T em = eps[axis_neighbor(g, x, y, z, a, -1)];
+        constexpr int px = a == 0, py = a == 1, pz = a == 2;
+        const T ep = ld(eps, nb.at(px, py, pz));
+        const T em = ld(eps, nb.at(-px, -py, -pz));
         ge[a] = (ep - em) * T(0.5);
         H[a][a] = (ep - T(2) * e0) + em;
     });
@@ -195,16 +270,13 @@ __device__ __forceinline__ void porosity_derivatives(const T *__restrict__ eps, 
         constexpr int a = decltype(ia)::value;
         unroll<a + 1, D>([&](auto ib) {
             constexpr int b = decltype(ib)::value;
-            int c[3];
-            auto at = [&](int ka, int kb) {
-                c[0] = x; c[1] = y; c[2] = z;
-                const int na = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
-                const int nb = b == 0 ? g.nx : (b == 1 ? g.ny : g.nz);
-                c[a] = wrap1(c[a], ka, na);
-                c[b] = wrap1(c[b], kb, nb);
-                return eps[cell_index(g, c[0], c[1], c[2])];
-            };
-            const T pp = at(1, 1), pm = at(1, -1), mp = at(-1, 1), mm = at(-1, -1);
+            // offsets of the diagonal neighbour (ka along a, kb along b)
+            constexpr int ax0 = a == 0, ay0 = a == 1, az0 = a == 2;
+            constexpr int bx0 = b == 0, by0 = b == 1, bz0 = b == 2;
+            const T pp = ld(eps, nb.at(ax0 + bx0, ay0 + by0, az0 + bz0));
+            const T pm = ld(eps, nb.at(ax0 - bx0, ay0 - by0, az0 - bz0));
+            const T mp = ld(eps, nb.at(-ax0 + bx0, -ay0 + by0, -az0 + bz0));
+            const T mm = ld(eps, nb.at(-ax0 - bx0, -ay0 - by0, -az0 - bz0));
             const T h = (((pp - pm) - mp) + mm) * T(0.25);
             H[a][b] = h;
             H[b][a] = h;
@@ -232,63 +304,78 @@ struct Rec {
 
 template <int D, typename T>
 __device__ __forceinline__ Rec<T> load_rec(const T *__restrict__ rho, const T *__restrict__ w,
-                                           const T *__restrict__ eps, const Grid &g, int64_t m) {
+                                           const T *__restrict__ eps, uint32_t N, uint32_t m) {
     Rec<T> q;
-    q.r = rho[m];
-    q.e = eps[m];
+    q.r = ld(rho, m);
+    q.e = ld(eps, m);
 #pragma unroll
-    for (int b = 0; b < D; ++b) q.w[b] = w[(int64_t)b * g.N + m];
+    for (int b = 0; b < D; ++b) q.w[b] = ld(plane(w, b, N), m);
     return q;
 }
 
+// m_b = rho w_b / eps of a record (the argument of Delta_nu in eqs. v_final and accel).
+template <int D, typename T>
+__device__ __forceinline__ void rec_m(const Rec<T> &q, T m[3]) {
+#pragma unroll
+    for (int b = 0; b < D; ++b) m[b] = dv(q.r * q.w[b], q.e);
+}
+
+// Load the axis neighbours of the cell with their fluid flags.
+template <int D, typename T, bool SOLIDS>
+__device__ __forceinline__ void load_stencil(const T *__restrict__ rho, const T *__restrict__ w,
+                                             const T *__restrict__ eps,
+                                             const uint8_t *__restrict__ mask, const Grid &g,
+                                             const Nbr<D> &nb, Rec<T> rec[3][2], bool fl[3][2]) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const uint32_t m = nb.axis(g, a, s ? 1 : -1);
+            rec[a][s] = load_rec<D>(rho, w, eps, g.N, m);
+            fl[a][s] = SOLIDS ? !mask[m] : true;
+        }
+    }
+}
+
 // Variable-porosity viscous correction Delta_nu(m) at the cell, m = rho w / eps built from the
-// record fields, eq. (porosity_correction_expanded):
+// records, eq. (porosity_correction_expanded):
 //   nu {[H + tr(H) I] m + (div m) grad eps + (grad m) grad eps}
 //     + nu' [|grad eps|^2 m + (m . grad eps) grad eps],   [(grad m) grad eps]_a = sum_b d_b m_a d_b eps.
-// own: the cell's record; nb[a][0|1]: records of the -/+ neighbours along axis a.
 template <int D, typename T, bool SOLIDS>
 __device__ __forceinline__ void delta_nu(const T *__restrict__ rho, const T *__restrict__ w,
                                          const T *__restrict__ eps,
-                                         const uint8_t *__restrict__ mask, const Grid &g, int x,
-                                         int y, int z, const Rec<T> &own, const Rec<T> nb[3][2],
-                                         const bool fl[3][2], const T ge[3], const T H[3][3],
-                                         const Visc<T> &vs, T out[3]) {
+                                         const uint8_t *__restrict__ mask, const Grid &g,
+                                         const Nbr<D> &nb, const Rec<T> &own,
+                                         const Rec<T> rec[3][2], const bool fl[3][2],
+                                         const T ge[3], const T H[3][3], const Visc<T> &vs,
+                                         T out[3]) {
     T mo[3];
-#pragma unroll
-    for (int b = 0; b < D; ++b) mo[b] = (own.r * own.w[b]) / own.e;
+    rec_m<D>(own, mo);
     T J[3][3];  // J[b][a] = d_a m_b
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         T mm[3], mp[3];
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-            mm[b] = (nb[a][0].r * nb[a][0].w[b]) / nb[a][0].e;
-            mp[b] = (nb[a][1].r * nb[a][1].w[b]) / nb[a][1].e;
-        }
+        rec_m<D>(rec[a][0], mm);
+        rec_m<D>(rec[a][1], mp);
         if (!SOLIDS || (fl[a][0] && fl[a][1])) {
 #pragma unroll
             for (int b = 0; b < D; ++b) J[b][a] = (mp[b] - mm[b]) * T(0.5);
         } else {
             bool f5[5] = {false, fl[a][0], true, fl[a][1], false};
-            Rec<T> r2[2];
+            T m2m[3] = {T(0), T(0), T(0)}, m2p[3] = {T(0), T(0), T(0)};
             if (fl[a][1] && !fl[a][0]) {
-                const int64_t p2 = axis_neighbor(g, x, y, z, a, 2);
+                const uint32_t p2 = nb.axis(g, a, 2);
                 f5[4] = !mask[p2];
-                if (f5[4]) r2[1] = load_rec<D>(rho, w, eps, g, p2);
+                if (f5[4]) rec_m<D>(load_rec<D>(rho, w, eps, g.N, p2), m2p);
             }
             if (fl[a][0] && !fl[a][1]) {
-                const int64_t m2 = axis_neighbor(g, x, y, z, a, -2);
+                const uint32_t m2 = nb.axis(g, a, -2);
                 f5[0] = !mask[m2];
-                if (f5[0]) r2[0] = load_rec<D>(rho, w, eps, g, m2);
+                if (f5[0]) rec_m<D>(load_rec<D>(rho, w, eps, g.N, m2), m2m);
             }
 #pragma unroll
             for (int b = 0; b < D; ++b) {
-                T v5[5];
-                v5[0] = f5[0] ? (r2[0].r * r2[0].w[b]) / r2[0].e : T(0);
-                v5[1] = mm[b];
-                v5[2] = mo[b];
-                v5[3] = mp[b];
-                v5[4] = f5[4] ? (r2[1].r * r2[1].w[b]) / r2[1].e : T(0);
+                const T v5[5] = {m2m[b], mm[b], mo[b], mp[b], m2p[b]};
                 J[b][a] = deriv_rule(v5, f5);
             }
         }
@@ -318,44 +405,26 @@ __device__ __forceinline__ void delta_nu(const T *__restrict__ rho, const T *__r
     }
 }
 
-// Load the own record and the 2D axis neighbours with their fluid flags.
-template <int D, typename T, bool SOLIDS>
-__device__ __forceinline__ void load_stencil(const T *__restrict__ rho, const T *__restrict__ w,
-                                             const T *__restrict__ eps,
-                                             const uint8_t *__restrict__ mask, const Grid &g,
-                                             int x, int y, int z, Rec<T> nb[3][2],
-                                             bool fl[3][2]) {
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int64_t m = axis_neighbor(g, x, y, z, a, s ? 1 : -1);
-            nb[a][s] = load_rec<D>(rho, w, eps, g, m);
-            fl[a][s] = SOLIDS ? !mask[m] : true;
-        }
-    }
-}
-
 // Derivative along axis a of a scalar built from a record (Phi^ext's flux, or v_a).
 template <int D, typename T, bool SOLIDS, typename F>
 __device__ __forceinline__ T record_deriv(const T *__restrict__ rho, const T *__restrict__ w,
                                           const T *__restrict__ eps,
-                                          const uint8_t *__restrict__ mask, const Grid &g, int x,
-                                          int y, int z, int a, const Rec<T> &own,
-                                          const Rec<T> nb[3][2], const bool fl[3][2], F fn) {
-    const T vm = fn(nb[a][0]), vp = fn(nb[a][1]);
+                                          const uint8_t *__restrict__ mask, const Grid &g,
+                                          const Nbr<D> &nb, int a, const Rec<T> &own,
+                                          const Rec<T> rec[3][2], const bool fl[3][2], F fn) {
+    const T vm = fn(rec[a][0]), vp = fn(rec[a][1]);
     if (!SOLIDS || (fl[a][0] && fl[a][1])) return (vp - vm) * T(0.5);
     bool f5[5] = {false, fl[a][0], true, fl[a][1], false};
     T v5[5] = {T(0), vm, fn(own), vp, T(0)};
     if (fl[a][1] && !fl[a][0]) {
-        const int64_t p2 = axis_neighbor(g, x, y, z, a, 2);
+        const uint32_t p2 = nb.axis(g, a, 2);
         f5[4] = !mask[p2];
-        if (f5[4]) v5[4] = fn(load_rec<D>(rho, w, eps, g, p2));
+        if (f5[4]) v5[4] = fn(load_rec<D>(rho, w, eps, g.N, p2));
     }
     if (fl[a][0] && !fl[a][1]) {
-        const int64_t m2 = axis_neighbor(g, x, y, z, a, -2);
+        const uint32_t m2 = nb.axis(g, a, -2);
         f5[0] = !mask[m2];
-        if (f5[0]) v5[0] = fn(load_rec<D>(rho, w, eps, g, m2));
+        if (f5[0]) v5[0] = fn(load_rec<D>(rho, w, eps, g.N, m2));
     }
     return deriv_rule(v5, f5);
 }
@@ -369,37 +438,37 @@ __device__ __forceinline__ void forcing_args(const T *__restrict__ rho, const T 
                                              const T *__restrict__ muD,
                                              const T *__restrict__ muF,
                                              const uint8_t *__restrict__ mask, const Grid &g,
-                                             const Phys<T> &ph, int x, int y, int z, int64_t n,
-                                             Rec<T> &own, Visc<T> &vs, T xi[3], T P[3], T xs[3],
-                                             T Ps[3]) {
-    own = load_rec<D>(rho, v, eps, g, n);
-    Rec<T> nb[3][2];
+                                             const Phys<T> &ph, const Nbr<D> &nb, Rec<T> &own,
+                                             Visc<T> &vs, T xi[3], T P[3], T xs[3], T Ps[3]) {
+    const uint32_t n = nb.self();
+    own = load_rec<D>(rho, v, eps, g.N, n);
+    Rec<T> rec[3][2];
     bool fl[3][2];
-    load_stencil<D, T, SOLIDS>(rho, v, eps, mask, g, x, y, z, nb, fl);
+    load_stencil<D, T, SOLIDS>(rho, v, eps, mask, g, nb, rec, fl);
     T ge[3], H[3][3];
-    porosity_derivatives<D>(eps, g, x, y, z, own.e, ge, H);
+    porosity_derivatives<D>(eps, nb, own.e, ge, H);
     vs = viscosity(ph, own.e);
     T dm[3] = {T(0), T(0), T(0)};
-    delta_nu<D, T, SOLIDS>(rho, v, eps, mask, g, x, y, z, own, nb, fl, ge, H, vs, dm);
+    delta_nu<D, T, SOLIDS>(rho, v, eps, mask, g, nb, own, rec, fl, ge, H, vs, dm);
     T s = T(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) s = s + own.w[a] * own.w[a];
-    const T vm = sqrt(s);
-    const T md = muD[n], mf = muF[n];
+    const T vm = sq(s);
+    const T md = ld(muD, n), mf = ld(muF, n);
     T acc[3];
 #pragma unroll
     for (int a = 0; a < D; ++a)
         acc[a] = (((own.e * ph.b[a] - md * own.w[a]) - (mf * vm) * own.w[a]) + ph.RT * ge[a]) +
-                 dm[a] / own.r;
+                 dv(dm[a], own.r);
     T phx[3];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         const T omr = ph.omr;
         auto gext = [a, omr](const Rec<T> &q) {
             const T va = q.w[a];
-            return (q.r * va) * omr - (q.r * ((va * va) * va)) / (q.e * q.e);
+            return (q.r * va) * omr - dv(q.r * ((va * va) * va), q.e * q.e);
         };
-        phx[a] = record_deriv<D, T, SOLIDS>(rho, v, eps, mask, g, x, y, z, a, own, nb, fl, gext);
+        phx[a] = record_deriv<D, T, SOLIDS>(rho, v, eps, mask, g, nb, a, own, rec, fl, gext);
     }
     T pheta = T(0);
     if (ph.eta_on) {
@@ -407,17 +476,17 @@ __device__ __forceinline__ void forcing_args(const T *__restrict__ rho, const T 
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             auto va = [a](const Rec<T> &q) { return q.w[a]; };
-            divv = divv + record_deriv<D, T, SOLIDS>(rho, v, eps, mask, g, x, y, z, a, own, nb,
-                                                       fl, va);
+            divv = divv + record_deriv<D, T, SOLIDS>(rho, v, eps, mask, g, nb, a, own, rec, fl, va);
         }
-        pheta = ((own.r * ph.RT) * (ph.two_over_D - ph.eta / vs.nu)) * divv;
+        pheta = ((own.r * ph.RT) * (ph.two_over_D - dv(ph.eta, vs.nu))) * divv;
     }
+    const T ier = dv(T(1), own.e * own.r);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        xi[a] = own.w[a] / own.e;
+        xi[a] = dv(own.w[a], own.e);
         P[a] = xi[a] * xi[a] + ph.RT;
-        xs[a] = (own.w[a] + acc[a]) / own.e;
-        Ps[a] = (xs[a] * xs[a] + ph.RT) + (T(1) / (own.e * own.r)) * (phx[a] + pheta);
+        xs[a] = dv(own.w[a] + acc[a], own.e);
+        Ps[a] = (xs[a] * xs[a] + ph.RT) + ier * (phx[a] + pheta);
     }
 }
 
@@ -455,14 +524,45 @@ struct ProductForm {
 };
 
 // ------------------------------------------------------------------------------------------
-// Kernels.  Launch: block (64, 4, 1) over (x, y), grid z = cells along z.
+// Kernels, one thread per cell.  A workgroup of 256 threads owns a tx x ty x 1 tile
+// (tx * ty = 256, tx = 256 for rows of 192 cells or more, so that the x-shifted accesses of the
+// swapped AA phase stay inside one workgroup); tiles are numbered x-fastest and handed to the
+// eight XCDs in contiguous ranges (workgroup w runs on XCD w mod 8), so tiles that share
+// neighbour data also share an L2.  Launch: block 256, grid 8 * per workgroups with
+// per = ceil(tiles / 8).
 // ------------------------------------------------------------------------------------------
-#define LBM_CELL_PROLOGUE                                             \
-    const int x = blockIdx.x * 64 + threadIdx.x;                     \
-    const int y = blockIdx.y * 4 + threadIdx.y;                      \
-    const int z = blockIdx.z;                                        \
-    if (x >= g.nx || y >= g.ny) return;                              \
-    const int64_t n = cell_index(g, x, y, z);
+struct Tiling {
+    int tx, ty;     // tile shape, tx * ty = 256
+    int ntx, nty, ntz;
+    uint32_t per;   // tiles per XCD
+};
+
+__device__ __forceinline__ bool tile_cell(const Grid &g, const Tiling &tl, int &x, int &y,
+                                          int &z) {
+    const uint32_t w = blockIdx.x;
+#ifdef LBM_LINEAR_TILES
+    const uint32_t t = w;
+#else
+    const uint32_t t = (w & 7u) * tl.per + (w >> 3);
+#endif
+    const uint32_t nt = (uint32_t)tl.ntx * (uint32_t)tl.nty * (uint32_t)tl.ntz;
+    if (t >= nt) return false;
+    const uint32_t tx = t % (uint32_t)tl.ntx;
+    const uint32_t r = t / (uint32_t)tl.ntx;
+    const uint32_t ty = r % (uint32_t)tl.nty;
+    const uint32_t tz = r / (uint32_t)tl.nty;
+    x = (int)(tx * (uint32_t)tl.tx + threadIdx.x % (uint32_t)tl.tx);
+    y = (int)(ty * (uint32_t)tl.ty + threadIdx.x / (uint32_t)tl.tx);
+    z = (int)tz;
+    return x < g.nx && y < g.ny;
+}
+
+#define LBM_CELL_PROLOGUE(D)                                         \
+    int x, y, z;                                                     \
+    if (!tile_cell(g, tl, x, y, z)) return;                          \
+    Nbr<D> nb;                                                       \
+    nb.init(g, x, y, z);                                             \
+    const uint32_t n = nb.self();
 
 // Pass one: density (transformed_density_moment), transformed momentum
 // (transformed_momentum_moment), v^(0) (v_(0)) and the closed-form drag solve v^(1)
@@ -474,21 +574,21 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f,
                                                  const T *__restrict__ muF,
                                                  const uint8_t *__restrict__ mask,
                                                  T *__restrict__ rho_out, T *__restrict__ v1_out,
-                                                 Grid g, Phys<T> ph) {
-    LBM_CELL_PROLOGUE
+                                                 Grid g, Tiling tl, Phys<T> ph) {
+    LBM_CELL_PROLOGUE(D)
     using L = Lat<D>;
     if constexpr (SOLIDS) {
         if (mask[n]) {
-            rho_out[n] = T(0);
+            *at(rho_out, n) = T(0);
 #pragma unroll
-            for (int a = 0; a < D; ++a) v1_out[(int64_t)a * g.N + n] = T(0);
+            for (int a = 0; a < D; ++a) *at(plane(v1_out, a, g.N), n) = T(0);
             return;
         }
     }
     T fi[L::Q];
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, g, x, y, z, n);
+        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
     });
     T S = T(0), Pi[3] = {T(0), T(0), T(0)};
     unroll<0, L::Q>([&](auto ii) {
@@ -500,25 +600,25 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f,
             else if constexpr (L::c[i][a] == -1) Pi[a] = Pi[a] - fi[i];
         });
     });
-    const T e = eps[n];
-    const T rho = S / e;
+    const T e = ld(eps, n);
+    const T rho = dv(S, e);
     T v0[3];
     unroll<0, D>([&](auto ia) {
         constexpr int a = decltype(ia)::value;
-        const T ge = (eps[axis_neighbor(g, x, y, z, a, 1)] - eps[axis_neighbor(g, x, y, z, a, -1)]) *
-                     T(0.5);
-        v0[a] = Pi[a] / rho + T(0.5) * (e * ph.b[a] + ph.RT * ge);
+        constexpr int px = a == 0, py = a == 1, pz = a == 2;
+        const T ge = (ld(eps, nb.at(px, py, pz)) - ld(eps, nb.at(-px, -py, -pz))) * T(0.5);
+        v0[a] = dv(Pi[a], rho) + T(0.5) * (e * ph.b[a] + ph.RT * ge);
     });
-    const T c1 = T(1) + T(0.5) * muD[n];
-    const T c2 = T(0.5) * muF[n];
+    const T c1 = T(1) + T(0.5) * ld(muD, n);
+    const T c2 = T(0.5) * ld(muF, n);
     T s = T(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) s = s + v0[a] * v0[a];
-    const T vm = sqrt(s);
-    const T den = c1 + sqrt(c1 * c1 + (T(4) * c2) * vm);
-    rho_out[n] = rho;
+    const T vm = sq(s);
+    const T den = c1 + sq(c1 * c1 + (T(4) * c2) * vm);
+    *at(rho_out, n) = rho;
 #pragma unroll
-    for (int a = 0; a < D; ++a) v1_out[(int64_t)a * g.N + n] = (T(2) * v0[a]) / den;
+    for (int a = 0; a < D; ++a) *at(plane(v1_out, a, g.N), n) = dv(T(2) * v0[a], den);
 }
 
 // Velocity correction (v_final): v = v^(1) + Delta_nu(rho v^(1) / eps) / (2 rho).
@@ -527,27 +627,28 @@ __global__ __launch_bounds__(256) void k_vcorrect(const T *__restrict__ rho,
                                                   const T *__restrict__ v1,
                                                   const T *__restrict__ eps,
                                                   const uint8_t *__restrict__ mask,
-                                                  T *__restrict__ v_out, Grid g, Phys<T> ph) {
-    LBM_CELL_PROLOGUE
+                                                  T *__restrict__ v_out, Grid g, Tiling tl,
+                                                  Phys<T> ph) {
+    LBM_CELL_PROLOGUE(D)
     if constexpr (SOLIDS) {
         if (mask[n]) {
 #pragma unroll
-            for (int a = 0; a < D; ++a) v_out[(int64_t)a * g.N + n] = T(0);
+            for (int a = 0; a < D; ++a) *at(plane(v_out, a, g.N), n) = T(0);
             return;
         }
     }
-    const Rec<T> own = load_rec<D>(rho, v1, eps, g, n);
-    Rec<T> nb[3][2];
+    const Rec<T> own = load_rec<D>(rho, v1, eps, g.N, n);
+    Rec<T> rec[3][2];
     bool fl[3][2];
-    load_stencil<D, T, SOLIDS>(rho, v1, eps, mask, g, x, y, z, nb, fl);
+    load_stencil<D, T, SOLIDS>(rho, v1, eps, mask, g, nb, rec, fl);
     T ge[3], H[3][3];
-    porosity_derivatives<D>(eps, g, x, y, z, own.e, ge, H);
+    porosity_derivatives<D>(eps, nb, own.e, ge, H);
     const Visc<T> vs = viscosity(ph, own.e);
     T dn[3];
-    delta_nu<D, T, SOLIDS>(rho, v1, eps, mask, g, x, y, z, own, nb, fl, ge, H, vs, dn);
+    delta_nu<D, T, SOLIDS>(rho, v1, eps, mask, g, nb, own, rec, fl, ge, H, vs, dn);
 #pragma unroll
     for (int a = 0; a < D; ++a)
-        v_out[(int64_t)a * g.N + n] = own.w[a] + dn[a] / (T(2) * own.r);
+        *at(plane(v_out, a, g.N), n) = own.w[a] + dv(dn[a], T(2) * own.r);
 }
 
 // Forcing, collision (dicrete_scheme, momentum_rate with lambda = dt = 1) and streaming with
@@ -560,34 +661,36 @@ __global__ __launch_bounds__(256) void k_collide(T *__restrict__ f, const T *__r
                                                  const T *__restrict__ muD,
                                                  const T *__restrict__ muF,
                                                  const uint8_t *__restrict__ mask, Grid g,
-                                                 Phys<T> ph) {
-    LBM_CELL_PROLOGUE
+                                                 Tiling tl, Phys<T> ph) {
+    LBM_CELL_PROLOGUE(D)
     using L = Lat<D>;
     if constexpr (SOLIDS) {
         if (mask[n]) return;
     }
-    T fi[L::Q];
-    unroll<0, L::Q>([&](auto ii) {
-        constexpr int i = decltype(ii)::value;
-        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, g, x, y, z, n);
-    });
     Rec<T> own;
     Visc<T> vs;
     T xi[3], P[3], xs[3], Ps[3];
-    forcing_args<D, T, SOLIDS>(rho, v, eps, muD, muF, mask, g, ph, x, y, z, n, own, vs, xi, P,
-                               xs, Ps);
+    forcing_args<D, T, SOLIDS>(rho, v, eps, muD, muF, mask, g, ph, nb, own, vs, xi, P, xs, Ps);
     const T er = own.e * own.r;
     ProductForm<D, T> peq, pst;
     peq.init(er, xi, P);
     pst.init(er, xs, Ps);
     const T two_beta = T(2) * vs.beta;
     const T omb = T(1) - vs.beta;
+    // The populations are loaded only now, after the forcing arguments: fewer registers are
+    // live across the stencil work, so more waves share each SIMD.
+    __builtin_amdgcn_sched_barrier(0);
+    T fi[L::Q];
+    unroll<0, L::Q>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
+    });
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
         const T feq = peq.template at<i>();
         const T fst = pst.template at<i>();
         const T fpc = (fi[i] + two_beta * (feq - fi[i])) + omb * (fst - feq);
-        store_pop<D, SOLIDS, PH, i>(f, mask, g, x, y, z, n, fpc);
+        store_pop<D, SOLIDS, PH, i>(f, mask, g, nb, fpc);
     });
 }
 
@@ -600,14 +703,14 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ f, const T *__rest
                                               const T *__restrict__ muD,
                                               const T *__restrict__ muF,
                                               const uint8_t *__restrict__ mask, Grid g,
-                                              Phys<T> ph) {
-    LBM_CELL_PROLOGUE
+                                              Tiling tl, Phys<T> ph) {
+    LBM_CELL_PROLOGUE(D)
     using L = Lat<D>;
     if constexpr (SOLIDS) {
         if (mask[n]) {
             unroll<0, L::Q>([&](auto ii) {
                 constexpr int i = decltype(ii)::value;
-                f[(int64_t)i * g.N + n] = T(0);
+                *at(plane(f, i, g.N), n) = T(0);
             });
             return;
         }
@@ -615,15 +718,14 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ f, const T *__rest
     Rec<T> own;
     Visc<T> vs;
     T xi[3], P[3], xs[3], Ps[3];
-    forcing_args<D, T, SOLIDS>(rho, v, eps, muD, muF, mask, g, ph, x, y, z, n, own, vs, xi, P,
-                               xs, Ps);
+    forcing_args<D, T, SOLIDS>(rho, v, eps, muD, muF, mask, g, ph, nb, own, vs, xi, P, xs, Ps);
     const T er = own.e * own.r;
     ProductForm<D, T> peq, pst;
     peq.init(er, xi, P);
     pst.init(er, xs, Ps);
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        f[(int64_t)i * g.N + n] = T(1.5) * peq.template at<i>() - T(0.5) * pst.template at<i>();
+        *at(plane(f, i, g.N), n) = T(1.5) * peq.template at<i>() - T(0.5) * pst.template at<i>();
     });
 }
 
@@ -655,20 +757,21 @@ __global__ __launch_bounds__(256) void k_fill_init(const double *__restrict__ rh
     const bool solid = mask && mask[n];
     rho[n] = solid ? T(0) : (T)(rho_in ? rho_in[n] : rho0);
 #pragma unroll
-    for (int a = 0; a < D; ++a) v[(int64_t)a * N + n] = solid ? T(0) : (T)(v_in ? v_in[(int64_t)a * N + n] : 0.0);
+    for (int a = 0; a < D; ++a)
+        v[(int64_t)a * N + n] = solid ? T(0) : (T)(v_in ? v_in[(int64_t)a * N + n] : 0.0);
 }
 
 // Natural-layout copy of the current populations (0 on solid cells).
 template <int D, typename T, bool SOLIDS, int PH, typename O>
 __global__ __launch_bounds__(256) void k_export(const T *__restrict__ f,
                                                 const uint8_t *__restrict__ mask,
-                                                O *__restrict__ out, Grid g) {
-    LBM_CELL_PROLOGUE
+                                                O *__restrict__ out, Grid g, Tiling tl) {
+    LBM_CELL_PROLOGUE(D)
     using L = Lat<D>;
     const bool solid = SOLIDS && mask[n];
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        out[(int64_t)i * g.N + n] = solid ? O(0) : (O)load_pop<D, SOLIDS, PH, i>(f, mask, g, x, y, z, n);
+        out[(int64_t)i * g.N + n] = solid ? O(0) : (O)load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
     });
 }
 
@@ -726,16 +829,18 @@ __global__ __launch_bounds__(256) void k_stats(const T *__restrict__ f, const T 
                                                double *__restrict__ partial, Grid g) {
     using L = Lat<D>;
     double acc[kStatsSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N; n += stride) {
+    const uint32_t stride = gridDim.x * 256u;
+    for (uint32_t n = blockIdx.x * 256u + threadIdx.x; n < g.N; n += stride) {
         if (SOLIDS && mask[n]) continue;
-        const int x = (int)(n % g.nx);
-        const int y = (int)((n / g.nx) % g.ny);
-        const int z = (int)(n / ((int64_t)g.nx * g.ny));
+        const int x = (int)(n % (uint32_t)g.nx);
+        const int y = (int)((n / (uint32_t)g.nx) % (uint32_t)g.ny);
+        const int z = (int)(n / ((uint32_t)g.nx * (uint32_t)g.ny));
+        Nbr<D> nb;
+        nb.init(g, x, y, z);
         T cell = T(0);
         unroll<0, L::Q>([&](auto ii) {
             constexpr int i = decltype(ii)::value;
-            cell = cell + load_pop<D, SOLIDS, PH, i>(f, mask, g, x, y, z, n);
+            cell = cell + load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
         });
         const double cm = (double)cell;
         acc[0] += cm;
@@ -744,13 +849,13 @@ __global__ __launch_bounds__(256) void k_stats(const T *__restrict__ f, const T 
         const double r = (double)rho[n];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const double va = (double)v[(int64_t)a * g.N + n];
-            const double sa = (double)vsnap[(int64_t)a * g.N + n];
+            const double va = (double)v[(size_t)a * g.N + n];
+            const double sa = (double)vsnap[(size_t)a * g.N + n];
             acc[1 + a] += r * va;
             vv += va * va;
             acc[5] += (va - sa) * (va - sa);
             acc[6] += sa * sa;
-            vsnap[(int64_t)a * g.N + n] = v[(int64_t)a * g.N + n];
+            vsnap[(size_t)a * g.N + n] = v[(size_t)a * g.N + n];
         }
         if (!isfinite(vv)) acc[7] += 1.0;
         else acc[4] = fmax(acc[4], sqrt(vv));
