@@ -49,7 +49,7 @@ int fail(int code, const char *fmt, ...) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t f, eps, muD, muF, mask, rho, v1, v, vsnap, part, res, total;
+    size_t f, eps, muD, muF, mask, m1, m2, vsnap, part, res, total;
 };
 
 Layout make_layout(int Q, int D, size_t N, size_t s, bool solids) {
@@ -65,9 +65,8 @@ Layout make_layout(int Q, int D, size_t N, size_t s, bool solids) {
     L.muD = take(N * s);
     L.muF = take(N * s);
     L.mask = solids ? take(N) : 0;
-    L.rho = take(N * s);
-    L.v1 = take((size_t)D * N * s);
-    L.v = take((size_t)D * N * s);
+    L.m1 = take(4 * N * s);  // packed (rho, v^(1)) records
+    L.m2 = take(4 * N * s);  // packed (rho, v) records
     L.vsnap = take((size_t)D * N * s);
     L.part = take((size_t)lbm::kStatsBlocks * lbm::kStatsSlots * sizeof(double));
     L.res = take(lbm::kStatsSlots * sizeof(double));
@@ -91,7 +90,7 @@ struct lbm_solver {
     int phase;  // AA-pattern layout: 0 natural, 1 swapped
     double RT, nu_f, nu_eff_ref, eta_eff, b[3];
     int nu_eff_pow;
-    lbm::Tiling tiles;  // 64 x 4 x 1 cell tiles in XCD-contiguous order
+    lbm::Tiling tiles;  // 256-cell tiles, blocked, in XCD-contiguous ranges
 };
 
 namespace {
@@ -122,7 +121,16 @@ lbm::Tiling make_tiling(int nx, int ny, int nz) {
     t.ntx = (nx + t.tx - 1) / t.tx;
     t.nty = (ny + t.ty - 1) / t.ty;
     t.ntz = nz;
-    const int64_t nt = (int64_t)t.ntx * t.nty * t.ntz;
+    int by = 64, bz = 4;  // tile rows per block along y and z (measured best on 256^3)
+    if (const char *e = std::getenv("LBM_TILE_BLOCK")) {  // "BYxBZ", for tuning sweeps
+        int a = 0, b = 0;
+        if (std::sscanf(e, "%dx%d", &a, &b) == 2 && a >= 1 && b >= 1) { by = a; bz = b; }
+    }
+    t.by = std::min(by, t.nty);
+    t.bz = std::min(bz, t.ntz);
+    t.nby = (t.nty + t.by - 1) / t.by;
+    t.nbz = (t.ntz + t.bz - 1) / t.bz;
+    const int64_t nt = (int64_t)t.ntx * t.by * t.bz * t.nby * t.nbz;
     t.per = (uint32_t)((nt + 7) / 8);
     return t;
 }
@@ -145,24 +153,23 @@ void launch_moments(const lbm_solver *h) {
     hipLaunchKernelGGL((lbm::k_moments<D, T, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
                        ws_ptr<const T>(h, h->L.f), ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
-                       ws_ptr<T>(h, h->L.rho), ws_ptr<T>(h, h->L.v1), grid_of(h), h->tiles, ph);
+                       ws_ptr<lbm::P4<T>>(h, h->L.m1), grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, bool S>
 void launch_vcorrect(const lbm_solver *h) {
     auto ph = phys_of<T>(h);
     hipLaunchKernelGGL((lbm::k_vcorrect<D, T, S>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<const T>(h, h->L.rho), ws_ptr<const T>(h, h->L.v1),
-                       ws_ptr<const T>(h, h->L.eps), mask_ptr(h), ws_ptr<T>(h, h->L.v),
-                       grid_of(h), h->tiles, ph);
+                       ws_ptr<const lbm::P4<T>>(h, h->L.m1), ws_ptr<const T>(h, h->L.eps),
+                       mask_ptr(h), ws_ptr<lbm::P4<T>>(h, h->L.m2), grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, bool S, int PH>
 void launch_collide(const lbm_solver *h) {
     auto ph = phys_of<T>(h);
     hipLaunchKernelGGL((lbm::k_collide<D, T, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<T>(h, h->L.f), ws_ptr<const T>(h, h->L.rho),
-                       ws_ptr<const T>(h, h->L.v), ws_ptr<const T>(h, h->L.eps),
+                       ws_ptr<T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m2),
+                       ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
                        grid_of(h), h->tiles, ph);
 }
@@ -171,8 +178,8 @@ template <int D, typename T, bool S>
 void launch_init(const lbm_solver *h) {
     auto ph = phys_of<T>(h);
     hipLaunchKernelGGL((lbm::k_init<D, T, S>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<T>(h, h->L.f), ws_ptr<const T>(h, h->L.rho),
-                       ws_ptr<const T>(h, h->L.v), ws_ptr<const T>(h, h->L.eps),
+                       ws_ptr<T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m2),
+                       ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
                        grid_of(h), h->tiles, ph);
 }
@@ -186,8 +193,8 @@ void launch_export(const lbm_solver *h, O *out) {
 template <int D, typename T, bool S, int PH>
 void launch_stats(const lbm_solver *h) {
     hipLaunchKernelGGL((lbm::k_stats<D, T, S, PH>), dim3(lbm::kStatsBlocks), dim3(256), 0,
-                       h->stream, ws_ptr<const T>(h, h->L.f), ws_ptr<const T>(h, h->L.rho),
-                       ws_ptr<const T>(h, h->L.v), ws_ptr<T>(h, h->L.vsnap), mask_ptr(h),
+                       h->stream, ws_ptr<const T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m2),
+                       ws_ptr<T>(h, h->L.vsnap), mask_ptr(h),
                        ws_ptr<double>(h, h->L.part), grid_of(h));
 }
 
@@ -250,7 +257,7 @@ struct ExportPass {
     }
 };
 
-// Moments of the current state into the internal rho, v1, v buffers.
+// Moments of the current state into the internal packed (rho, v^(1)) and (rho, v) records.
 int current_moments(lbm_solver *h) {
     dispatch(h, MomentsPass{h});
     LAUNCH_CHECK();
@@ -279,9 +286,10 @@ int validate_shape(const lbm_params *p, int *D, int *Q, size_t *s, int64_t *N) {
     if (p->ny > 4 * 65535 || p->nz > 65535)
         return fail(LBM_ERR_UNSUPPORTED, "ny must be <= 262140 and nz <= 65535");
     *N = (int64_t)p->nx * p->ny * p->nz;
-    // every array plane is addressed with 32-bit byte offsets
-    if ((uint64_t)*N * *s >= ((uint64_t)1 << 32))
-        return fail(LBM_ERR_UNSUPPORTED, "%lld cells of %zu bytes exceed 4 GiB per field",
+    // every array plane is addressed with 32-bit byte offsets; the largest plane is the packed
+    // moment record field, four values per cell
+    if ((uint64_t)*N * 4 * *s >= ((uint64_t)1 << 32))
+        return fail(LBM_ERR_UNSUPPORTED, "%lld cells of 4 x %zu-byte moment records exceed 4 GiB",
                     (long long)*N, *s);
     return LBM_OK;
 }
@@ -428,11 +436,11 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     }
     const uint8_t *mk = mask_ptr(h);
     if (h->storage == LBM_F64) {
-        if (D == 2) hipLaunchKernelGGL((lbm::k_fill_init<2, double>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<double>(h, L.rho), ws_ptr<double>(h, L.v), N, p->rho0);
-        else hipLaunchKernelGGL((lbm::k_fill_init<3, double>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<double>(h, L.rho), ws_ptr<double>(h, L.v), N, p->rho0);
+        if (D == 2) hipLaunchKernelGGL((lbm::k_fill_init<2, double>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<lbm::P4<double>>(h, L.m2), N, p->rho0);
+        else hipLaunchKernelGGL((lbm::k_fill_init<3, double>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<lbm::P4<double>>(h, L.m2), N, p->rho0);
     } else {
-        if (D == 2) hipLaunchKernelGGL((lbm::k_fill_init<2, float>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<float>(h, L.rho), ws_ptr<float>(h, L.v), N, p->rho0);
-        else hipLaunchKernelGGL((lbm::k_fill_init<3, float>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<float>(h, L.rho), ws_ptr<float>(h, L.v), N, p->rho0);
+        if (D == 2) hipLaunchKernelGGL((lbm::k_fill_init<2, float>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<lbm::P4<float>>(h, L.m2), N, p->rho0);
+        else hipLaunchKernelGGL((lbm::k_fill_init<3, float>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<lbm::P4<float>>(h, L.m2), N, p->rho0);
     }
     if ((e = hipGetLastError()) != hipSuccess)
         return cleanup(fail(LBM_ERR_HIP, "initial-field kernel failed: %s", hipGetErrorString(e)));
@@ -517,8 +525,8 @@ LBM_API int lbm_moments(lbm_solver *h, void *rho_dev, void *v_dev, int dtype, in
     const int64_t N = h->N;
 #define LBM_OUT(DD, TT, OO)                                                                      \
     hipLaunchKernelGGL((lbm::k_moments_out<DD, TT, OO>), flat_grid(N), dim3(256), 0, h->stream, \
-                       ws_ptr<const TT>(h, h->L.rho), ws_ptr<const TT>(h, h->L.v),              \
-                       ws_ptr<const TT>(h, h->L.eps), (OO *)rho_dev, (OO *)v_dev, N, velocity_kind)
+                       ws_ptr<const lbm::P4<TT>>(h, h->L.m2), ws_ptr<const TT>(h, h->L.eps),    \
+                       (OO *)rho_dev, (OO *)v_dev, N, velocity_kind)
     if (h->D == 2) {
         if (h->storage == LBM_F64) { if (dtype == LBM_DTYPE_F64) LBM_OUT(2, double, double); else LBM_OUT(2, double, float); }
         else { if (dtype == LBM_DTYPE_F64) LBM_OUT(2, float, double); else LBM_OUT(2, float, float); }

@@ -19,8 +19,8 @@
 // written back to slot (opp(i), n).  Every thread reads and writes the same set of slots, so
 // the update is race-free in place.  Every axis wraps periodically.
 //
-// Addressing: every array plane holds fewer than 2^32 bytes, so a thread addresses it with a
-// 32-bit byte offset added to a uniform 64-bit base (the scalar-base + vector-offset form of
+// Addressing: every array plane (one population, one scalar field, or the packed four-value
+// moment records) holds fewer than 2^32 bytes, so a thread addresses it with a 32-bit byte offset added to a uniform 64-bit base (the scalar-base + vector-offset form of
 // the global memory instructions).  The periodic neighbours of a cell are precomputed once
 // per thread (three x positions, nine y/z row bases).
 //
@@ -73,7 +73,7 @@ __device__ __forceinline__ void unroll(F &&f) {
 
 struct Grid {
     int nx, ny, nz;
-    uint32_t N;  // cells; N * sizeof(T) < 2^32
+    uint32_t N;  // cells; 4 N sizeof(T) < 2^32
 };
 
 template <typename T>
@@ -296,6 +296,31 @@ __device__ __forceinline__ T deriv_rule(const T v[5], const bool fl[5]) {
     return T(0);
 }
 
+// Moment fields are stored packed per cell, (rho, w_x, w_y, w_z) in one 16-byte (FP32) or
+// 32-byte (FP64) record, so a stencil neighbour costs one vector load plus its porosity.
+template <typename T>
+struct Packed;
+template <>
+struct Packed<float> {
+    using type = float4;
+};
+template <>
+struct Packed<double> {
+    using type = double4;
+};
+template <typename T>
+using P4 = typename Packed<T>::type;
+
+template <typename T>
+__device__ __forceinline__ P4<T> pack(T r, T a, T b, T c) {
+    P4<T> q;
+    q.x = r;
+    q.y = a;
+    q.z = b;
+    q.w = c;
+    return q;
+}
+
 // Moment record of one cell: intrinsic density, porosity, velocity.
 template <typename T>
 struct Rec {
@@ -303,13 +328,15 @@ struct Rec {
 };
 
 template <int D, typename T>
-__device__ __forceinline__ Rec<T> load_rec(const T *__restrict__ rho, const T *__restrict__ w,
-                                           const T *__restrict__ eps, uint32_t N, uint32_t m) {
+__device__ __forceinline__ Rec<T> load_rec(const P4<T> *__restrict__ m,
+                                           const T *__restrict__ eps, uint32_t idx) {
+    const P4<T> q4 = ld(m, idx);
     Rec<T> q;
-    q.r = ld(rho, m);
-    q.e = ld(eps, m);
-#pragma unroll
-    for (int b = 0; b < D; ++b) q.w[b] = ld(plane(w, b, N), m);
+    q.r = q4.x;
+    q.w[0] = q4.y;
+    q.w[1] = q4.z;
+    q.w[2] = q4.w;
+    q.e = ld(eps, idx);
     return q;
 }
 
@@ -322,7 +349,7 @@ __device__ __forceinline__ void rec_m(const Rec<T> &q, T m[3]) {
 
 // Load the axis neighbours of the cell with their fluid flags.
 template <int D, typename T, bool SOLIDS>
-__device__ __forceinline__ void load_stencil(const T *__restrict__ rho, const T *__restrict__ w,
+__device__ __forceinline__ void load_stencil(const P4<T> *__restrict__ mom,
                                              const T *__restrict__ eps,
                                              const uint8_t *__restrict__ mask, const Grid &g,
                                              const Nbr<D> &nb, Rec<T> rec[3][2], bool fl[3][2]) {
@@ -331,7 +358,7 @@ __device__ __forceinline__ void load_stencil(const T *__restrict__ rho, const T 
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const uint32_t m = nb.axis(g, a, s ? 1 : -1);
-            rec[a][s] = load_rec<D>(rho, w, eps, g.N, m);
+            rec[a][s] = load_rec<D>(mom, eps, m);
             fl[a][s] = SOLIDS ? !mask[m] : true;
         }
     }
@@ -342,7 +369,7 @@ __device__ __forceinline__ void load_stencil(const T *__restrict__ rho, const T 
 //   nu {[H + tr(H) I] m + (div m) grad eps + (grad m) grad eps}
 //     + nu' [|grad eps|^2 m + (m . grad eps) grad eps],   [(grad m) grad eps]_a = sum_b d_b m_a d_b eps.
 template <int D, typename T, bool SOLIDS>
-__device__ __forceinline__ void delta_nu(const T *__restrict__ rho, const T *__restrict__ w,
+__device__ __forceinline__ void delta_nu(const P4<T> *__restrict__ mom,
                                          const T *__restrict__ eps,
                                          const uint8_t *__restrict__ mask, const Grid &g,
                                          const Nbr<D> &nb, const Rec<T> &own,
@@ -366,12 +393,12 @@ __device__ __forceinline__ void delta_nu(const T *__restrict__ rho, const T *__r
             if (fl[a][1] && !fl[a][0]) {
                 const uint32_t p2 = nb.axis(g, a, 2);
                 f5[4] = !mask[p2];
-                if (f5[4]) rec_m<D>(load_rec<D>(rho, w, eps, g.N, p2), m2p);
+                if (f5[4]) rec_m<D>(load_rec<D>(mom, eps, p2), m2p);
             }
             if (fl[a][0] && !fl[a][1]) {
                 const uint32_t m2 = nb.axis(g, a, -2);
                 f5[0] = !mask[m2];
-                if (f5[0]) rec_m<D>(load_rec<D>(rho, w, eps, g.N, m2), m2m);
+                if (f5[0]) rec_m<D>(load_rec<D>(mom, eps, m2), m2m);
             }
 #pragma unroll
             for (int b = 0; b < D; ++b) {
@@ -407,7 +434,7 @@ __device__ __forceinline__ void delta_nu(const T *__restrict__ rho, const T *__r
 
 // Derivative along axis a of a scalar built from a record (Phi^ext's flux, or v_a).
 template <int D, typename T, bool SOLIDS, typename F>
-__device__ __forceinline__ T record_deriv(const T *__restrict__ rho, const T *__restrict__ w,
+__device__ __forceinline__ T record_deriv(const P4<T> *__restrict__ mom,
                                           const T *__restrict__ eps,
                                           const uint8_t *__restrict__ mask, const Grid &g,
                                           const Nbr<D> &nb, int a, const Rec<T> &own,
@@ -419,12 +446,12 @@ __device__ __forceinline__ T record_deriv(const T *__restrict__ rho, const T *__
     if (fl[a][1] && !fl[a][0]) {
         const uint32_t p2 = nb.axis(g, a, 2);
         f5[4] = !mask[p2];
-        if (f5[4]) v5[4] = fn(load_rec<D>(rho, w, eps, g.N, p2));
+        if (f5[4]) v5[4] = fn(load_rec<D>(mom, eps, p2));
     }
     if (fl[a][0] && !fl[a][1]) {
         const uint32_t m2 = nb.axis(g, a, -2);
         f5[0] = !mask[m2];
-        if (f5[0]) v5[0] = fn(load_rec<D>(rho, w, eps, g.N, m2));
+        if (f5[0]) v5[0] = fn(load_rec<D>(mom, eps, m2));
     }
     return deriv_rule(v5, f5);
 }
@@ -433,7 +460,7 @@ __device__ __forceinline__ T record_deriv(const T *__restrict__ rho, const T *__
 // acceleration (accel), Phi^ext (ex_corr), Phi^eta (eta_corr), then xi, P (xi_alpha_eq,
 // P_alpha_alpha_eq) and xi*, P* (xi_alpha_*, P_aa_*) with lambda = 1.
 template <int D, typename T, bool SOLIDS>
-__device__ __forceinline__ void forcing_args(const T *__restrict__ rho, const T *__restrict__ v,
+__device__ __forceinline__ void forcing_args(const P4<T> *__restrict__ mom,
                                              const T *__restrict__ eps,
                                              const T *__restrict__ muD,
                                              const T *__restrict__ muF,
@@ -441,15 +468,15 @@ __device__ __forceinline__ void forcing_args(const T *__restrict__ rho, const T 
                                              const Phys<T> &ph, const Nbr<D> &nb, Rec<T> &own,
                                              Visc<T> &vs, T xi[3], T P[3], T xs[3], T Ps[3]) {
     const uint32_t n = nb.self();
-    own = load_rec<D>(rho, v, eps, g.N, n);
+    own = load_rec<D>(mom, eps, n);
     Rec<T> rec[3][2];
     bool fl[3][2];
-    load_stencil<D, T, SOLIDS>(rho, v, eps, mask, g, nb, rec, fl);
+    load_stencil<D, T, SOLIDS>(mom, eps, mask, g, nb, rec, fl);
     T ge[3], H[3][3];
     porosity_derivatives<D>(eps, nb, own.e, ge, H);
     vs = viscosity(ph, own.e);
     T dm[3] = {T(0), T(0), T(0)};
-    delta_nu<D, T, SOLIDS>(rho, v, eps, mask, g, nb, own, rec, fl, ge, H, vs, dm);
+    delta_nu<D, T, SOLIDS>(mom, eps, mask, g, nb, own, rec, fl, ge, H, vs, dm);
     T s = T(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) s = s + own.w[a] * own.w[a];
@@ -468,7 +495,7 @@ __device__ __forceinline__ void forcing_args(const T *__restrict__ rho, const T 
             const T va = q.w[a];
             return (q.r * va) * omr - dv(q.r * ((va * va) * va), q.e * q.e);
         };
-        phx[a] = record_deriv<D, T, SOLIDS>(rho, v, eps, mask, g, nb, a, own, rec, fl, gext);
+        phx[a] = record_deriv<D, T, SOLIDS>(mom, eps, mask, g, nb, a, own, rec, fl, gext);
     }
     T pheta = T(0);
     if (ph.eta_on) {
@@ -476,7 +503,7 @@ __device__ __forceinline__ void forcing_args(const T *__restrict__ rho, const T 
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             auto va = [a](const Rec<T> &q) { return q.w[a]; };
-            divv = divv + record_deriv<D, T, SOLIDS>(rho, v, eps, mask, g, nb, a, own, rec, fl, va);
+            divv = divv + record_deriv<D, T, SOLIDS>(mom, eps, mask, g, nb, a, own, rec, fl, va);
         }
         pheta = ((own.r * ph.RT) * (ph.two_over_D - dv(ph.eta, vs.nu))) * divv;
     }
@@ -526,35 +553,37 @@ struct ProductForm {
 // ------------------------------------------------------------------------------------------
 // Kernels, one thread per cell.  A workgroup of 256 threads owns a tx x ty x 1 tile
 // (tx * ty = 256, tx = 256 for rows of 192 cells or more, so that the x-shifted accesses of the
-// swapped AA phase stay inside one workgroup); tiles are numbered x-fastest and handed to the
-// eight XCDs in contiguous ranges (workgroup w runs on XCD w mod 8), so tiles that share
-// neighbour data also share an L2.  Launch: block 256, grid 8 * per workgroups with
-// per = ceil(tiles / 8).
+// swapped AA phase stay inside one workgroup).  Tiles are ordered so that stencil neighbours
+// are processed close in time on the same XCD: the (tile-row, plane) grid is cut into blocks of
+// by x bz tile rows, each block is traversed x-fastest then y then z, the blocks y-fastest then
+// z, and the eight XCDs take contiguous ranges of that order (workgroup w runs on XCD w mod 8).
+// A neighbour row in y or z is then at most by tiles away inside a block, and the shared L2 of
+// the XCD still holds it.  Launch: block 256, grid 8 * per workgroups, per = ceil(tiles / 8).
 // ------------------------------------------------------------------------------------------
 struct Tiling {
-    int tx, ty;     // tile shape, tx * ty = 256
+    int tx, ty;       // tile shape, tx * ty = 256
     int ntx, nty, ntz;
-    uint32_t per;   // tiles per XCD
+    int by, bz;       // block of tile rows
+    int nby, nbz;     // blocks along y and z
+    uint32_t per;     // tiles per XCD (padded order)
 };
 
 __device__ __forceinline__ bool tile_cell(const Grid &g, const Tiling &tl, int &x, int &y,
                                           int &z) {
     const uint32_t w = blockIdx.x;
-#ifdef LBM_LINEAR_TILES
-    const uint32_t t = w;
-#else
     const uint32_t t = (w & 7u) * tl.per + (w >> 3);
-#endif
-    const uint32_t nt = (uint32_t)tl.ntx * (uint32_t)tl.nty * (uint32_t)tl.ntz;
+    const uint32_t rows_per_block = (uint32_t)tl.by * (uint32_t)tl.bz;
+    const uint32_t nt = (uint32_t)tl.ntx * rows_per_block * (uint32_t)tl.nby * (uint32_t)tl.nbz;
     if (t >= nt) return false;
     const uint32_t tx = t % (uint32_t)tl.ntx;
     const uint32_t r = t / (uint32_t)tl.ntx;
-    const uint32_t ty = r % (uint32_t)tl.nty;
-    const uint32_t tz = r / (uint32_t)tl.nty;
+    const uint32_t blk = r / rows_per_block, in = r % rows_per_block;
+    const uint32_t ty = (blk % (uint32_t)tl.nby) * (uint32_t)tl.by + in % (uint32_t)tl.by;
+    const uint32_t tz = (blk / (uint32_t)tl.nby) * (uint32_t)tl.bz + in / (uint32_t)tl.by;
     x = (int)(tx * (uint32_t)tl.tx + threadIdx.x % (uint32_t)tl.tx);
     y = (int)(ty * (uint32_t)tl.ty + threadIdx.x / (uint32_t)tl.tx);
     z = (int)tz;
-    return x < g.nx && y < g.ny;
+    return x < g.nx && y < g.ny && z < g.nz;
 }
 
 #define LBM_CELL_PROLOGUE(D)                                         \
@@ -566,22 +595,20 @@ __device__ __forceinline__ bool tile_cell(const Grid &g, const Tiling &tl, int &
 
 // Pass one: density (transformed_density_moment), transformed momentum
 // (transformed_momentum_moment), v^(0) (v_(0)) and the closed-form drag solve v^(1)
-// (v_(1), velocity_coefficients); writes rho [N] and v^(1) [D][N].
+// (v_(1), velocity_coefficients); writes the packed record (rho, v^(1)).
 template <int D, typename T, bool SOLIDS, int PH>
 __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f,
                                                  const T *__restrict__ eps,
                                                  const T *__restrict__ muD,
                                                  const T *__restrict__ muF,
                                                  const uint8_t *__restrict__ mask,
-                                                 T *__restrict__ rho_out, T *__restrict__ v1_out,
-                                                 Grid g, Tiling tl, Phys<T> ph) {
+                                                 P4<T> *__restrict__ m1_out, Grid g, Tiling tl,
+                                                 Phys<T> ph) {
     LBM_CELL_PROLOGUE(D)
     using L = Lat<D>;
     if constexpr (SOLIDS) {
         if (mask[n]) {
-            *at(rho_out, n) = T(0);
-#pragma unroll
-            for (int a = 0; a < D; ++a) *at(plane(v1_out, a, g.N), n) = T(0);
+            *at(m1_out, n) = pack(T(0), T(0), T(0), T(0));
             return;
         }
     }
@@ -616,47 +643,48 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f,
     for (int a = 0; a < D; ++a) s = s + v0[a] * v0[a];
     const T vm = sq(s);
     const T den = c1 + sq(c1 * c1 + (T(4) * c2) * vm);
-    *at(rho_out, n) = rho;
+    T v1[3] = {T(0), T(0), T(0)};
 #pragma unroll
-    for (int a = 0; a < D; ++a) *at(plane(v1_out, a, g.N), n) = dv(T(2) * v0[a], den);
+    for (int a = 0; a < D; ++a) v1[a] = dv(T(2) * v0[a], den);
+    *at(m1_out, n) = pack(rho, v1[0], v1[1], v1[2]);
 }
 
-// Velocity correction (v_final): v = v^(1) + Delta_nu(rho v^(1) / eps) / (2 rho).
+// Velocity correction (v_final): v = v^(1) + Delta_nu(rho v^(1) / eps) / (2 rho); reads the
+// packed (rho, v^(1)) records and writes packed (rho, v) records.
 template <int D, typename T, bool SOLIDS>
-__global__ __launch_bounds__(256) void k_vcorrect(const T *__restrict__ rho,
-                                                  const T *__restrict__ v1,
+__global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ m1,
                                                   const T *__restrict__ eps,
                                                   const uint8_t *__restrict__ mask,
-                                                  T *__restrict__ v_out, Grid g, Tiling tl,
+                                                  P4<T> *__restrict__ m2_out, Grid g, Tiling tl,
                                                   Phys<T> ph) {
     LBM_CELL_PROLOGUE(D)
     if constexpr (SOLIDS) {
         if (mask[n]) {
-#pragma unroll
-            for (int a = 0; a < D; ++a) *at(plane(v_out, a, g.N), n) = T(0);
+            *at(m2_out, n) = pack(T(0), T(0), T(0), T(0));
             return;
         }
     }
-    const Rec<T> own = load_rec<D>(rho, v1, eps, g.N, n);
+    const Rec<T> own = load_rec<D>(m1, eps, n);
     Rec<T> rec[3][2];
     bool fl[3][2];
-    load_stencil<D, T, SOLIDS>(rho, v1, eps, mask, g, nb, rec, fl);
+    load_stencil<D, T, SOLIDS>(m1, eps, mask, g, nb, rec, fl);
     T ge[3], H[3][3];
     porosity_derivatives<D>(eps, nb, own.e, ge, H);
     const Visc<T> vs = viscosity(ph, own.e);
     T dn[3];
-    delta_nu<D, T, SOLIDS>(rho, v1, eps, mask, g, nb, own, rec, fl, ge, H, vs, dn);
+    delta_nu<D, T, SOLIDS>(m1, eps, mask, g, nb, own, rec, fl, ge, H, vs, dn);
+    T v[3] = {T(0), T(0), T(0)};
 #pragma unroll
-    for (int a = 0; a < D; ++a)
-        *at(plane(v_out, a, g.N), n) = own.w[a] + dv(dn[a], T(2) * own.r);
+    for (int a = 0; a < D; ++a) v[a] = own.w[a] + dv(dn[a], T(2) * own.r);
+    *at(m2_out, n) = pack(own.r, v[0], v[1], v[2]);
 }
 
 // Forcing, collision (dicrete_scheme, momentum_rate with lambda = dt = 1) and streaming with
 // halfway bounce-back, in place:
 //   f^pc_i = f_i + 2 beta (f^eq_i - f_i) + (1 - beta)(f^*_i - f^eq_i).
 template <int D, typename T, bool SOLIDS, int PH>
-__global__ __launch_bounds__(256) void k_collide(T *__restrict__ f, const T *__restrict__ rho,
-                                                 const T *__restrict__ v,
+__global__ __launch_bounds__(256) void k_collide(T *__restrict__ f,
+                                                 const P4<T> *__restrict__ m2,
                                                  const T *__restrict__ eps,
                                                  const T *__restrict__ muD,
                                                  const T *__restrict__ muF,
@@ -670,7 +698,7 @@ __global__ __launch_bounds__(256) void k_collide(T *__restrict__ f, const T *__r
     Rec<T> own;
     Visc<T> vs;
     T xi[3], P[3], xs[3], Ps[3];
-    forcing_args<D, T, SOLIDS>(rho, v, eps, muD, muF, mask, g, ph, nb, own, vs, xi, P, xs, Ps);
+    forcing_args<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, vs, xi, P, xs, Ps);
     const T er = own.e * own.r;
     ProductForm<D, T> peq, pst;
     peq.init(er, xi, P);
@@ -697,8 +725,8 @@ __global__ __launch_bounds__(256) void k_collide(T *__restrict__ f, const T *__r
 // Initial populations, eq. (eq_bc_f_bar) with lambda = dt = 1, from the moment fields (rho, v):
 // f-bar_i = (1 + 1/2) f^eq_i - (1/2) f^*_i, written in natural layout.
 template <int D, typename T, bool SOLIDS>
-__global__ __launch_bounds__(256) void k_init(T *__restrict__ f, const T *__restrict__ rho,
-                                              const T *__restrict__ v,
+__global__ __launch_bounds__(256) void k_init(T *__restrict__ f,
+                                              const P4<T> *__restrict__ m2,
                                               const T *__restrict__ eps,
                                               const T *__restrict__ muD,
                                               const T *__restrict__ muF,
@@ -718,7 +746,7 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ f, const T *__rest
     Rec<T> own;
     Visc<T> vs;
     T xi[3], P[3], xs[3], Ps[3];
-    forcing_args<D, T, SOLIDS>(rho, v, eps, muD, muF, mask, g, ph, nb, own, vs, xi, P, xs, Ps);
+    forcing_args<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, vs, xi, P, xs, Ps);
     const T er = own.e * own.r;
     ProductForm<D, T> peq, pst;
     peq.init(er, xi, P);
@@ -745,20 +773,20 @@ __global__ __launch_bounds__(256) void k_static(const double *__restrict__ eps_i
     muF[n] = (T)(e * cf_in[n]);
 }
 
-// Initial moment fields: rho = rho_init or rho0, v = v_init or 0 (0 on solid cells).
+// Initial moment records: rho = rho_init or rho0, v = v_init or 0 (0 on solid cells).
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_fill_init(const double *__restrict__ rho_in,
                                                    const double *__restrict__ v_in,
                                                    const uint8_t *__restrict__ mask,
-                                                   T *__restrict__ rho, T *__restrict__ v,
-                                                   int64_t N, double rho0) {
+                                                   P4<T> *__restrict__ m2, int64_t N, double rho0) {
     const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (n >= N) return;
     const bool solid = mask && mask[n];
-    rho[n] = solid ? T(0) : (T)(rho_in ? rho_in[n] : rho0);
+    T w[3] = {T(0), T(0), T(0)};
+    if (!solid && v_in)
 #pragma unroll
-    for (int a = 0; a < D; ++a)
-        v[(int64_t)a * N + n] = solid ? T(0) : (T)(v_in ? v_in[(int64_t)a * N + n] : 0.0);
+        for (int a = 0; a < D; ++a) w[a] = (T)v_in[(int64_t)a * N + n];
+    m2[n] = pack(solid ? T(0) : (T)(rho_in ? rho_in[n] : rho0), w[0], w[1], w[2]);
 }
 
 // Natural-layout copy of the current populations (0 on solid cells).
@@ -782,23 +810,21 @@ __global__ __launch_bounds__(256) void k_import(T *__restrict__ f, const I *__re
     if (k < total) f[k] = (T)in[k];
 }
 
-// Caller-facing moments: rho and v (kind 0) or u = v / eps (kind 1).
+// Caller-facing moments: rho and v (kind 0) or u = v / eps (kind 1), from the packed records.
 template <int D, typename T, typename O>
-__global__ __launch_bounds__(256) void k_moments_out(const T *__restrict__ rho,
-                                                     const T *__restrict__ v,
+__global__ __launch_bounds__(256) void k_moments_out(const P4<T> *__restrict__ m2,
                                                      const T *__restrict__ eps,
                                                      O *__restrict__ rho_out, O *__restrict__ v_out,
                                                      int64_t N, int kind) {
     const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (n >= N) return;
-    if (rho_out) rho_out[n] = (O)rho[n];
+    const P4<T> q = m2[n];
+    if (rho_out) rho_out[n] = (O)q.x;
     if (v_out) {
         const T e = eps[n];
+        const T w[3] = {q.y, q.z, q.w};
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const T va = v[(int64_t)a * N + n];
-            v_out[(int64_t)a * N + n] = (O)(kind ? va / e : va);
-        }
+        for (int a = 0; a < D; ++a) v_out[(int64_t)a * N + n] = (O)(kind ? w[a] / e : w[a]);
     }
 }
 
@@ -823,8 +849,9 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 template <int D, typename T, bool SOLIDS, int PH>
-__global__ __launch_bounds__(256) void k_stats(const T *__restrict__ f, const T *__restrict__ rho,
-                                               const T *__restrict__ v, T *__restrict__ vsnap,
+__global__ __launch_bounds__(256) void k_stats(const T *__restrict__ f,
+                                               const P4<T> *__restrict__ m2,
+                                               T *__restrict__ vsnap,
                                                const uint8_t *__restrict__ mask,
                                                double *__restrict__ partial, Grid g) {
     using L = Lat<D>;
@@ -846,16 +873,18 @@ __global__ __launch_bounds__(256) void k_stats(const T *__restrict__ f, const T 
         acc[0] += cm;
         if (!isfinite(cm)) acc[7] += 1.0;
         double vv = 0.0;
-        const double r = (double)rho[n];
+        const P4<T> q = m2[n];
+        const double r = (double)q.x;
+        const T w[3] = {q.y, q.z, q.w};
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const double va = (double)v[(size_t)a * g.N + n];
+            const double va = (double)w[a];
             const double sa = (double)vsnap[(size_t)a * g.N + n];
             acc[1 + a] += r * va;
             vv += va * va;
             acc[5] += (va - sa) * (va - sa);
             acc[6] += sa * sa;
-            vsnap[(size_t)a * g.N + n] = v[(size_t)a * g.N + n];
+            vsnap[(size_t)a * g.N + n] = w[a];
         }
         if (!isfinite(vv)) acc[7] += 1.0;
         else acc[4] = fmax(acc[4], sqrt(vv));
