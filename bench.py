@@ -38,9 +38,17 @@ def kernel_bytes_per_cell(Q, D, s):
     }
 
 
-def method_bytes_per_cell(Q, D, s):
-    """Two-pass minimum of the faithful method: pass one reads Q pops + 3 static fields and
+def lagged_bytes_per_cell(Q, D, s):
+    """Single pass of the lagged scheme: read Q pops, 3 static fields and the previous step's
+    rho, v^(1), v; write Q pops and the new rho, v^(1), v."""
+    return (Q + 3 + (2 * D + 1) + Q + (2 * D + 1)) * s
+
+
+def method_bytes_per_cell(Q, D, s, lagged=False):
+    """Per-step minimum of the method.  Two-pass: pass one reads Q pops + 3 static fields and
     writes rho, v^(1); pass two reads Q pops, rho, v, 3 static fields and writes Q pops."""
+    if lagged:
+        return lagged_bytes_per_cell(Q, D, s)
     return (Q + 3 + (D + 1)) * s + (Q + (D + 1) + 3 + Q) * s
 
 
@@ -95,6 +103,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="cells per side")
     ap.add_argument("--storage", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--scheme", choices=["two-pass", "lagged"], default="two-pass",
+                    help="two-pass: the method as written (headline); lagged: single fused pass "
+                         "with previous-step neighbour moments")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB "
@@ -117,7 +128,10 @@ def main():
     w = workloads.random_porosity_3d(n=n, seed=0, ell=16.0, steps=args.steps)
     storage = capi.LBM_F32 if args.storage == "f32" else capi.LBM_F64
     s_bytes = 4 if args.storage == "f32" else 8
-    solver = capi.Solver.from_workload(w, storage=storage)
+    lagged = args.scheme == "lagged"
+    solver = capi.Solver.from_workload(
+        w, storage=storage,
+        scheme=capi.LBM_SCHEME_LAGGED if lagged else capi.LBM_SCHEME_TWO_PASS)
     N = w.cells
     print(f"[bench] created {w.name}, {args.storage}, workspace {solver.nbytes / 2**30:.2f} GiB",
           file=sys.stderr, flush=True)
@@ -138,15 +152,19 @@ def main():
     assert st.nonfinite == 0
 
     Q, D = 27, 3
-    kb = kernel_bytes_per_cell(Q, D, s_bytes)
-    avg_ms = {"moments": kms[0] / args.steps, "vcorrect": kms[1] / args.steps,
-              "collide": kms[2] / args.steps}
+    if lagged:
+        kb = {"fused": lagged_bytes_per_cell(Q, D, s_bytes)}
+        avg_ms = {"fused": kms[2] / args.steps}
+    else:
+        kb = kernel_bytes_per_cell(Q, D, s_bytes)
+        avg_ms = {"moments": kms[0] / args.steps, "vcorrect": kms[1] / args.steps,
+                  "collide": kms[2] / args.steps}
     dom = max(avg_ms, key=avg_ms.get)
     algo = kb[dom] * N
     achieved = algo / (avg_ms[dom] * 1e-3) / 1e9
     src = source_hash()
     traffic = traffic_from_profiles(dom, N, src)
-    step_bytes = method_bytes_per_cell(Q, D, s_bytes)
+    step_bytes = method_bytes_per_cell(Q, D, s_bytes, lagged)
     kernels = {k: {"avg_ms": round(avg_ms[k], 4), "bytes_per_cell": kb[k],
                    "achieved_GBps": round(kb[k] * N / (avg_ms[k] * 1e-3) / 1e9, 1)}
                for k in avg_ms}
@@ -166,7 +184,7 @@ def main():
         "config": {"workload": f"random-porosity D3Q27 {n}^3 periodic box, seed 0, "
                                f"correlation length 16, phi in (0.3,1), Kozeny-Carman K (d=2), "
                                f"C_F=0.55/sqrt(K), nu=0.01, b=1e-6 x", "lattice": "D3Q27",
-                   "cells": N, "storage": args.storage, "scheme": "faithful two-pass"},
+                   "cells": N, "storage": args.storage, "scheme": args.scheme},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),

@@ -54,6 +54,20 @@ extern "C" {
 #define LBM_F64 0
 #define LBM_F32 1
 
+/*
+ * Time-stepping scheme.
+ * LBM_SCHEME_TWO_PASS follows Sec. 3.5 as written: every step first takes the moments and the
+ *   corrected velocity of all cells (pass one), then forces, collides and streams (pass two).
+ * LBM_SCHEME_LAGGED fuses both into one pass over the populations: a cell's own moments,
+ *   velocity correction and forcing use its current populations, while the neighbour values
+ *   inside the stencils of Delta_nu, Phi^ext and Phi^eta are the previous step's.  A steady
+ *   state of either scheme is one of the other; transients differ by O(dt).  The first step
+ *   after lbm_create uses the initial fields as the previous step; the first step after
+ *   lbm_set_populations is a two-pass step.
+ */
+#define LBM_SCHEME_TWO_PASS 0
+#define LBM_SCHEME_LAGGED 1
+
 /* Output element type for lbm_moments / lbm_get_populations / lbm_set_populations. */
 #define LBM_DTYPE_F64 0
 #define LBM_DTYPE_F32 1
@@ -70,6 +84,7 @@ extern "C" {
 typedef struct lbm_params {
     int lattice;          /* LBM_D2Q9 or LBM_D3Q27 */
     int storage;          /* LBM_F64 or LBM_F32 */
+    int scheme;           /* LBM_SCHEME_TWO_PASS or LBM_SCHEME_LAGGED */
     int nx, ny, nz;       /* >= 1; nz must be 1 for D2Q9 */
     double RT;            /* lattice temperature RT > 0 (1/3 is the lattice reference) */
     double nu_f;          /* fluid viscosity in the Darcy coefficient mu_D = eps nu_f / kappa
@@ -109,7 +124,7 @@ typedef struct lbm_solver lbm_solver;
 
 /*
  * Bytes of device workspace lbm_create needs for these parameters (pure host computation, no
- * device work).  Only lattice, storage, nx, ny, nz and whether mask is non-NULL are read.
+ * device work).  Only lattice, storage, scheme, nx, ny, nz and whether mask is non-NULL are read.
  * Errors: LBM_ERR_INVALID_ARG for NULL pointers or bad lattice, storage or dimensions.
  */
 LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes);
@@ -129,10 +144,11 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
                        void *hip_stream, lbm_solver **out);
 
 /*
- * Enqueue n >= 0 time steps (Sec. 3.5, collide-and-stream loop).  Each step runs the moment
- * pass (eqs. transformed_density_moment, transformed_momentum_moment, v_(0), v_(1)), the velocity
- * correction (eq. v_final) and the fused forcing-collide-stream pass (eqs. accel, ex_corr,
- * eta_corr, prod_form, dicrete_scheme) with halfway bounce-back and periodic wrap.
+ * Enqueue n >= 0 time steps (Sec. 3.5, collide-and-stream loop).  A two-pass step runs the
+ * moment pass (eqs. transformed_density_moment, transformed_momentum_moment, v_(0), v_(1)), the
+ * velocity correction (eq. v_final) and the fused forcing-collide-stream pass (eqs. accel,
+ * ex_corr, eta_corr, prod_form, dicrete_scheme) with halfway bounce-back and periodic wrap; a
+ * lagged step runs all of it in one kernel (LBM_SCHEME_LAGGED).
  * Asynchronous; kernel faults surface at the next synchronising call.
  */
 LBM_API int lbm_step(lbm_solver *h, int64_t n);
@@ -140,7 +156,8 @@ LBM_API int lbm_step(lbm_solver *h, int64_t n);
 /*
  * As lbm_step, and also measures each kernel class with HIP events on the handle's stream;
  * synchronises.  kernel_ms[0..2] receive the summed durations (ms) of the moment, velocity
- * correction and collide-stream kernels over the n steps.
+ * correction and collide-stream kernels over the n steps (lagged steps count their single
+ * kernel under collide-stream).
  */
 LBM_API int lbm_step_timed(lbm_solver *h, int64_t n, double kernel_ms[3]);
 
@@ -148,7 +165,8 @@ LBM_API int lbm_step_timed(lbm_solver *h, int64_t n, double kernel_ms[3]);
  * Write the macroscopic fields of the current state: intrinsic density rho [N] and the
  * corrected velocity [D][N] (eqs. v_(0), v_(1), v_final), superficial v or intrinsic u = v/eps
  * per velocity_kind, as LBM_DTYPE_F64 or LBM_DTYPE_F32 into caller device buffers (either
- * pointer may be NULL).  Solid cells get 0.  Asynchronous.
+ * pointer may be NULL).  Solid cells get 0.  Under LBM_SCHEME_LAGGED the correction takes its
+ * neighbour values from the previous step, as the next step will.  Asynchronous.
  */
 LBM_API int lbm_moments(lbm_solver *h, void *rho_dev, void *v_dev, int dtype, int velocity_kind);
 

@@ -29,6 +29,8 @@ LBM_D2Q9 = 9
 LBM_D3Q27 = 27
 LBM_F64 = 0
 LBM_F32 = 1
+LBM_SCHEME_TWO_PASS = 0
+LBM_SCHEME_LAGGED = 1
 LBM_DTYPE_F64 = 0
 LBM_DTYPE_F32 = 1
 LBM_VELOCITY_SUPERFICIAL = 0
@@ -39,7 +41,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 class lbm_params(ctypes.Structure):
     _fields_ = [
-        ("lattice", ctypes.c_int), ("storage", ctypes.c_int),
+        ("lattice", ctypes.c_int), ("storage", ctypes.c_int), ("scheme", ctypes.c_int),
         ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
         ("RT", ctypes.c_double), ("nu_f", ctypes.c_double), ("nu_eff_ref", ctypes.c_double),
         ("nu_eff_pow", ctypes.c_int), ("eta_eff", ctypes.c_double),
@@ -179,7 +181,8 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
                 forch: np.ndarray, mask: Optional[np.ndarray] = None, RT: float = 1.0 / 3.0,
                 nu_f: float = 1.0 / 6.0, nu_eff_ref: float = 1.0 / 6.0, nu_eff_pow: int = 0,
                 eta_eff: float = math.nan, b=(0.0, 0.0, 0.0), rho0: float = 1.0,
-                rho_init: Optional[np.ndarray] = None, v_init: Optional[np.ndarray] = None):
+                rho_init: Optional[np.ndarray] = None, v_init: Optional[np.ndarray] = None,
+                scheme: int = LBM_SCHEME_TWO_PASS):
     """Build an lbm_params from numpy arrays shaped [nz, ny, nx]; returns (params, keepalive)."""
     eps = np.ascontiguousarray(eps, dtype=np.float64)
     if eps.ndim == 2:
@@ -195,7 +198,7 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
         return a.ctypes.data_as(_dp)
 
     p = lbm_params()
-    p.lattice, p.storage = lattice, storage
+    p.lattice, p.storage, p.scheme = lattice, storage, scheme
     p.nx, p.ny, p.nz = nx, ny, nz
     p.RT, p.nu_f, p.nu_eff_ref, p.nu_eff_pow, p.eta_eff = RT, nu_f, nu_eff_ref, nu_eff_pow, eta_eff
     for a in range(3):
@@ -235,11 +238,11 @@ class Solver:
         del keepalive
 
     @classmethod
-    def from_workload(cls, w, storage: int = LBM_F32, **kw):
+    def from_workload(cls, w, storage: int = LBM_F32, scheme: int = LBM_SCHEME_TWO_PASS, **kw):
         p, keep = make_params(w.lattice, storage, w.eps, w.kappa, w.forch, w.mask, RT=w.RT,
                               nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow,
                               eta_eff=w.eta_eff, b=w.b, rho0=w.rho0, rho_init=w.rho_init,
-                              v_init=w.v_init)
+                              v_init=w.v_init, scheme=scheme)
         return cls(p, keep, **kw)
 
     def close(self):

@@ -49,10 +49,10 @@ int fail(int code, const char *fmt, ...) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t f, eps, muD, muF, mask, m1, m2, vsnap, part, res, total;
+    size_t f, eps, muD, muF, mask, m1[2], m2[2], vsnap, part, res, total;
 };
 
-Layout make_layout(int Q, int D, size_t N, size_t s, bool solids) {
+Layout make_layout(int Q, int D, size_t N, size_t s, bool solids, bool lagged) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -65,8 +65,12 @@ Layout make_layout(int Q, int D, size_t N, size_t s, bool solids) {
     L.muD = take(N * s);
     L.muF = take(N * s);
     L.mask = solids ? take(N) : 0;
-    L.m1 = take(4 * N * s);  // packed (rho, v^(1)) records
-    L.m2 = take(4 * N * s);  // packed (rho, v) records
+    // packed (rho, v^(1)) and (rho, v) records; the lagged scheme keeps a second pair so that
+    // one step reads the previous records while it writes the new ones
+    L.m1[0] = take(4 * N * s);
+    L.m2[0] = take(4 * N * s);
+    L.m1[1] = lagged ? take(4 * N * s) : L.m1[0];
+    L.m2[1] = lagged ? take(4 * N * s) : L.m2[0];
     L.vsnap = take((size_t)D * N * s);
     L.part = take((size_t)lbm::kStatsBlocks * lbm::kStatsSlots * sizeof(double));
     L.res = take(lbm::kStatsSlots * sizeof(double));
@@ -88,6 +92,9 @@ struct lbm_solver {
     Layout L;
     int64_t step;
     int phase;  // AA-pattern layout: 0 natural, 1 swapped
+    int scheme;
+    int cur;        // record pair that holds the previous step's moments (lagged scheme)
+    bool have_prev; // whether that pair is valid (lagged scheme)
     double RT, nu_f, nu_eff_ref, eta_eff, b[3];
     int nu_eff_pow;
     lbm::Tiling tiles;  // 256-cell tiles, blocked, in XCD-contiguous ranges
@@ -148,37 +155,49 @@ const uint8_t *mask_ptr(const lbm_solver *h) {
 
 // ---- kernel launchers, dispatched on (lattice, type, solids, phase) -----------------------
 template <int D, typename T, bool S, int PH>
-void launch_moments(const lbm_solver *h) {
+void launch_moments(const lbm_solver *h, size_t m1_out) {
     auto ph = phys_of<T>(h);
     hipLaunchKernelGGL((lbm::k_moments<D, T, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
                        ws_ptr<const T>(h, h->L.f), ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
-                       ws_ptr<lbm::P4<T>>(h, h->L.m1), grid_of(h), h->tiles, ph);
+                       ws_ptr<lbm::P4<T>>(h, m1_out), grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, bool S>
-void launch_vcorrect(const lbm_solver *h) {
+void launch_vcorrect(const lbm_solver *h, size_t own_src, size_t m1, size_t m2_out) {
     auto ph = phys_of<T>(h);
     hipLaunchKernelGGL((lbm::k_vcorrect<D, T, S>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<const lbm::P4<T>>(h, h->L.m1), ws_ptr<const T>(h, h->L.eps),
-                       mask_ptr(h), ws_ptr<lbm::P4<T>>(h, h->L.m2), grid_of(h), h->tiles, ph);
+                       ws_ptr<const lbm::P4<T>>(h, own_src), ws_ptr<const lbm::P4<T>>(h, m1),
+                       ws_ptr<const T>(h, h->L.eps), mask_ptr(h), ws_ptr<lbm::P4<T>>(h, m2_out),
+                       grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, bool S, int PH>
-void launch_collide(const lbm_solver *h) {
+void launch_collide(const lbm_solver *h, size_t m2) {
     auto ph = phys_of<T>(h);
     hipLaunchKernelGGL((lbm::k_collide<D, T, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m2),
+                       ws_ptr<T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
                        ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
                        grid_of(h), h->tiles, ph);
+}
+
+template <int D, typename T, bool S, int PH>
+void launch_fused(const lbm_solver *h, int prev, int next) {
+    auto ph = phys_of<T>(h);
+    hipLaunchKernelGGL((lbm::k_fused<D, T, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
+                       ws_ptr<T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m1[prev]),
+                       ws_ptr<const lbm::P4<T>>(h, h->L.m2[prev]),
+                       ws_ptr<lbm::P4<T>>(h, h->L.m1[next]), ws_ptr<lbm::P4<T>>(h, h->L.m2[next]),
+                       ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
+                       ws_ptr<const T>(h, h->L.muF), mask_ptr(h), grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, bool S>
 void launch_init(const lbm_solver *h) {
     auto ph = phys_of<T>(h);
     hipLaunchKernelGGL((lbm::k_init<D, T, S>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m2),
+                       ws_ptr<T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m2[0]),
                        ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
                        grid_of(h), h->tiles, ph);
@@ -191,9 +210,9 @@ void launch_export(const lbm_solver *h, O *out) {
 }
 
 template <int D, typename T, bool S, int PH>
-void launch_stats(const lbm_solver *h) {
+void launch_stats(const lbm_solver *h, size_t m2) {
     hipLaunchKernelGGL((lbm::k_stats<D, T, S, PH>), dim3(lbm::kStatsBlocks), dim3(256), 0,
-                       h->stream, ws_ptr<const T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m2),
+                       h->stream, ws_ptr<const T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
                        ws_ptr<T>(h, h->L.vsnap), mask_ptr(h),
                        ws_ptr<double>(h, h->L.part), grid_of(h));
 }
@@ -223,18 +242,27 @@ void dispatch(const lbm_solver *h, F &&fn) {
 
 struct MomentsPass {
     const lbm_solver *h;
+    size_t m1_out;
     template <int D, typename T, bool S, int PH>
-    void operator()() { launch_moments<D, T, S, PH>(h); }
+    void operator()() { launch_moments<D, T, S, PH>(h, m1_out); }
 };
 struct VcorrectPass {
     const lbm_solver *h;
+    size_t own_src, m1, m2_out;
     template <int D, typename T, bool S, int PH>
-    void operator()() { launch_vcorrect<D, T, S>(h); }
+    void operator()() { launch_vcorrect<D, T, S>(h, own_src, m1, m2_out); }
 };
 struct CollidePass {
     const lbm_solver *h;
+    size_t m2;
     template <int D, typename T, bool S, int PH>
-    void operator()() { launch_collide<D, T, S, PH>(h); }
+    void operator()() { launch_collide<D, T, S, PH>(h, m2); }
+};
+struct FusedPass {
+    const lbm_solver *h;
+    int prev, next;
+    template <int D, typename T, bool S, int PH>
+    void operator()() { launch_fused<D, T, S, PH>(h, prev, next); }
 };
 struct InitPass {
     const lbm_solver *h;
@@ -243,8 +271,9 @@ struct InitPass {
 };
 struct StatsPass {
     const lbm_solver *h;
+    size_t m2;
     template <int D, typename T, bool S, int PH>
-    void operator()() { launch_stats<D, T, S, PH>(h); }
+    void operator()() { launch_stats<D, T, S, PH>(h, m2); }
 };
 struct ExportPass {
     const lbm_solver *h;
@@ -257,13 +286,46 @@ struct ExportPass {
     }
 };
 
-// Moments of the current state into the internal packed (rho, v^(1)) and (rho, v) records.
-int current_moments(lbm_solver *h) {
-    dispatch(h, MomentsPass{h});
-    LAUNCH_CHECK();
-    dispatch(h, VcorrectPass{h});
-    LAUNCH_CHECK();
-    return LBM_OK;
+// Moments of the current state into internal packed records; returns the offset of the
+// (rho, v) records.  Under the lagged scheme with a valid history the correction takes its
+// neighbour values from the previous step's records, which stay untouched.
+size_t current_moments(lbm_solver *h) {
+    if (h->scheme == LBM_SCHEME_LAGGED && h->have_prev) {
+        const int nx = h->cur ^ 1;
+        dispatch(h, MomentsPass{h, h->L.m1[nx]});
+        dispatch(h, VcorrectPass{h, h->L.m1[nx], h->L.m1[h->cur], h->L.m2[nx]});
+        return h->L.m2[nx];
+    }
+    const int c = h->cur;
+    dispatch(h, MomentsPass{h, h->L.m1[c]});
+    dispatch(h, VcorrectPass{h, h->L.m1[c], h->L.m1[c], h->L.m2[c]});
+    return h->L.m2[c];
+}
+
+// Enqueue one time step; ev (optional) receives events after each kernel class.
+hipError_t one_step(lbm_solver *h, hipEvent_t *ev) {
+    hipError_t e = hipSuccess;
+    if (h->scheme == LBM_SCHEME_LAGGED && h->have_prev) {
+        const int nx = h->cur ^ 1;
+        if (ev) e = hipEventRecord(ev[0], h->stream);
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
+        dispatch(h, FusedPass{h, h->cur, nx});
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
+        h->cur = nx;
+    } else {
+        const int c = h->cur;
+        dispatch(h, MomentsPass{h, h->L.m1[c]});
+        if (ev) e = hipEventRecord(ev[0], h->stream);
+        dispatch(h, VcorrectPass{h, h->L.m1[c], h->L.m1[c], h->L.m2[c]});
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
+        dispatch(h, CollidePass{h, h->L.m2[c]});
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
+        h->have_prev = true;  // this step's records are the next step's history
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    h->phase ^= 1;
+    h->step += 1;
+    return e;
 }
 
 int check_handle(const lbm_solver *h) {
@@ -280,6 +342,8 @@ int validate_shape(const lbm_params *p, int *D, int *Q, size_t *s, int64_t *N) {
     if (p->storage == LBM_F64) *s = 8;
     else if (p->storage == LBM_F32) *s = 4;
     else return fail(LBM_ERR_UNSUPPORTED, "storage %d is not supported", p->storage);
+    if (p->scheme != LBM_SCHEME_TWO_PASS && p->scheme != LBM_SCHEME_LAGGED)
+        return fail(LBM_ERR_INVALID_ARG, "scheme must be LBM_SCHEME_TWO_PASS or LBM_SCHEME_LAGGED, got %d", p->scheme);
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LBM_ERR_INVALID_ARG, "dimensions must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
     if (*D == 2 && p->nz != 1) return fail(LBM_ERR_INVALID_ARG, "D2Q9 needs nz = 1 (got %d)", p->nz);
@@ -326,7 +390,7 @@ LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes) {
     if (!workspace_bytes) return fail(LBM_ERR_INVALID_ARG, "workspace_bytes is NULL");
     int rc = validate_shape(p, &D, &Q, &s, &N);
     if (rc) return rc;
-    *workspace_bytes = make_layout(Q, D, (size_t)N, s, p->mask != nullptr).total;
+    *workspace_bytes = make_layout(Q, D, (size_t)N, s, p->mask != nullptr, p->scheme == LBM_SCHEME_LAGGED).total;
     return LBM_OK;
 }
 
@@ -370,7 +434,7 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     }
     if (!any_fluid) return fail(LBM_ERR_INVALID_ARG, "no fluid cell");
     const bool solids = p->mask != nullptr;
-    const Layout L = make_layout(Q, D, (size_t)N, s, solids);
+    const Layout L = make_layout(Q, D, (size_t)N, s, solids, p->scheme == LBM_SCHEME_LAGGED);
     if (!dev_workspace) return fail(LBM_ERR_INVALID_ARG, "dev_workspace is NULL");
     if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
         return fail(LBM_ERR_WORKSPACE, "dev_workspace must be 256-byte aligned");
@@ -393,6 +457,9 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->tiles = make_tiling(p->nx, p->ny, p->nz);
     h->step = 0;
     h->phase = 0;
+    h->scheme = p->scheme;
+    h->cur = 0;
+    h->have_prev = true;  // the initial fields stand for the previous step
     h->RT = p->RT;
     h->nu_f = p->nu_f;
     h->nu_eff_ref = p->nu_eff_ref;
@@ -435,12 +502,13 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
         v_st = st + N;
     }
     const uint8_t *mk = mask_ptr(h);
+    const bool lag = p->scheme == LBM_SCHEME_LAGGED;
     if (h->storage == LBM_F64) {
-        if (D == 2) hipLaunchKernelGGL((lbm::k_fill_init<2, double>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<lbm::P4<double>>(h, L.m2), N, p->rho0);
-        else hipLaunchKernelGGL((lbm::k_fill_init<3, double>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<lbm::P4<double>>(h, L.m2), N, p->rho0);
+        if (D == 2) hipLaunchKernelGGL((lbm::k_fill_init<2, double>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<lbm::P4<double>>(h, L.m2[0]), lag ? ws_ptr<lbm::P4<double>>(h, L.m1[0]) : nullptr, N, p->rho0);
+        else hipLaunchKernelGGL((lbm::k_fill_init<3, double>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<lbm::P4<double>>(h, L.m2[0]), lag ? ws_ptr<lbm::P4<double>>(h, L.m1[0]) : nullptr, N, p->rho0);
     } else {
-        if (D == 2) hipLaunchKernelGGL((lbm::k_fill_init<2, float>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<lbm::P4<float>>(h, L.m2), N, p->rho0);
-        else hipLaunchKernelGGL((lbm::k_fill_init<3, float>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<lbm::P4<float>>(h, L.m2), N, p->rho0);
+        if (D == 2) hipLaunchKernelGGL((lbm::k_fill_init<2, float>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<lbm::P4<float>>(h, L.m2[0]), lag ? ws_ptr<lbm::P4<float>>(h, L.m1[0]) : nullptr, N, p->rho0);
+        else hipLaunchKernelGGL((lbm::k_fill_init<3, float>), flat_grid(N), dim3(256), 0, h->stream, rho_st, v_st, mk, ws_ptr<lbm::P4<float>>(h, L.m2[0]), lag ? ws_ptr<lbm::P4<float>>(h, L.m1[0]) : nullptr, N, p->rho0);
     }
     if ((e = hipGetLastError()) != hipSuccess)
         return cleanup(fail(LBM_ERR_HIP, "initial-field kernel failed: %s", hipGetErrorString(e)));
@@ -461,12 +529,8 @@ LBM_API int lbm_step(lbm_solver *h, int64_t n) {
     if (rc) return rc;
     if (n < 0) return fail(LBM_ERR_INVALID_ARG, "negative step count");
     for (int64_t k = 0; k < n; ++k) {
-        dispatch(h, MomentsPass{h});
-        dispatch(h, VcorrectPass{h});
-        dispatch(h, CollidePass{h});
-        LAUNCH_CHECK();
-        h->phase ^= 1;
-        h->step += 1;
+        hipError_t e = one_step(h, nullptr);
+        if (e != hipSuccess) return fail(LBM_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     }
     return LBM_OK;
 }
@@ -485,17 +549,7 @@ LBM_API int lbm_step_timed(lbm_solver *h, int64_t n, double kernel_ms[3]) {
     for (int64_t done = 0; done < n && out == LBM_OK;) {
         const int64_t m = std::min<int64_t>(n - done, kChunk);
         hipError_t e = hipEventRecord(ev[0], h->stream);
-        for (int64_t k = 0; k < m && e == hipSuccess; ++k) {
-            dispatch(h, MomentsPass{h});
-            e = hipEventRecord(ev[3 * k + 1], h->stream);
-            dispatch(h, VcorrectPass{h});
-            if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 2], h->stream);
-            dispatch(h, CollidePass{h});
-            if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 3], h->stream);
-            if (e == hipSuccess) e = hipGetLastError();
-            h->phase ^= 1;
-            h->step += 1;
-        }
+        for (int64_t k = 0; k < m && e == hipSuccess; ++k) e = one_step(h, &ev[3 * k + 1]);
         if (e == hipSuccess) e = hipEventSynchronize(ev[3 * m]);
         if (e != hipSuccess) {
             out = fail(LBM_ERR_HIP, "timed step failed: %s", hipGetErrorString(e));
@@ -520,12 +574,12 @@ LBM_API int lbm_moments(lbm_solver *h, void *rho_dev, void *v_dev, int dtype, in
     if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_INVALID_ARG, "bad dtype");
     if (velocity_kind != LBM_VELOCITY_SUPERFICIAL && velocity_kind != LBM_VELOCITY_INTRINSIC)
         return fail(LBM_ERR_INVALID_ARG, "bad velocity_kind");
-    rc = current_moments(h);
-    if (rc) return rc;
+    const size_t m2 = current_moments(h);
+    LAUNCH_CHECK();
     const int64_t N = h->N;
 #define LBM_OUT(DD, TT, OO)                                                                      \
     hipLaunchKernelGGL((lbm::k_moments_out<DD, TT, OO>), flat_grid(N), dim3(256), 0, h->stream, \
-                       ws_ptr<const lbm::P4<TT>>(h, h->L.m2), ws_ptr<const TT>(h, h->L.eps),    \
+                       ws_ptr<const lbm::P4<TT>>(h, m2), ws_ptr<const TT>(h, h->L.eps),           \
                        (OO *)rho_dev, (OO *)v_dev, N, velocity_kind)
     if (h->D == 2) {
         if (h->storage == LBM_F64) { if (dtype == LBM_DTYPE_F64) LBM_OUT(2, double, double); else LBM_OUT(2, double, float); }
@@ -543,9 +597,9 @@ LBM_API int lbm_residual(lbm_solver *h, lbm_stats *out) {
     int rc = check_handle(h);
     if (rc) return rc;
     if (!out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
-    rc = current_moments(h);
-    if (rc) return rc;
-    dispatch(h, StatsPass{h});
+    const size_t m2 = current_moments(h);
+    LAUNCH_CHECK();
+    dispatch(h, StatsPass{h, m2});
     LAUNCH_CHECK();
     hipLaunchKernelGGL(lbm::k_stats_final, dim3(1), dim3(256), 0, h->stream,
                        ws_ptr<const double>(h, h->L.part), lbm::kStatsBlocks, ws_ptr<double>(h, h->L.res));
@@ -594,6 +648,7 @@ LBM_API int lbm_set_populations(lbm_solver *h, const void *dev_in, int dtype, in
     LAUNCH_CHECK();
     h->phase = 0;
     h->step = step;
+    h->have_prev = false;  // the lagged scheme's history restarts with a two-pass step
     return LBM_OK;
 }
 

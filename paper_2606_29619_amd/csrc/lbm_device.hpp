@@ -458,23 +458,23 @@ __device__ __forceinline__ T record_deriv(const P4<T> *__restrict__ mom,
 
 // Equilibrium and shifted-equilibrium arguments of one cell from the moment fields (rho, v):
 // acceleration (accel), Phi^ext (ex_corr), Phi^eta (eta_corr), then xi, P (xi_alpha_eq,
-// P_alpha_alpha_eq) and xi*, P* (xi_alpha_*, P_aa_*) with lambda = 1.
+// P_alpha_alpha_eq) and xi*, P* (xi_alpha_*, P_aa_*) with lambda = 1.  `own` is the cell's
+// record; the neighbour records come from `mom` (the same step's, or the previous step's in
+// the lagged scheme).
 template <int D, typename T, bool SOLIDS>
 __device__ __forceinline__ void forcing_args(const P4<T> *__restrict__ mom,
                                              const T *__restrict__ eps,
                                              const T *__restrict__ muD,
                                              const T *__restrict__ muF,
                                              const uint8_t *__restrict__ mask, const Grid &g,
-                                             const Phys<T> &ph, const Nbr<D> &nb, Rec<T> &own,
-                                             Visc<T> &vs, T xi[3], T P[3], T xs[3], T Ps[3]) {
+                                             const Phys<T> &ph, const Nbr<D> &nb,
+                                             const Rec<T> &own, const T ge[3], const T H[3][3],
+                                             const Visc<T> &vs, T xi[3], T P[3], T xs[3],
+                                             T Ps[3]) {
     const uint32_t n = nb.self();
-    own = load_rec<D>(mom, eps, n);
     Rec<T> rec[3][2];
     bool fl[3][2];
     load_stencil<D, T, SOLIDS>(mom, eps, mask, g, nb, rec, fl);
-    T ge[3], H[3][3];
-    porosity_derivatives<D>(eps, nb, own.e, ge, H);
-    vs = viscosity(ph, own.e);
     T dm[3] = {T(0), T(0), T(0)};
     delta_nu<D, T, SOLIDS>(mom, eps, mask, g, nb, own, rec, fl, ge, H, vs, dm);
     T s = T(0);
@@ -550,6 +550,62 @@ struct ProductForm {
     }
 };
 
+// Porosity record, derivatives and viscosity of the cell, the common prologue of the passes
+// that work on the moment records.
+template <int D, typename T>
+struct CellStatic {
+    T ge[3], H[3][3];
+    Visc<T> vs;
+};
+
+template <int D, typename T>
+__device__ __forceinline__ CellStatic<D, T> cell_static(const T *__restrict__ eps,
+                                                        const Nbr<D> &nb, const Phys<T> &ph,
+                                                        T e0) {
+    CellStatic<D, T> c;
+    porosity_derivatives<D>(eps, nb, e0, c.ge, c.H);
+    c.vs = viscosity(ph, e0);
+    return c;
+}
+
+// Velocity correction (v_final): v = v^(1) + Delta_nu(rho v^(1) / eps) / (2 rho) from the
+// cell's own record (rho, v^(1)) and the neighbour records in `m1`.
+template <int D, typename T, bool SOLIDS>
+__device__ __forceinline__ void corrected_velocity(const P4<T> *__restrict__ m1,
+                                                   const T *__restrict__ eps,
+                                                   const uint8_t *__restrict__ mask,
+                                                   const Grid &g, const Nbr<D> &nb,
+                                                   const Rec<T> &own, const CellStatic<D, T> &cs,
+                                                   T v[3]) {
+    Rec<T> rec[3][2];
+    bool fl[3][2];
+    load_stencil<D, T, SOLIDS>(m1, eps, mask, g, nb, rec, fl);
+    T dn[3];
+    delta_nu<D, T, SOLIDS>(m1, eps, mask, g, nb, own, rec, fl, cs.ge, cs.H, cs.vs, dn);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] = own.w[a] + dv(dn[a], T(2) * own.r);
+}
+
+// Equilibria of the cell (prod_form) for the equilibrium and shifted-equilibrium arguments.
+template <int D, typename T, bool SOLIDS>
+__device__ __forceinline__ void cell_equilibria(const P4<T> *__restrict__ m2,
+                                                const T *__restrict__ eps,
+                                                const T *__restrict__ muD,
+                                                const T *__restrict__ muF,
+                                                const uint8_t *__restrict__ mask, const Grid &g,
+                                                const Phys<T> &ph, const Nbr<D> &nb,
+                                                const Rec<T> &own, const CellStatic<D, T> &cs,
+                                                ProductForm<D, T> &peq, ProductForm<D, T> &pst) {
+    T xi[3], P[3], xs[3], Ps[3];
+    forcing_args<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, cs.ge, cs.H, cs.vs, xi,
+                               P, xs, Ps);
+    const T er = own.e * own.r;
+    peq.init(er, xi, P);
+    pst.init(er, xs, Ps);
+}
+
 // ------------------------------------------------------------------------------------------
 // Kernels, one thread per cell.  A workgroup of 256 threads owns a tx x ty x 1 tile
 // (tx * ty = 256, tx = 256 for rows of 192 cells or more, so that the x-shifted accesses of the
@@ -593,30 +649,16 @@ __device__ __forceinline__ bool tile_cell(const Grid &g, const Tiling &tl, int &
     nb.init(g, x, y, z);                                             \
     const uint32_t n = nb.self();
 
-// Pass one: density (transformed_density_moment), transformed momentum
-// (transformed_momentum_moment), v^(0) (v_(0)) and the closed-form drag solve v^(1)
-// (v_(1), velocity_coefficients); writes the packed record (rho, v^(1)).
-template <int D, typename T, bool SOLIDS, int PH>
-__global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f,
-                                                 const T *__restrict__ eps,
-                                                 const T *__restrict__ muD,
-                                                 const T *__restrict__ muF,
-                                                 const uint8_t *__restrict__ mask,
-                                                 P4<T> *__restrict__ m1_out, Grid g, Tiling tl,
-                                                 Phys<T> ph) {
-    LBM_CELL_PROLOGUE(D)
+// Density (transformed_density_moment), transformed momentum (transformed_momentum_moment),
+// v^(0) (v_(0)) and the closed-form drag solve v^(1) (v_(1), velocity_coefficients) of a cell
+// from its populations fi: returns the record (rho, eps, v^(1)).
+template <int D, typename T>
+__device__ __forceinline__ Rec<T> cell_moments(const T fi[], const T *__restrict__ eps,
+                                               const T *__restrict__ muD,
+                                               const T *__restrict__ muF, const Nbr<D> &nb,
+                                               const Phys<T> &ph) {
     using L = Lat<D>;
-    if constexpr (SOLIDS) {
-        if (mask[n]) {
-            *at(m1_out, n) = pack(T(0), T(0), T(0), T(0));
-            return;
-        }
-    }
-    T fi[L::Q];
-    unroll<0, L::Q>([&](auto ii) {
-        constexpr int i = decltype(ii)::value;
-        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
-    });
+    const uint32_t n = nb.self();
     T S = T(0), Pi[3] = {T(0), T(0), T(0)};
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
@@ -643,16 +685,73 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f,
     for (int a = 0; a < D; ++a) s = s + v0[a] * v0[a];
     const T vm = sq(s);
     const T den = c1 + sq(c1 * c1 + (T(4) * c2) * vm);
-    T v1[3] = {T(0), T(0), T(0)};
+    Rec<T> q;
+    q.r = rho;
+    q.e = e;
 #pragma unroll
-    for (int a = 0; a < D; ++a) v1[a] = dv(T(2) * v0[a], den);
-    *at(m1_out, n) = pack(rho, v1[0], v1[1], v1[2]);
+    for (int a = 0; a < 3; ++a) q.w[a] = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) q.w[a] = dv(T(2) * v0[a], den);
+    return q;
 }
 
-// Velocity correction (v_final): v = v^(1) + Delta_nu(rho v^(1) / eps) / (2 rho); reads the
-// packed (rho, v^(1)) records and writes packed (rho, v) records.
+template <int D, typename T>
+__device__ __forceinline__ void store_rec(P4<T> *__restrict__ m, uint32_t n, T r, const T w[3]) {
+    *at(m, n) = pack(r, w[0], w[1], D == 3 ? w[2] : T(0));
+}
+
+// Collision (dicrete_scheme, momentum_rate with lambda = dt = 1) and streaming with halfway
+// bounce-back, in place: f^pc_i = f_i + 2 beta (f^eq_i - f_i) + (1 - beta)(f^*_i - f^eq_i).
+template <int D, typename T, bool SOLIDS, int PH>
+__device__ __forceinline__ void collide_stream(T *__restrict__ f,
+                                               const uint8_t *__restrict__ mask, const Grid &g,
+                                               const Nbr<D> &nb, const T fi[], T beta,
+                                               const ProductForm<D, T> &peq,
+                                               const ProductForm<D, T> &pst) {
+    using L = Lat<D>;
+    const T two_beta = T(2) * beta;
+    const T omb = T(1) - beta;
+    unroll<0, L::Q>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        const T feq = peq.template at<i>();
+        const T fst = pst.template at<i>();
+        const T fpc = (fi[i] + two_beta * (feq - fi[i])) + omb * (fst - feq);
+        store_pop<D, SOLIDS, PH, i>(f, mask, g, nb, fpc);
+    });
+}
+
+// Pass one of the two-pass scheme: the record (rho, v^(1)) of every cell.
+template <int D, typename T, bool SOLIDS, int PH>
+__global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f,
+                                                 const T *__restrict__ eps,
+                                                 const T *__restrict__ muD,
+                                                 const T *__restrict__ muF,
+                                                 const uint8_t *__restrict__ mask,
+                                                 P4<T> *__restrict__ m1_out, Grid g, Tiling tl,
+                                                 Phys<T> ph) {
+    LBM_CELL_PROLOGUE(D)
+    using L = Lat<D>;
+    if constexpr (SOLIDS) {
+        if (mask[n]) {
+            *at(m1_out, n) = pack(T(0), T(0), T(0), T(0));
+            return;
+        }
+    }
+    T fi[L::Q];
+    unroll<0, L::Q>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
+    });
+    const Rec<T> q = cell_moments<D>(fi, eps, muD, muF, nb, ph);
+    store_rec<D>(m1_out, n, q.r, q.w);
+}
+
+// Velocity correction (v_final) of every cell: reads the cell's own (rho, v^(1)) record from
+// `own_src` and the neighbour records from `m1` (the same buffer in the two-pass scheme; the
+// previous step's records when the lagged scheme reports moments), writes (rho, v).
 template <int D, typename T, bool SOLIDS>
-__global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ m1,
+__global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ own_src,
+                                                  const P4<T> *__restrict__ m1,
                                                   const T *__restrict__ eps,
                                                   const uint8_t *__restrict__ mask,
                                                   P4<T> *__restrict__ m2_out, Grid g, Tiling tl,
@@ -664,24 +763,14 @@ __global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ m1,
             return;
         }
     }
-    const Rec<T> own = load_rec<D>(m1, eps, n);
-    Rec<T> rec[3][2];
-    bool fl[3][2];
-    load_stencil<D, T, SOLIDS>(m1, eps, mask, g, nb, rec, fl);
-    T ge[3], H[3][3];
-    porosity_derivatives<D>(eps, nb, own.e, ge, H);
-    const Visc<T> vs = viscosity(ph, own.e);
-    T dn[3];
-    delta_nu<D, T, SOLIDS>(m1, eps, mask, g, nb, own, rec, fl, ge, H, vs, dn);
-    T v[3] = {T(0), T(0), T(0)};
-#pragma unroll
-    for (int a = 0; a < D; ++a) v[a] = own.w[a] + dv(dn[a], T(2) * own.r);
-    *at(m2_out, n) = pack(own.r, v[0], v[1], v[2]);
+    const Rec<T> own = load_rec<D>(own_src, eps, n);
+    const CellStatic<D, T> cs = cell_static<D>(eps, nb, ph, own.e);
+    T v[3];
+    corrected_velocity<D, T, SOLIDS>(m1, eps, mask, g, nb, own, cs, v);
+    store_rec<D>(m2_out, n, own.r, v);
 }
 
-// Forcing, collision (dicrete_scheme, momentum_rate with lambda = dt = 1) and streaming with
-// halfway bounce-back, in place:
-//   f^pc_i = f_i + 2 beta (f^eq_i - f_i) + (1 - beta)(f^*_i - f^eq_i).
+// Pass two of the two-pass scheme: forcing from the (rho, v) records, collision, streaming.
 template <int D, typename T, bool SOLIDS, int PH>
 __global__ __launch_bounds__(256) void k_collide(T *__restrict__ f,
                                                  const P4<T> *__restrict__ m2,
@@ -695,16 +784,10 @@ __global__ __launch_bounds__(256) void k_collide(T *__restrict__ f,
     if constexpr (SOLIDS) {
         if (mask[n]) return;
     }
-    Rec<T> own;
-    Visc<T> vs;
-    T xi[3], P[3], xs[3], Ps[3];
-    forcing_args<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, vs, xi, P, xs, Ps);
-    const T er = own.e * own.r;
+    const Rec<T> own = load_rec<D>(m2, eps, n);
+    const CellStatic<D, T> cs = cell_static<D>(eps, nb, ph, own.e);
     ProductForm<D, T> peq, pst;
-    peq.init(er, xi, P);
-    pst.init(er, xs, Ps);
-    const T two_beta = T(2) * vs.beta;
-    const T omb = T(1) - vs.beta;
+    cell_equilibria<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
     // The populations are loaded only now, after the forcing arguments: fewer registers are
     // live across the stencil work, so more waves share each SIMD.
     __builtin_amdgcn_sched_barrier(0);
@@ -713,13 +796,46 @@ __global__ __launch_bounds__(256) void k_collide(T *__restrict__ f,
         constexpr int i = decltype(ii)::value;
         fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
     });
+    collide_stream<D, T, SOLIDS, PH>(f, mask, g, nb, fi, cs.vs.beta, peq, pst);
+}
+
+// One pass of the lagged scheme: the cell's own moments, velocity correction and forcing are
+// those of the current populations, while the neighbour values entering Delta_nu, Phi^ext and
+// Phi^eta are the previous step's records (m1p: rho, v^(1); m2p: rho, v).  The cell's new
+// records go to m1n / m2n for the next step.  A steady state of this scheme is a steady state
+// of the two-pass scheme.
+template <int D, typename T, bool SOLIDS, int PH>
+__global__ __launch_bounds__(256) void k_fused(T *__restrict__ f, const P4<T> *__restrict__ m1p,
+                                               const P4<T> *__restrict__ m2p,
+                                               P4<T> *__restrict__ m1n, P4<T> *__restrict__ m2n,
+                                               const T *__restrict__ eps,
+                                               const T *__restrict__ muD,
+                                               const T *__restrict__ muF,
+                                               const uint8_t *__restrict__ mask, Grid g,
+                                               Tiling tl, Phys<T> ph) {
+    LBM_CELL_PROLOGUE(D)
+    using L = Lat<D>;
+    if constexpr (SOLIDS) {
+        if (mask[n]) {
+            *at(m1n, n) = pack(T(0), T(0), T(0), T(0));
+            *at(m2n, n) = pack(T(0), T(0), T(0), T(0));
+            return;
+        }
+    }
+    T fi[L::Q];
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        const T feq = peq.template at<i>();
-        const T fst = pst.template at<i>();
-        const T fpc = (fi[i] + two_beta * (feq - fi[i])) + omb * (fst - feq);
-        store_pop<D, SOLIDS, PH, i>(f, mask, g, nb, fpc);
+        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
     });
+    const Rec<T> own1 = cell_moments<D>(fi, eps, muD, muF, nb, ph);
+    const CellStatic<D, T> cs = cell_static<D>(eps, nb, ph, own1.e);
+    Rec<T> own2 = own1;
+    corrected_velocity<D, T, SOLIDS>(m1p, eps, mask, g, nb, own1, cs, own2.w);
+    ProductForm<D, T> peq, pst;
+    cell_equilibria<D, T, SOLIDS>(m2p, eps, muD, muF, mask, g, ph, nb, own2, cs, peq, pst);
+    collide_stream<D, T, SOLIDS, PH>(f, mask, g, nb, fi, cs.vs.beta, peq, pst);
+    store_rec<D>(m1n, n, own1.r, own1.w);
+    store_rec<D>(m2n, n, own2.r, own2.w);
 }
 
 // Initial populations, eq. (eq_bc_f_bar) with lambda = dt = 1, from the moment fields (rho, v):
@@ -743,14 +859,10 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ f,
             return;
         }
     }
-    Rec<T> own;
-    Visc<T> vs;
-    T xi[3], P[3], xs[3], Ps[3];
-    forcing_args<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, vs, xi, P, xs, Ps);
-    const T er = own.e * own.r;
+    const Rec<T> own = load_rec<D>(m2, eps, n);
+    const CellStatic<D, T> cs = cell_static<D>(eps, nb, ph, own.e);
     ProductForm<D, T> peq, pst;
-    peq.init(er, xi, P);
-    pst.init(er, xs, Ps);
+    cell_equilibria<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
         *at(plane(f, i, g.N), n) = T(1.5) * peq.template at<i>() - T(0.5) * pst.template at<i>();
@@ -773,12 +885,14 @@ __global__ __launch_bounds__(256) void k_static(const double *__restrict__ eps_i
     muF[n] = (T)(e * cf_in[n]);
 }
 
-// Initial moment records: rho = rho_init or rho0, v = v_init or 0 (0 on solid cells).
+// Initial moment records: rho = rho_init or rho0, v = v_init or 0 (0 on solid cells); m1, when
+// given, receives the same records (the lagged scheme's previous-step history at creation).
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_fill_init(const double *__restrict__ rho_in,
                                                    const double *__restrict__ v_in,
                                                    const uint8_t *__restrict__ mask,
-                                                   P4<T> *__restrict__ m2, int64_t N, double rho0) {
+                                                   P4<T> *__restrict__ m2, P4<T> *__restrict__ m1,
+                                                   int64_t N, double rho0) {
     const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (n >= N) return;
     const bool solid = mask && mask[n];
@@ -786,7 +900,9 @@ __global__ __launch_bounds__(256) void k_fill_init(const double *__restrict__ rh
     if (!solid && v_in)
 #pragma unroll
         for (int a = 0; a < D; ++a) w[a] = (T)v_in[(int64_t)a * N + n];
-    m2[n] = pack(solid ? T(0) : (T)(rho_in ? rho_in[n] : rho0), w[0], w[1], w[2]);
+    const P4<T> q = pack(solid ? T(0) : (T)(rho_in ? rho_in[n] : rho0), w[0], w[1], w[2]);
+    m2[n] = q;
+    if (m1) m1[n] = q;
 }
 
 // Natural-layout copy of the current populations (0 on solid cells).

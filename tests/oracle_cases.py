@@ -10,7 +10,7 @@ from paper_2606_29619_amd import workloads
 
 
 def channel(D, H, eps_rows, kappa_rows, cf_rows=None, nu=0.1, nu_f=None, b=1e-6, pow_=0,
-            visc_corr=1, ext_corr=1, nx=1, nz=1):
+            visc_corr=1, ext_corr=1, nx=1, nz=1, lagged=0):
     """Channel periodic in x (and z), solid rows y = 0 and y = H + 1, so the halfway walls sit at
     distance H apart and fluid row j lies at y = j - 1/2 from the lower wall."""
     ny = H + 2
@@ -30,7 +30,7 @@ def channel(D, H, eps_rows, kappa_rows, cf_rows=None, nu=0.1, nu_f=None, b=1e-6,
     cfg = oracle.OracleConfig(D=D, eps=eps, kappa=kappa, cf=cf, mask=mask,
                               nu_f=nu if nu_f is None else nu_f, nu_eff_ref=nu,
                               nu_eff_pow=pow_, b=(b, 0.0, 0.0), visc_corr=visc_corr,
-                              ext_corr=ext_corr)
+                              ext_corr=ext_corr, lagged=lagged)
     return oracle.Oracle(cfg)
 
 

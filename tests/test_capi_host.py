@@ -60,19 +60,25 @@ def test_footprint_sizes():
     p, _ = _params(shape=(4, 5, 6))
     N = 120
     fp = capi.lbm_footprint(p)
-    # populations + 3 static + rho + 3x(D components) + reduction scratch, 256-byte aligned
-    assert fp >= (27 + 3 + 1 + 9) * N * 4
-    assert fp < (27 + 3 + 1 + 9) * N * 4 + 20 * 256 + 1024 * 8 * 8 + 64
+    # populations + 3 static + two 4-value moment records + D-component residual snapshot +
+    # reduction scratch, each region 256-byte aligned
+    assert fp >= (27 + 3 + 8 + 3) * N * 4
+    assert fp < (27 + 3 + 8 + 3) * N * 4 + 20 * 256 + 1024 * 8 * 8 + 64
     p64, _ = _params(storage=capi.LBM_F64)
     assert capi.lbm_footprint(p64) > fp
     pm, _ = _params(mask=np.zeros((4, 5, 6), np.uint8))
     assert capi.lbm_footprint(pm) > fp
+    # the lagged scheme double-buffers both records
+    pl, _ = _params(scheme=capi.LBM_SCHEME_LAGGED)
+    assert capi.lbm_footprint(pl) - fp >= 8 * N * 4
+    assert capi.lbm_footprint(pl) - fp < 8 * N * 4 + 2 * 256
 
 
 @pytest.mark.parametrize("mutate,code", [
     (dict(lattice=15), capi.LBM_ERR_INVALID_ARG),
     (dict(storage=9), capi.LBM_ERR_UNSUPPORTED),
     (dict(nx=0), capi.LBM_ERR_INVALID_ARG),
+    (dict(scheme=2), capi.LBM_ERR_INVALID_ARG),
 ])
 def test_footprint_rejects_bad_shape(mutate, code):
     p, _ = _params()

@@ -260,6 +260,35 @@ def test_heterogeneous_channel_matches_bvp(visc_corr):
     assert np.ptp(rho) / rho.mean() < 5e-3     # measured 2.3e-3, falling as 1/H^2
 
 
+def test_lagged_scheme_shares_the_two_pass_steady_state():
+    """The lagged single-pass scheme (neighbour values of the Delta_nu, Phi^ext and Phi^eta
+    stencils from the previous step) has the two-pass scheme's fixed points: once the state
+    stops changing the previous step's moments are the current ones.  On Setup I of Sec. 5.2.2
+    both schemes reach the same steady profile, which solves the target problem
+    (Poiseuille_v_BVP), while their transients differ."""
+    H, nu = 48, 0.1
+    y, eps_rows = workloads.heterogeneous_channel_setup1(H)
+    kappa = 1e-2 * H * H
+    b = 8 * nu * 0.01 / H ** 2
+    two = oc.channel(2, H, eps_rows, np.full(H, kappa), nu=nu, b=b)
+    lag = oc.channel(2, H, eps_rows, np.full(H, kappa), nu=nu, b=b, lagged=1)
+    two.step(40)
+    lag.step(40)
+    _, v_two = oc.profile(two)
+    _, v_lag = oc.profile(lag)
+    transient = np.abs(v_lag - v_two).max() / np.abs(v_two).max()
+    assert transient > 1e-6, transient            # the lag is active during the transient
+    oc.run_to_steady(two, tol=1e-12, chunk=500)
+    oc.run_to_steady(lag, tol=1e-12, chunk=500)
+    _, v_two = oc.profile(two)
+    _, v_lag = oc.profile(lag)
+    assert np.abs(v_lag - v_two).max() / v_two.max() < 1e-8
+    eps_f = lambda yy: _eps_cont(yy, H)
+    muD_f = lambda yy: eps_f(yy) * nu / kappa
+    target = _solve_channel_bvp(H, eps_f, muD_f, lambda yy: 0.0 * yy, b, nu)(y)
+    assert np.abs(v_lag - target).max() / target.max() < 3e-3
+
+
 # --------------------------------------------------------------------------------------------
 # Dispersion and dissipation (Sec. 4): Phi^ext, Phi^eta, nu_eff and the drag linearisation
 # --------------------------------------------------------------------------------------------

@@ -61,9 +61,10 @@ def _print(tag, errs):
     print(tag, " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
 
 
-def _run_pair(w, steps, storage=capi.LBM_F64, chunks=1):
-    s = capi.Solver.from_workload(w, storage=storage)
-    o = _oracle_for(w)
+def _run_pair(w, steps, storage=capi.LBM_F64, chunks=1, lagged=False):
+    scheme = capi.LBM_SCHEME_LAGGED if lagged else capi.LBM_SCHEME_TWO_PASS
+    s = capi.Solver.from_workload(w, storage=storage, scheme=scheme)
+    o = _oracle_for(w, lagged=int(lagged))
     per = steps // chunks
     for _ in range(chunks):
         s.step(per)
@@ -162,6 +163,92 @@ def test_initial_state_matches():
     s, o = _run_pair(w, 0)
     errs = _field_errors(s, o)
     assert max(errs.values()) <= FP64_TOL, errs
+
+
+# --------------------------------------------------------------------------------------------
+# Lagged single-pass scheme
+# --------------------------------------------------------------------------------------------
+def _options_2d():
+    w = workloads.random_porosity_2d(nx=67, ny=29, seed=4, ell=4.0, nu=0.03, b=2e-4)
+    w.RT = 0.25
+    w.eta_eff = 0.05
+    w.nu_eff_pow = 1
+    y, x = np.meshgrid(np.arange(29), np.arange(67), indexing="ij")
+    w.v_init = np.stack([0.01 * np.sin(2 * np.pi * y / 29), 0.005 * np.cos(2 * np.pi * x / 67)])[:, None]
+    w.rho_init = (1 + 0.002 * np.cos(2 * np.pi * x / 67))[None]
+    m = np.zeros(w.shape, np.uint8)
+    m[0, 10:14, 20:31] = 1
+    w.mask = m
+    return w
+
+
+def _solids_3d(shape=(9, 13, 70)):
+    w = workloads.random_porosity_3d(shape=shape, seed=11, ell=2.5, nu=0.04, b=3e-4)
+    w.eta_eff = 0.02
+    m = np.zeros(shape, np.uint8)
+    m[2:5, 3:7, 10:20] = 1
+    m[:, 0, 40:45] = 1
+    m[0, :, 63:66] = 1
+    w.mask = m
+    return w
+
+
+@pytest.mark.parametrize("case", ["d2q9_options", "d3q27_solids"])
+def test_lagged_scheme_matches_oracle(case):
+    """LBM_SCHEME_LAGGED against the oracle's lagged mode, FP64: the single fused kernel (own
+    moments current, stencil neighbours from the previous step, history double-buffered) and
+    the lagged velocity correction of lbm_moments, with every option and solid cells."""
+    w = _options_2d() if case == "d2q9_options" else _solids_3d()
+    s, o = _run_pair(w, 30, chunks=3, lagged=True)
+    errs = _field_errors(s, o)
+    _print(f"lagged {case}:", errs)
+    assert max(errs.values()) <= FP64_TOL, errs
+    # the lagged and two-pass transients differ by far more than the tolerance
+    t = capi.Solver.from_workload(w, storage=capi.LBM_F64)
+    t.step(30)
+    _, v_two = t.moments(torch.float64)
+    _, v_lag = s.moments(torch.float64)
+    assert _rel(v_lag.cpu().numpy(), v_two.cpu().numpy()) > 1e-9
+
+
+def test_lagged_restart_takes_a_two_pass_step():
+    """After lbm_set_populations the lagged history restarts: the next step is a two-pass step,
+    as in the oracle, and the run continues lagged from there."""
+    w = _solids_3d(shape=(6, 7, 9))
+    s, o = _run_pair(w, 5, lagged=True)
+    s.set_populations(s.populations(), step=5)
+    o.set_populations(o.populations(), t=5)
+    s.step(4)
+    o.step(4)
+    errs = _field_errors(s, o)
+    _print("lagged restart:", errs)
+    assert max(errs.values()) <= FP64_TOL, errs
+    assert s.step_count == 9
+
+
+def test_lagged_statistics_match_oracle():
+    w = workloads.random_porosity_2d(nx=40, ny=30, seed=8, ell=4.0, nu=0.05, b=1e-4)
+    s, o = _run_pair(w, 0, lagged=True)
+    s.residual()
+    o.stats()
+    for _ in range(2):
+        s.step(25)
+        o.step(25)
+        g, r = s.residual(), o.stats()
+        assert abs(g.mass - r["mass"]) <= 1e-13 * r["mass"]
+        assert abs(g.vmax - r["vmax"]) <= 1e-12 * r["vmax"]
+        assert abs(g.residual - r["residual"]) <= 1e-10 * r["residual"]
+
+
+def test_lagged_fp32_tracks_fp64_oracle():
+    """FP32 lagged scheme against the FP64 lagged oracle on the random-porosity recipe (32^3,
+    100 steps), with the tolerances of the two-pass FP32 case."""
+    w = workloads.random_porosity_3d(shape=(32, 32, 32), seed=0, ell=16.0)
+    s, o = _run_pair(w, 100, storage=capi.LBM_F32, lagged=True)
+    errs = _field_errors(s, o)
+    _print("lagged fp32 vs fp64 oracle:", errs)
+    assert errs["f"] < 3e-5 and errs["rho"] < 5e-5
+    assert max(errs[k] for k in ("v0", "v1", "v2")) < 2e-3
 
 
 # --------------------------------------------------------------------------------------------
