@@ -26,30 +26,31 @@ HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E, published
 METRIC = "MLUPS & % HBM roofline (D3Q27); served MLUPS + p50/p99 time-to-steady"
 
 
-def kernel_bytes_per_cell(Q, D, s):
-    """Algorithmic HBM bytes per cell of each kernel (values each kernel must move once):
+def kernel_bytes_per_cell(Q, D, sp, s):
+    """Algorithmic HBM bytes per cell of each kernel (values each kernel must move once), with
+    sp bytes per population and s per static-field or moment value:
     moments: read Q pops + eps, mu_D, mu_F; write rho and v^(1) (D+1);
     velocity correction: read rho, v^(1), eps; write v (D);
     collide-stream: read Q pops, rho, v, eps, mu_D, mu_F; write Q pops."""
     return {
-        "moments": (Q + 3 + (D + 1)) * s,
+        "moments": Q * sp + (3 + (D + 1)) * s,
         "vcorrect": ((D + 1) + 1 + D) * s,
-        "collide": (Q + (D + 1) + 3 + Q) * s,
+        "collide": 2 * Q * sp + ((D + 1) + 3) * s,
     }
 
 
-def lagged_bytes_per_cell(Q, D, s):
+def lagged_bytes_per_cell(Q, D, sp, s):
     """Single pass of the lagged scheme: read Q pops, 3 static fields and the previous step's
     rho, v^(1), v; write Q pops and the new rho, v^(1), v."""
-    return (Q + 3 + (2 * D + 1) + Q + (2 * D + 1)) * s
+    return 2 * Q * sp + (3 + 2 * (2 * D + 1)) * s
 
 
-def method_bytes_per_cell(Q, D, s, lagged=False):
+def method_bytes_per_cell(Q, D, sp, s, lagged=False):
     """Per-step minimum of the method.  Two-pass: pass one reads Q pops + 3 static fields and
     writes rho, v^(1); pass two reads Q pops, rho, v, 3 static fields and writes Q pops."""
     if lagged:
-        return lagged_bytes_per_cell(Q, D, s)
-    return (Q + 3 + (D + 1)) * s + (Q + (D + 1) + 3 + Q) * s
+        return lagged_bytes_per_cell(Q, D, sp, s)
+    return 3 * Q * sp + (3 + (D + 1) + (D + 1) + 3) * s
 
 
 def source_hash():
@@ -102,7 +103,10 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="cells per side")
-    ap.add_argument("--storage", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--storage", choices=["f32", "f64", "f16", "bf16"], default="f32",
+                    help="population storage; f16/bf16 are the shifted 16-bit forms (FP32 math)")
+    ap.add_argument("--shift", choices=["weights", "porous"], default="porous",
+                    help="shift of the 16-bit forms")
     ap.add_argument("--scheme", choices=["two-pass", "lagged"], default="two-pass",
                     help="two-pass: the method as written (headline); lagged: single fused pass "
                          "with previous-step neighbour moments")
@@ -126,11 +130,14 @@ def main():
     torch.cuda.set_device(0)
     n = args.n
     w = workloads.random_porosity_3d(n=n, seed=0, ell=16.0, steps=args.steps)
-    storage = capi.LBM_F32 if args.storage == "f32" else capi.LBM_F64
-    s_bytes = 4 if args.storage == "f32" else 8
+    storage = {"f32": capi.LBM_F32, "f64": capi.LBM_F64, "f16": capi.LBM_F16_SHIFTED,
+               "bf16": capi.LBM_BF16_SHIFTED}[args.storage]
+    s_bytes = 8 if args.storage == "f64" else 4
+    sp_bytes = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[args.storage]
+    shift = capi.LBM_SHIFT_POROUS if args.shift == "porous" else capi.LBM_SHIFT_WEIGHTS
     lagged = args.scheme == "lagged"
     solver = capi.Solver.from_workload(
-        w, storage=storage,
+        w, storage=storage, shift=shift,
         scheme=capi.LBM_SCHEME_LAGGED if lagged else capi.LBM_SCHEME_TWO_PASS)
     N = w.cells
     print(f"[bench] created {w.name}, {args.storage}, workspace {solver.nbytes / 2**30:.2f} GiB",
@@ -153,10 +160,10 @@ def main():
 
     Q, D = 27, 3
     if lagged:
-        kb = {"fused": lagged_bytes_per_cell(Q, D, s_bytes)}
+        kb = {"fused": lagged_bytes_per_cell(Q, D, sp_bytes, s_bytes)}
         avg_ms = {"fused": kms[2] / args.steps}
     else:
-        kb = kernel_bytes_per_cell(Q, D, s_bytes)
+        kb = kernel_bytes_per_cell(Q, D, sp_bytes, s_bytes)
         avg_ms = {"moments": kms[0] / args.steps, "vcorrect": kms[1] / args.steps,
                   "collide": kms[2] / args.steps}
     dom = max(avg_ms, key=avg_ms.get)
@@ -164,7 +171,7 @@ def main():
     achieved = algo / (avg_ms[dom] * 1e-3) / 1e9
     src = source_hash()
     traffic = traffic_from_profiles(dom, N, src)
-    step_bytes = method_bytes_per_cell(Q, D, s_bytes, lagged)
+    step_bytes = method_bytes_per_cell(Q, D, sp_bytes, s_bytes, lagged)
     kernels = {k: {"avg_ms": round(avg_ms[k], 4), "bytes_per_cell": kb[k],
                    "achieved_GBps": round(kb[k] * N / (avg_ms[k] * 1e-3) / 1e9, 1)}
                for k in avg_ms}
@@ -179,12 +186,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.storage,
+        "dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"random-porosity D3Q27 {n}^3 periodic box, seed 0, "
                                f"correlation length 16, phi in (0.3,1), Kozeny-Carman K (d=2), "
                                f"C_F=0.55/sqrt(K), nu=0.01, b=1e-6 x", "lattice": "D3Q27",
-                   "cells": N, "storage": args.storage, "scheme": args.scheme},
+                   "cells": N, "scheme": args.scheme,
+                   "storage": args.storage if sp_bytes != 2 else
+                   f"{args.storage} shifted ({args.shift})"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),

@@ -50,9 +50,29 @@ extern "C" {
 #define LBM_D2Q9 9
 #define LBM_D3Q27 27
 
-/* Storage and arithmetic type of the populations, moments and static fields. */
+/*
+ * Storage of the populations.  LBM_F64 and LBM_F32 store f-bar and compute in that type
+ * (static fields and moments too).  The shifted 16-bit forms store, per population,
+ * (f-bar_i - sigma_i) * 2^12 / w_i in FP16 or BF16 (w_i: lattice weight, the rest state of
+ * the product-form equilibrium, eq. prod_form), with sigma_i chosen by lbm_params.shift; every
+ * value is decoded to FP32, collided in FP32 and re-encoded (round to nearest even); static
+ * fields and moment records are FP32, statistics FP64.
+ */
 #define LBM_F64 0
 #define LBM_F32 1
+#define LBM_F16_SHIFTED 2
+#define LBM_BF16_SHIFTED 3
+
+/*
+ * Shift sigma_i of the 16-bit storage forms.
+ * LBM_SHIFT_WEIGHTS: sigma_i = rho0 w_i, the lattice weights.
+ * LBM_SHIFT_POROUS:  sigma_i = rho0 eps(src) w_i, src being the cell whose collision produced
+ *   the value (the upstream cell x - c_i, or x itself after a bounce-back).  A porous cell at
+ *   rest holds eps rho0 w_i (eq. prod_form with v = 0), so this shift removes the porosity
+ *   from the stored deviation.
+ */
+#define LBM_SHIFT_WEIGHTS 0
+#define LBM_SHIFT_POROUS 1
 
 /*
  * Time-stepping scheme.
@@ -83,8 +103,9 @@ extern "C" {
  */
 typedef struct lbm_params {
     int lattice;          /* LBM_D2Q9 or LBM_D3Q27 */
-    int storage;          /* LBM_F64 or LBM_F32 */
+    int storage;          /* LBM_F64, LBM_F32, LBM_F16_SHIFTED or LBM_BF16_SHIFTED */
     int scheme;           /* LBM_SCHEME_TWO_PASS or LBM_SCHEME_LAGGED */
+    int shift;            /* LBM_SHIFT_WEIGHTS or LBM_SHIFT_POROUS (16-bit storage only) */
     int nx, ny, nz;       /* >= 1; nz must be 1 for D2Q9 */
     double RT;            /* lattice temperature RT > 0 (1/3 is the lattice reference) */
     double nu_f;          /* fluid viscosity in the Darcy coefficient mu_D = eps nu_f / kappa
@@ -124,7 +145,8 @@ typedef struct lbm_solver lbm_solver;
 
 /*
  * Bytes of device workspace lbm_create needs for these parameters (pure host computation, no
- * device work).  Only lattice, storage, scheme, nx, ny, nz and whether mask is non-NULL are read.
+ * device work).  Only lattice, storage, scheme, shift, nx, ny, nz and whether mask is non-NULL
+ * are read.
  * Errors: LBM_ERR_INVALID_ARG for NULL pointers or bad lattice, storage or dimensions.
  */
 LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes);

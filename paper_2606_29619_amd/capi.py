@@ -29,6 +29,10 @@ LBM_D2Q9 = 9
 LBM_D3Q27 = 27
 LBM_F64 = 0
 LBM_F32 = 1
+LBM_F16_SHIFTED = 2
+LBM_BF16_SHIFTED = 3
+LBM_SHIFT_WEIGHTS = 0
+LBM_SHIFT_POROUS = 1
 LBM_SCHEME_TWO_PASS = 0
 LBM_SCHEME_LAGGED = 1
 LBM_DTYPE_F64 = 0
@@ -42,7 +46,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 class lbm_params(ctypes.Structure):
     _fields_ = [
         ("lattice", ctypes.c_int), ("storage", ctypes.c_int), ("scheme", ctypes.c_int),
-        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("shift", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
         ("RT", ctypes.c_double), ("nu_f", ctypes.c_double), ("nu_eff_ref", ctypes.c_double),
         ("nu_eff_pow", ctypes.c_int), ("eta_eff", ctypes.c_double),
         ("b", ctypes.c_double * 3), ("rho0", ctypes.c_double),
@@ -182,7 +186,7 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
                 nu_f: float = 1.0 / 6.0, nu_eff_ref: float = 1.0 / 6.0, nu_eff_pow: int = 0,
                 eta_eff: float = math.nan, b=(0.0, 0.0, 0.0), rho0: float = 1.0,
                 rho_init: Optional[np.ndarray] = None, v_init: Optional[np.ndarray] = None,
-                scheme: int = LBM_SCHEME_TWO_PASS):
+                scheme: int = LBM_SCHEME_TWO_PASS, shift: int = LBM_SHIFT_WEIGHTS):
     """Build an lbm_params from numpy arrays shaped [nz, ny, nx]; returns (params, keepalive)."""
     eps = np.ascontiguousarray(eps, dtype=np.float64)
     if eps.ndim == 2:
@@ -198,7 +202,7 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
         return a.ctypes.data_as(_dp)
 
     p = lbm_params()
-    p.lattice, p.storage, p.scheme = lattice, storage, scheme
+    p.lattice, p.storage, p.scheme, p.shift = lattice, storage, scheme, shift
     p.nx, p.ny, p.nz = nx, ny, nz
     p.RT, p.nu_f, p.nu_eff_ref, p.nu_eff_pow, p.eta_eff = RT, nu_f, nu_eff_ref, nu_eff_pow, eta_eff
     for a in range(3):
@@ -228,6 +232,7 @@ class Solver:
         self.Q = params.lattice
         self.shape = (params.nz, params.ny, params.nx)
         self.N = params.nx * params.ny * params.nz
+        # dtype of exported populations and moments: the arithmetic type
         self.dtype = torch.float64 if params.storage == LBM_F64 else torch.float32
         self.nbytes = lbm_footprint(params)
         self.device = torch.device(device)
@@ -238,11 +243,12 @@ class Solver:
         del keepalive
 
     @classmethod
-    def from_workload(cls, w, storage: int = LBM_F32, scheme: int = LBM_SCHEME_TWO_PASS, **kw):
+    def from_workload(cls, w, storage: int = LBM_F32, scheme: int = LBM_SCHEME_TWO_PASS,
+                      shift: int = LBM_SHIFT_WEIGHTS, **kw):
         p, keep = make_params(w.lattice, storage, w.eps, w.kappa, w.forch, w.mask, RT=w.RT,
                               nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow,
                               eta_eff=w.eta_eff, b=w.b, rho0=w.rho0, rho_init=w.rho_init,
-                              v_init=w.v_init, scheme=scheme)
+                              v_init=w.v_init, scheme=scheme, shift=shift)
         return cls(p, keep, **kw)
 
     def close(self):

@@ -52,7 +52,8 @@ struct Layout {
     size_t f, eps, muD, muF, mask, m1[2], m2[2], vsnap, part, res, total;
 };
 
-Layout make_layout(int Q, int D, size_t N, size_t s, bool solids, bool lagged) {
+// sp: bytes per population value; s: bytes per value of the static fields and moment records.
+Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool solids, bool lagged) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -60,7 +61,8 @@ Layout make_layout(int Q, int D, size_t N, size_t s, bool solids, bool lagged) {
         off = align256(off + bytes);
         return o;
     };
-    L.f = take((size_t)Q * N * s);
+    // the population region also stages the FP64 inputs at creation (up to 4 arrays of N)
+    L.f = take(std::max((size_t)Q * N * sp, 4 * N * sizeof(double)));
     L.eps = take(N * s);
     L.muD = take(N * s);
     L.muF = take(N * s);
@@ -95,8 +97,9 @@ struct lbm_solver {
     int scheme;
     int cur;        // record pair that holds the previous step's moments (lagged scheme)
     bool have_prev; // whether that pair is valid (lagged scheme)
-    double RT, nu_f, nu_eff_ref, eta_eff, b[3];
+    double RT, nu_f, nu_eff_ref, eta_eff, b[3], rho0;
     int nu_eff_pow;
+    int shift;          // 16-bit population shift (LBM_SHIFT_*)
     lbm::Tiling tiles;  // 256-cell tiles, blocked, in XCD-contiguous ranges
 };
 
@@ -113,6 +116,8 @@ lbm::Phys<T> phys_of(const lbm_solver *h) {
     ph.two_over_D = (T)(2.0 / (double)h->D);
     for (int a = 0; a < 3; ++a) ph.b[a] = (T)h->b[a];
     ph.nu_pow = h->nu_eff_pow;
+    ph.rho0 = (T)h->rho0;
+    ph.shift_porous = h->shift == LBM_SHIFT_POROUS ? 1 : 0;
     return ph;
 }
 
@@ -153,12 +158,13 @@ const uint8_t *mask_ptr(const lbm_solver *h) {
     return h->solids ? reinterpret_cast<const uint8_t *>(h->ws + h->L.mask) : nullptr;
 }
 
-// ---- kernel launchers, dispatched on (lattice, type, solids, phase) -----------------------
-template <int D, typename T, bool S, int PH>
+// ---- kernel launchers, dispatched on (lattice, arithmetic type T, population storage type P,
+// solids, phase) ------------------------------------------------------------------------------
+template <int D, typename T, typename P, bool S, int PH>
 void launch_moments(const lbm_solver *h, size_t m1_out) {
     auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_moments<D, T, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<const T>(h, h->L.f), ws_ptr<const T>(h, h->L.eps),
+    hipLaunchKernelGGL((lbm::k_moments<D, T, P, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
+                       ws_ptr<const P>(h, h->L.f), ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
                        ws_ptr<lbm::P4<T>>(h, m1_out), grid_of(h), h->tiles, ph);
 }
@@ -172,117 +178,138 @@ void launch_vcorrect(const lbm_solver *h, size_t own_src, size_t m1, size_t m2_o
                        grid_of(h), h->tiles, ph);
 }
 
-template <int D, typename T, bool S, int PH>
+template <int D, typename T, typename P, bool S, int PH>
 void launch_collide(const lbm_solver *h, size_t m2) {
     auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_collide<D, T, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
+    hipLaunchKernelGGL((lbm::k_collide<D, T, P, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
+                       ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
                        ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
                        grid_of(h), h->tiles, ph);
 }
 
-template <int D, typename T, bool S, int PH>
+template <int D, typename T, typename P, bool S, int PH>
 void launch_fused(const lbm_solver *h, int prev, int next) {
     auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_fused<D, T, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m1[prev]),
+    hipLaunchKernelGGL((lbm::k_fused<D, T, P, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
+                       ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m1[prev]),
                        ws_ptr<const lbm::P4<T>>(h, h->L.m2[prev]),
                        ws_ptr<lbm::P4<T>>(h, h->L.m1[next]), ws_ptr<lbm::P4<T>>(h, h->L.m2[next]),
                        ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
                        ws_ptr<const T>(h, h->L.muF), mask_ptr(h), grid_of(h), h->tiles, ph);
 }
 
-template <int D, typename T, bool S>
+template <int D, typename T, typename P, bool S>
 void launch_init(const lbm_solver *h) {
     auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_init<D, T, S>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m2[0]),
+    hipLaunchKernelGGL((lbm::k_init<D, T, P, S>), cell_tiles(h), dim3(256), 0, h->stream,
+                       ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m2[0]),
                        ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
                        grid_of(h), h->tiles, ph);
 }
 
-template <int D, typename T, bool S, int PH, typename O>
+template <int D, typename T, typename P, bool S, int PH, typename O>
 void launch_export(const lbm_solver *h, O *out) {
-    hipLaunchKernelGGL((lbm::k_export<D, T, S, PH, O>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<const T>(h, h->L.f), mask_ptr(h), out, grid_of(h), h->tiles);
+    hipLaunchKernelGGL((lbm::k_export<D, T, P, S, PH, O>), cell_tiles(h), dim3(256), 0,
+                       h->stream, ws_ptr<const P>(h, h->L.f), mask_ptr(h),
+                       ws_ptr<const T>(h, h->L.eps), out, grid_of(h), h->tiles, phys_of<T>(h));
 }
 
-template <int D, typename T, bool S, int PH>
+template <int D, typename T, typename P, bool S, typename I>
+void launch_import(const lbm_solver *h, const I *in) {
+    hipLaunchKernelGGL((lbm::k_import<D, T, P, S, I>), cell_tiles(h), dim3(256), 0, h->stream,
+                       ws_ptr<P>(h, h->L.f), in, mask_ptr(h), ws_ptr<const T>(h, h->L.eps),
+                       grid_of(h), h->tiles, phys_of<T>(h));
+}
+
+template <int D, typename T, typename P, bool S, int PH>
 void launch_stats(const lbm_solver *h, size_t m2) {
-    hipLaunchKernelGGL((lbm::k_stats<D, T, S, PH>), dim3(lbm::kStatsBlocks), dim3(256), 0,
-                       h->stream, ws_ptr<const T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
-                       ws_ptr<T>(h, h->L.vsnap), mask_ptr(h),
-                       ws_ptr<double>(h, h->L.part), grid_of(h));
+    hipLaunchKernelGGL((lbm::k_stats<D, T, P, S, PH>), dim3(lbm::kStatsBlocks), dim3(256), 0,
+                       h->stream, ws_ptr<const P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
+                       ws_ptr<T>(h, h->L.vsnap), mask_ptr(h), ws_ptr<const T>(h, h->L.eps),
+                       ws_ptr<double>(h, h->L.part), grid_of(h), phys_of<T>(h));
 }
 
-// Calls fn.template operator()<D, T, S, PH>() for the handle's configuration.
+// Calls fn.template operator()<D, T, P, S, PH>() for the handle's configuration.
 template <typename F>
 void dispatch(const lbm_solver *h, F &&fn) {
     const bool s = h->solids;
     const int ph = h->phase;
-#define LBM_DISPATCH_T(DD, TT)                                       \
+#define LBM_DISPATCH_T(DD, TT, PP)                                   \
     if (s) {                                                         \
-        if (ph) fn.template operator()<DD, TT, true, 1>();           \
-        else fn.template operator()<DD, TT, true, 0>();              \
+        if (ph) fn.template operator()<DD, TT, PP, true, 1>();       \
+        else fn.template operator()<DD, TT, PP, true, 0>();          \
     } else {                                                         \
-        if (ph) fn.template operator()<DD, TT, false, 1>();          \
-        else fn.template operator()<DD, TT, false, 0>();             \
+        if (ph) fn.template operator()<DD, TT, PP, false, 1>();      \
+        else fn.template operator()<DD, TT, PP, false, 0>();         \
     }
-    if (h->D == 2) {
-        if (h->storage == LBM_F64) { LBM_DISPATCH_T(2, double) }
-        else { LBM_DISPATCH_T(2, float) }
-    } else {
-        if (h->storage == LBM_F64) { LBM_DISPATCH_T(3, double) }
-        else { LBM_DISPATCH_T(3, float) }
+#define LBM_DISPATCH_D(DD)                                                        \
+    switch (h->storage) {                                                         \
+    case LBM_F64: { LBM_DISPATCH_T(DD, double, double) } break;                   \
+    case LBM_F32: { LBM_DISPATCH_T(DD, float, float) } break;                     \
+    case LBM_F16_SHIFTED: { LBM_DISPATCH_T(DD, float, _Float16) } break;          \
+    default: { LBM_DISPATCH_T(DD, float, __bf16) } break;                         \
     }
+    if (h->D == 2) { LBM_DISPATCH_D(2) }
+    else { LBM_DISPATCH_D(3) }
+#undef LBM_DISPATCH_D
 #undef LBM_DISPATCH_T
 }
 
 struct MomentsPass {
     const lbm_solver *h;
     size_t m1_out;
-    template <int D, typename T, bool S, int PH>
-    void operator()() { launch_moments<D, T, S, PH>(h, m1_out); }
+    template <int D, typename T, typename P, bool S, int PH>
+    void operator()() { launch_moments<D, T, P, S, PH>(h, m1_out); }
 };
 struct VcorrectPass {
     const lbm_solver *h;
     size_t own_src, m1, m2_out;
-    template <int D, typename T, bool S, int PH>
+    template <int D, typename T, typename P, bool S, int PH>
     void operator()() { launch_vcorrect<D, T, S>(h, own_src, m1, m2_out); }
 };
 struct CollidePass {
     const lbm_solver *h;
     size_t m2;
-    template <int D, typename T, bool S, int PH>
-    void operator()() { launch_collide<D, T, S, PH>(h, m2); }
+    template <int D, typename T, typename P, bool S, int PH>
+    void operator()() { launch_collide<D, T, P, S, PH>(h, m2); }
 };
 struct FusedPass {
     const lbm_solver *h;
     int prev, next;
-    template <int D, typename T, bool S, int PH>
-    void operator()() { launch_fused<D, T, S, PH>(h, prev, next); }
+    template <int D, typename T, typename P, bool S, int PH>
+    void operator()() { launch_fused<D, T, P, S, PH>(h, prev, next); }
 };
 struct InitPass {
     const lbm_solver *h;
-    template <int D, typename T, bool S, int PH>
-    void operator()() { launch_init<D, T, S>(h); }
+    template <int D, typename T, typename P, bool S, int PH>
+    void operator()() { launch_init<D, T, P, S>(h); }
 };
 struct StatsPass {
     const lbm_solver *h;
     size_t m2;
-    template <int D, typename T, bool S, int PH>
-    void operator()() { launch_stats<D, T, S, PH>(h, m2); }
+    template <int D, typename T, typename P, bool S, int PH>
+    void operator()() { launch_stats<D, T, P, S, PH>(h, m2); }
 };
 struct ExportPass {
     const lbm_solver *h;
     void *out;
     int dtype;
-    template <int D, typename T, bool S, int PH>
+    template <int D, typename T, typename P, bool S, int PH>
     void operator()() {
-        if (dtype == LBM_DTYPE_F64) launch_export<D, T, S, PH, double>(h, (double *)out);
-        else launch_export<D, T, S, PH, float>(h, (float *)out);
+        if (dtype == LBM_DTYPE_F64) launch_export<D, T, P, S, PH, double>(h, (double *)out);
+        else launch_export<D, T, P, S, PH, float>(h, (float *)out);
+    }
+};
+struct ImportPass {
+    const lbm_solver *h;
+    const void *in;
+    int dtype;
+    template <int D, typename T, typename P, bool S, int PH>
+    void operator()() {
+        if (dtype == LBM_DTYPE_F64) launch_import<D, T, P, S, double>(h, (const double *)in);
+        else launch_import<D, T, P, S, float>(h, (const float *)in);
     }
 };
 
@@ -334,14 +361,17 @@ int check_handle(const lbm_solver *h) {
     return LBM_OK;
 }
 
-int validate_shape(const lbm_params *p, int *D, int *Q, size_t *s, int64_t *N) {
+int validate_shape(const lbm_params *p, int *D, int *Q, size_t *sp, size_t *s, int64_t *N) {
     if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
     if (p->lattice == LBM_D2Q9) { *D = 2; *Q = 9; }
     else if (p->lattice == LBM_D3Q27) { *D = 3; *Q = 27; }
     else return fail(LBM_ERR_INVALID_ARG, "lattice must be LBM_D2Q9 or LBM_D3Q27, got %d", p->lattice);
-    if (p->storage == LBM_F64) *s = 8;
-    else if (p->storage == LBM_F32) *s = 4;
+    if (p->storage == LBM_F64) { *sp = 8; *s = 8; }
+    else if (p->storage == LBM_F32) { *sp = 4; *s = 4; }
+    else if (p->storage == LBM_F16_SHIFTED || p->storage == LBM_BF16_SHIFTED) { *sp = 2; *s = 4; }
     else return fail(LBM_ERR_UNSUPPORTED, "storage %d is not supported", p->storage);
+    if (p->shift != LBM_SHIFT_WEIGHTS && p->shift != LBM_SHIFT_POROUS)
+        return fail(LBM_ERR_INVALID_ARG, "shift must be LBM_SHIFT_WEIGHTS or LBM_SHIFT_POROUS, got %d", p->shift);
     if (p->scheme != LBM_SCHEME_TWO_PASS && p->scheme != LBM_SCHEME_LAGGED)
         return fail(LBM_ERR_INVALID_ARG, "scheme must be LBM_SCHEME_TWO_PASS or LBM_SCHEME_LAGGED, got %d", p->scheme);
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
@@ -385,12 +415,12 @@ LBM_API int lbm_lattice_info(int lattice, int *c_out, int *opp_out) {
 
 LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes) {
     int D, Q;
-    size_t s;
+    size_t sp, s;
     int64_t N;
     if (!workspace_bytes) return fail(LBM_ERR_INVALID_ARG, "workspace_bytes is NULL");
-    int rc = validate_shape(p, &D, &Q, &s, &N);
+    int rc = validate_shape(p, &D, &Q, &sp, &s, &N);
     if (rc) return rc;
-    *workspace_bytes = make_layout(Q, D, (size_t)N, s, p->mask != nullptr, p->scheme == LBM_SCHEME_LAGGED).total;
+    *workspace_bytes = make_layout(Q, D, (size_t)N, sp, s, p->mask != nullptr, p->scheme == LBM_SCHEME_LAGGED).total;
     return LBM_OK;
 }
 
@@ -399,9 +429,9 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     if (!out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     int D, Q;
-    size_t s;
+    size_t sp, s;
     int64_t N;
-    int rc = validate_shape(p, &D, &Q, &s, &N);
+    int rc = validate_shape(p, &D, &Q, &sp, &s, &N);
     if (rc) return rc;
     if (!(is_finite(p->RT) && p->RT > 0)) return fail(LBM_ERR_INVALID_ARG, "RT must be finite and > 0");
     if (!(is_finite(p->nu_f) && p->nu_f >= 0)) return fail(LBM_ERR_INVALID_ARG, "nu_f must be finite and >= 0");
@@ -434,7 +464,7 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     }
     if (!any_fluid) return fail(LBM_ERR_INVALID_ARG, "no fluid cell");
     const bool solids = p->mask != nullptr;
-    const Layout L = make_layout(Q, D, (size_t)N, s, solids, p->scheme == LBM_SCHEME_LAGGED);
+    const Layout L = make_layout(Q, D, (size_t)N, sp, s, solids, p->scheme == LBM_SCHEME_LAGGED);
     if (!dev_workspace) return fail(LBM_ERR_INVALID_ARG, "dev_workspace is NULL");
     if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
         return fail(LBM_ERR_WORKSPACE, "dev_workspace must be 256-byte aligned");
@@ -465,14 +495,16 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->nu_eff_ref = p->nu_eff_ref;
     h->nu_eff_pow = p->nu_eff_pow;
     h->eta_eff = p->eta_eff;
+    h->rho0 = p->rho0;
+    h->shift = p->shift;
     for (int a = 0; a < 3; ++a) h->b[a] = a < D ? p->b[a] : 0.0;
 
     auto cleanup = [&](int code) {
         delete h;
         return code;
     };
-    // Stage the FP64 input fields in the population region (Q*N*s >= 3*N*8 for every lattice
-    // and storage), derive the static fields, then stage the initial moments the same way.
+    // Stage the FP64 input fields in the population region (sized for 4 FP64 arrays), derive
+    // the static fields, then stage the initial moments the same way.
     const size_t NB = (size_t)N * sizeof(double);
     double *st = ws_ptr<double>(h, L.f);
     hipError_t e;
@@ -637,14 +669,8 @@ LBM_API int lbm_set_populations(lbm_solver *h, const void *dev_in, int dtype, in
     if (!dev_in) return fail(LBM_ERR_INVALID_ARG, "dev_in is NULL");
     if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_INVALID_ARG, "bad dtype");
     if (step < 0) return fail(LBM_ERR_INVALID_ARG, "negative step");
-    const int64_t total = (int64_t)h->Q * h->N;
-    if (h->storage == LBM_F64) {
-        if (dtype == LBM_DTYPE_F64) hipLaunchKernelGGL((lbm::k_import<double, double>), flat_grid(total), dim3(256), 0, h->stream, ws_ptr<double>(h, h->L.f), (const double *)dev_in, total);
-        else hipLaunchKernelGGL((lbm::k_import<double, float>), flat_grid(total), dim3(256), 0, h->stream, ws_ptr<double>(h, h->L.f), (const float *)dev_in, total);
-    } else {
-        if (dtype == LBM_DTYPE_F64) hipLaunchKernelGGL((lbm::k_import<float, double>), flat_grid(total), dim3(256), 0, h->stream, ws_ptr<float>(h, h->L.f), (const double *)dev_in, total);
-        else hipLaunchKernelGGL((lbm::k_import<float, float>), flat_grid(total), dim3(256), 0, h->stream, ws_ptr<float>(h, h->L.f), (const float *)dev_in, total);
-    }
+    h->phase = 0;  // the import writes the natural layout
+    dispatch(h, ImportPass{h, dev_in, dtype});
     LAUNCH_CHECK();
     h->phase = 0;
     h->step = step;

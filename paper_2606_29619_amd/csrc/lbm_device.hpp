@@ -84,8 +84,10 @@ struct Phys {
     T eta;         // effective bulk viscosity (Phi^eta)
     T two_over_D;  // 2 / D
     T b[3];        // body acceleration
+    T rho0;        // reference density of the 16-bit population shift
     int nu_pow;    // -1, 0, 1
     int eta_on;    // Phi^eta switched on
+    int shift_porous;  // 16-bit shift base rho0 eps(src) (1) or rho0 (0)
 };
 
 // ---- arithmetic policy -------------------------------------------------------------------
@@ -186,10 +188,110 @@ struct Nbr {
 };
 
 // ------------------------------------------------------------------------------------------
+// Population storage formats.  FP64 and FP32 slots hold f-bar itself.  The 16-bit formats
+// (FP16, BF16) hold the deviation from a shift, scaled per direction,
+//     slot = (f-bar_i - sigma_i) * 2^k_i,    sigma_i = base * w_i,
+// with base = rho0 (shift by the lattice weights) or base = rho0 eps(src) (porous shift), where
+// src is the cell whose collision produced the value: a resting porous cell holds eps rho0 w_i,
+// so the porous shift leaves only the flow's own deviation to the 16-bit value.  2^k_i is the
+// largest power of two not above 2^12 / w_i: deviations down to ~1e-5 of a weight stay in the
+// FP16 normal range, and the scaling is exact, so a value decoded in FP64 re-encodes to the
+// same bits.  Arithmetic stays FP32.
+// ------------------------------------------------------------------------------------------
+template <typename P>
+struct PopFmt {
+    static constexpr bool shifted = false;
+};
+template <>
+struct PopFmt<_Float16> {
+    static constexpr bool shifted = true;
+    __device__ static __forceinline__ float dec(_Float16 h) { return (float)h; }
+    __device__ static __forceinline__ _Float16 enc(float x) { return (_Float16)x; }
+};
+template <>
+struct PopFmt<__bf16> {
+    static constexpr bool shifted = true;
+    __device__ static __forceinline__ float dec(__bf16 h) { return (float)h; }
+    __device__ static __forceinline__ __bf16 enc(float x) { return (__bf16)x; }
+};
+
+// Lattice weight of direction I: the product over axes of 2/3 (c = 0) or 1/6 (c = +-1), i.e.
+// the rest-state factors of the product-form equilibrium.
+template <int D, int I>
+__device__ __forceinline__ constexpr float weight() {
+    using L = Lat<D>;
+    float w = 1.0f;
+    for (int a = 0; a < D; ++a) w *= L::c[I][a] == 0 ? (2.0f / 3.0f) : (1.0f / 6.0f);
+    return w;
+}
+// 2^k_I <= 2^12 / w_I (1 / w_I is a product of 3/2 and 6, computed exactly).
+template <int D, int I>
+__device__ __forceinline__ constexpr float enc_scale() {
+    using L = Lat<D>;
+    float r = 4096.0f;
+    for (int a = 0; a < D; ++a) r *= L::c[I][a] == 0 ? 1.5f : 6.0f;
+    float p = 1.0f;
+    while (p * 2.0f <= r) p *= 2.0f;
+    return p;
+}
+
+// Shift sigma_I = base * w_I of a value produced by cell m (16-bit formats; FP32 product).
+template <int D, int I, typename P, typename T>
+__device__ __forceinline__ float shift_sigma(const T *__restrict__ eps, const Phys<T> &ph,
+                                             uint32_t m) {
+    if constexpr (!PopFmt<P>::shifted) {
+        return 0.0f;
+    } else {
+        const float base = ph.shift_porous ? ph.rho0 * ld(eps, m) : ph.rho0;
+        return base * weight<D, I>();
+    }
+}
+
+// Value of a slot in arithmetic type A (FP32 in the kernels; FP64 for exact checkpoints).
+template <int D, int I, typename A, typename P>
+__device__ __forceinline__ A decode(P raw, float sigma) {
+    if constexpr (!PopFmt<P>::shifted) {
+        return (A)raw;
+    } else {
+        constexpr float dscale = 1.0f / enc_scale<D, I>();
+        return (A)sigma + (A)PopFmt<P>::dec(raw) * (A)dscale;
+    }
+}
+template <int D, int I, typename P, typename A>
+__device__ __forceinline__ P encode(A v, float sigma) {
+    if constexpr (!PopFmt<P>::shifted) {
+        return (P)v;
+    } else {
+        constexpr float escale = enc_scale<D, I>();
+        return PopFmt<P>::enc((float)((v - (A)sigma) * (A)escale));
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // AA-pattern population access
 // ------------------------------------------------------------------------------------------
-template <int D, bool SOLIDS, int PH, int I, typename T>
-__device__ __forceinline__ T load_pop(const T *__restrict__ f, const uint8_t *__restrict__ mask,
+// Cell whose collision produced the population f_I found at cell n: the upstream cell
+// n - c_I, or n itself when that cell is solid (the value was bounced back at n).  This holds
+// for the natural layout (read in phase 0) and for the swapped one (read in phase 1).
+template <int D, bool SOLIDS, int I>
+__device__ __forceinline__ uint32_t source_cell(const uint8_t *__restrict__ mask,
+                                                const Nbr<D> &nb) {
+    using L = Lat<D>;
+    constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+    if constexpr (cx == 0 && cy == 0 && cz == 0) {
+        return nb.self();
+    } else {
+        const uint32_t s = nb.at(-cx, -cy, -cz);
+        if constexpr (SOLIDS) {
+            if (mask[s]) return nb.self();
+        }
+        return s;
+    }
+}
+
+// Raw slot holding f_I of cell n (AA pattern, halfway bounce-back in phase 1).
+template <int D, bool SOLIDS, int PH, int I, typename P>
+__device__ __forceinline__ P load_raw(const P *__restrict__ f, const uint8_t *__restrict__ mask,
                                       const Grid &g, const Nbr<D> &nb) {
     using L = Lat<D>;
     constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
@@ -206,25 +308,53 @@ __device__ __forceinline__ T load_pop(const T *__restrict__ f, const uint8_t *__
     }
 }
 
-template <int D, bool SOLIDS, int PH, int I, typename T>
-__device__ __forceinline__ void store_pop(T *__restrict__ f, const uint8_t *__restrict__ mask,
-                                          const Grid &g, const Nbr<D> &nb, T val) {
+// Shift of the f_I found at cell n (0 for FP64/FP32 storage).
+template <int D, bool SOLIDS, int I, typename P, typename T>
+__device__ __forceinline__ float load_sigma(const uint8_t *__restrict__ mask,
+                                            const T *__restrict__ eps, const Phys<T> &ph,
+                                            const Nbr<D> &nb) {
+    if constexpr (!PopFmt<P>::shifted) return 0.0f;
+    else return shift_sigma<D, I, P>(eps, ph, source_cell<D, SOLIDS, I>(mask, nb));
+}
+
+template <int D, bool SOLIDS, int PH, int I, typename T, typename P>
+__device__ __forceinline__ T load_pop(const P *__restrict__ f, const uint8_t *__restrict__ mask,
+                                      const T *__restrict__ eps, const Phys<T> &ph,
+                                      const Grid &g, const Nbr<D> &nb) {
+    const P raw = load_raw<D, SOLIDS, PH, I>(f, mask, g, nb);
+    return decode<D, I, T>(raw, load_sigma<D, SOLIDS, I, P>(mask, eps, ph, nb));
+}
+
+// Store of the post-collision f_I of the cell; base is the cell's own shift base
+// (rho0 or rho0 eps(n)) for the 16-bit formats.
+template <int D, bool SOLIDS, int PH, int I, typename T, typename P>
+__device__ __forceinline__ void store_pop(P *__restrict__ f, const uint8_t *__restrict__ mask,
+                                          const Grid &g, const Nbr<D> &nb, T val, float base) {
     using L = Lat<D>;
     constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
     const uint32_t n = nb.self();
     constexpr bool NT = PH == 0;
+    const P raw = encode<D, I, P>(val, base * weight<D, I>());
     if constexpr (PH == 0 || (cx == 0 && cy == 0 && cz == 0)) {
-        st_pop<NT>(plane(f, L::opp[I], g.N), n, val);
+        st_pop<NT>(plane(f, L::opp[I], g.N), n, raw);
     } else {
         const uint32_t d = nb.at(cx, cy, cz);
         if constexpr (SOLIDS) {
             if (mask[d]) {
-                st_pop<NT>(plane(f, L::opp[I], g.N), n, val);
+                st_pop<NT>(plane(f, L::opp[I], g.N), n, raw);
                 return;
             }
         }
-        st_pop<NT>(plane(f, I, g.N), d, val);
+        st_pop<NT>(plane(f, I, g.N), d, raw);
     }
+}
+
+// Shift base of the cell itself for store_pop.
+template <typename P, typename T>
+__device__ __forceinline__ float own_base(const T *__restrict__ eps, const Phys<T> &ph,
+                                          uint32_t n) {
+    if constexpr (!PopFmt<P>::shifted) return 0.0f;
+    else return ph.shift_porous ? ph.rho0 * ld(eps, n) : ph.rho0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -702,10 +832,10 @@ __device__ __forceinline__ void store_rec(P4<T> *__restrict__ m, uint32_t n, T r
 
 // Collision (dicrete_scheme, momentum_rate with lambda = dt = 1) and streaming with halfway
 // bounce-back, in place: f^pc_i = f_i + 2 beta (f^eq_i - f_i) + (1 - beta)(f^*_i - f^eq_i).
-template <int D, typename T, bool SOLIDS, int PH>
-__device__ __forceinline__ void collide_stream(T *__restrict__ f,
+template <int D, typename T, typename P, bool SOLIDS, int PH>
+__device__ __forceinline__ void collide_stream(P *__restrict__ f,
                                                const uint8_t *__restrict__ mask, const Grid &g,
-                                               const Nbr<D> &nb, const T fi[], T beta,
+                                               const Nbr<D> &nb, const T fi[], T beta, float base,
                                                const ProductForm<D, T> &peq,
                                                const ProductForm<D, T> &pst) {
     using L = Lat<D>;
@@ -716,13 +846,13 @@ __device__ __forceinline__ void collide_stream(T *__restrict__ f,
         const T feq = peq.template at<i>();
         const T fst = pst.template at<i>();
         const T fpc = (fi[i] + two_beta * (feq - fi[i])) + omb * (fst - feq);
-        store_pop<D, SOLIDS, PH, i>(f, mask, g, nb, fpc);
+        store_pop<D, SOLIDS, PH, i>(f, mask, g, nb, fpc, base);
     });
 }
 
 // Pass one of the two-pass scheme: the record (rho, v^(1)) of every cell.
-template <int D, typename T, bool SOLIDS, int PH>
-__global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f,
+template <int D, typename T, typename P, bool SOLIDS, int PH>
+__global__ __launch_bounds__(256) void k_moments(const P *__restrict__ f,
                                                  const T *__restrict__ eps,
                                                  const T *__restrict__ muD,
                                                  const T *__restrict__ muF,
@@ -740,7 +870,7 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ f,
     T fi[L::Q];
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
+        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, eps, ph, g, nb);
     });
     const Rec<T> q = cell_moments<D>(fi, eps, muD, muF, nb, ph);
     store_rec<D>(m1_out, n, q.r, q.w);
@@ -771,8 +901,8 @@ __global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ own_
 }
 
 // Pass two of the two-pass scheme: forcing from the (rho, v) records, collision, streaming.
-template <int D, typename T, bool SOLIDS, int PH>
-__global__ __launch_bounds__(256) void k_collide(T *__restrict__ f,
+template <int D, typename T, typename P, bool SOLIDS, int PH>
+__global__ __launch_bounds__(256) void k_collide(P *__restrict__ f,
                                                  const P4<T> *__restrict__ m2,
                                                  const T *__restrict__ eps,
                                                  const T *__restrict__ muD,
@@ -794,9 +924,10 @@ __global__ __launch_bounds__(256) void k_collide(T *__restrict__ f,
     T fi[L::Q];
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
+        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, eps, ph, g, nb);
     });
-    collide_stream<D, T, SOLIDS, PH>(f, mask, g, nb, fi, cs.vs.beta, peq, pst);
+    collide_stream<D, T, P, SOLIDS, PH>(f, mask, g, nb, fi, cs.vs.beta,
+                                        own_base<P>(eps, ph, n), peq, pst);
 }
 
 // One pass of the lagged scheme: the cell's own moments, velocity correction and forcing are
@@ -804,8 +935,8 @@ __global__ __launch_bounds__(256) void k_collide(T *__restrict__ f,
 // Phi^eta are the previous step's records (m1p: rho, v^(1); m2p: rho, v).  The cell's new
 // records go to m1n / m2n for the next step.  A steady state of this scheme is a steady state
 // of the two-pass scheme.
-template <int D, typename T, bool SOLIDS, int PH>
-__global__ __launch_bounds__(256) void k_fused(T *__restrict__ f, const P4<T> *__restrict__ m1p,
+template <int D, typename T, typename P, bool SOLIDS, int PH>
+__global__ __launch_bounds__(256) void k_fused(P *__restrict__ f, const P4<T> *__restrict__ m1p,
                                                const P4<T> *__restrict__ m2p,
                                                P4<T> *__restrict__ m1n, P4<T> *__restrict__ m2n,
                                                const T *__restrict__ eps,
@@ -825,7 +956,7 @@ __global__ __launch_bounds__(256) void k_fused(T *__restrict__ f, const P4<T> *_
     T fi[L::Q];
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
+        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, eps, ph, g, nb);
     });
     const Rec<T> own1 = cell_moments<D>(fi, eps, muD, muF, nb, ph);
     const CellStatic<D, T> cs = cell_static<D>(eps, nb, ph, own1.e);
@@ -833,15 +964,17 @@ __global__ __launch_bounds__(256) void k_fused(T *__restrict__ f, const P4<T> *_
     corrected_velocity<D, T, SOLIDS>(m1p, eps, mask, g, nb, own1, cs, own2.w);
     ProductForm<D, T> peq, pst;
     cell_equilibria<D, T, SOLIDS>(m2p, eps, muD, muF, mask, g, ph, nb, own2, cs, peq, pst);
-    collide_stream<D, T, SOLIDS, PH>(f, mask, g, nb, fi, cs.vs.beta, peq, pst);
+    collide_stream<D, T, P, SOLIDS, PH>(f, mask, g, nb, fi, cs.vs.beta,
+                                        own_base<P>(eps, ph, n), peq, pst);
     store_rec<D>(m1n, n, own1.r, own1.w);
     store_rec<D>(m2n, n, own2.r, own2.w);
 }
 
 // Initial populations, eq. (eq_bc_f_bar) with lambda = dt = 1, from the moment fields (rho, v):
-// f-bar_i = (1 + 1/2) f^eq_i - (1/2) f^*_i, written in natural layout.
-template <int D, typename T, bool SOLIDS>
-__global__ __launch_bounds__(256) void k_init(T *__restrict__ f,
+// f-bar_i = (1 + 1/2) f^eq_i - (1/2) f^*_i, written in natural layout.  A 16-bit slot is
+// encoded with the shift of its source cell, as a phase-0 read decodes it.
+template <int D, typename T, typename P, bool SOLIDS>
+__global__ __launch_bounds__(256) void k_init(P *__restrict__ f,
                                               const P4<T> *__restrict__ m2,
                                               const T *__restrict__ eps,
                                               const T *__restrict__ muD,
@@ -854,7 +987,7 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ f,
         if (mask[n]) {
             unroll<0, L::Q>([&](auto ii) {
                 constexpr int i = decltype(ii)::value;
-                *at(plane(f, i, g.N), n) = T(0);
+                *at(plane(f, i, g.N), n) = P(0);
             });
             return;
         }
@@ -865,7 +998,8 @@ __global__ __launch_bounds__(256) void k_init(T *__restrict__ f,
     cell_equilibria<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        *at(plane(f, i, g.N), n) = T(1.5) * peq.template at<i>() - T(0.5) * pst.template at<i>();
+        const T v = T(1.5) * peq.template at<i>() - T(0.5) * pst.template at<i>();
+        *at(plane(f, i, g.N), n) = encode<D, i, P>(v, load_sigma<D, SOLIDS, i, P>(mask, eps, ph, nb));
     });
 }
 
@@ -906,24 +1040,43 @@ __global__ __launch_bounds__(256) void k_fill_init(const double *__restrict__ rh
 }
 
 // Natural-layout copy of the current populations (0 on solid cells).
-template <int D, typename T, bool SOLIDS, int PH, typename O>
-__global__ __launch_bounds__(256) void k_export(const T *__restrict__ f,
+template <int D, typename T, typename P, bool SOLIDS, int PH, typename O>
+__global__ __launch_bounds__(256) void k_export(const P *__restrict__ f,
                                                 const uint8_t *__restrict__ mask,
-                                                O *__restrict__ out, Grid g, Tiling tl) {
+                                                const T *__restrict__ eps, O *__restrict__ out,
+                                                Grid g, Tiling tl, Phys<T> ph) {
     LBM_CELL_PROLOGUE(D)
     using L = Lat<D>;
     const bool solid = SOLIDS && mask[n];
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        out[(int64_t)i * g.N + n] = solid ? O(0) : (O)load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
+        if (solid) {
+            out[(int64_t)i * g.N + n] = O(0);
+        } else {
+            const P raw = load_raw<D, SOLIDS, PH, i>(f, mask, g, nb);
+            out[(int64_t)i * g.N + n] =
+                decode<D, i, O>(raw, load_sigma<D, SOLIDS, i, P>(mask, eps, ph, nb));
+        }
     });
 }
 
-template <typename T, typename I>
-__global__ __launch_bounds__(256) void k_import(T *__restrict__ f, const I *__restrict__ in,
-                                                int64_t total) {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k < total) f[k] = (T)in[k];
+// Populations from a natural-layout array [Q][N] (the state then reads as phase 0).
+template <int D, typename T, typename P, bool SOLIDS, typename I>
+__global__ __launch_bounds__(256) void k_import(P *__restrict__ f, const I *__restrict__ in,
+                                                const uint8_t *__restrict__ mask,
+                                                const T *__restrict__ eps, Grid g, Tiling tl,
+                                                Phys<T> ph) {
+    LBM_CELL_PROLOGUE(D)
+    using L = Lat<D>;
+    unroll<0, L::Q>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        const float sig = load_sigma<D, SOLIDS, i, P>(mask, eps, ph, nb);
+        if constexpr (PopFmt<P>::shifted) {
+            *at(plane(f, i, g.N), n) = encode<D, i, P>(in[(int64_t)i * g.N + n], sig);
+        } else {
+            *at(plane(f, i, g.N), n) = (P)in[(int64_t)i * g.N + n];
+        }
+    });
 }
 
 // Caller-facing moments: rho and v (kind 0) or u = v / eps (kind 1), from the packed records.
@@ -964,12 +1117,14 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-template <int D, typename T, bool SOLIDS, int PH>
-__global__ __launch_bounds__(256) void k_stats(const T *__restrict__ f,
+template <int D, typename T, typename P, bool SOLIDS, int PH>
+__global__ __launch_bounds__(256) void k_stats(const P *__restrict__ f,
                                                const P4<T> *__restrict__ m2,
                                                T *__restrict__ vsnap,
                                                const uint8_t *__restrict__ mask,
-                                               double *__restrict__ partial, Grid g) {
+                                               const T *__restrict__ eps,
+                                               double *__restrict__ partial, Grid g,
+                                               Phys<T> ph) {
     using L = Lat<D>;
     double acc[kStatsSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
     const uint32_t stride = gridDim.x * 256u;
@@ -983,7 +1138,7 @@ __global__ __launch_bounds__(256) void k_stats(const T *__restrict__ f,
         T cell = T(0);
         unroll<0, L::Q>([&](auto ii) {
             constexpr int i = decltype(ii)::value;
-            cell = cell + load_pop<D, SOLIDS, PH, i>(f, mask, g, nb);
+            cell = cell + load_pop<D, SOLIDS, PH, i>(f, mask, eps, ph, g, nb);
         });
         const double cm = (double)cell;
         acc[0] += cm;

@@ -72,6 +72,14 @@ def test_footprint_sizes():
     pl, _ = _params(scheme=capi.LBM_SCHEME_LAGGED)
     assert capi.lbm_footprint(pl) - fp >= 8 * N * 4
     assert capi.lbm_footprint(pl) - fp < 8 * N * 4 + 2 * 256
+    # 16-bit populations, FP32 static fields and records
+    for st in (capi.LBM_F16_SHIFTED, capi.LBM_BF16_SHIFTED):
+        ph, _ = _params(storage=st)
+        assert fp - capi.lbm_footprint(ph) >= 27 * N * 2 - 256
+        assert fp - capi.lbm_footprint(ph) <= 27 * N * 2 + 256
+    # the population region also stages four FP64 input arrays at creation
+    p2, _ = _params(lattice=capi.LBM_D2Q9, storage=capi.LBM_F16_SHIFTED, shape=(1, 8, 8))
+    assert capi.lbm_footprint(p2) >= 4 * 64 * 8 + (3 + 8 + 2) * 64 * 4
 
 
 @pytest.mark.parametrize("mutate,code", [
@@ -79,6 +87,8 @@ def test_footprint_sizes():
     (dict(storage=9), capi.LBM_ERR_UNSUPPORTED),
     (dict(nx=0), capi.LBM_ERR_INVALID_ARG),
     (dict(scheme=2), capi.LBM_ERR_INVALID_ARG),
+    (dict(shift=5), capi.LBM_ERR_INVALID_ARG),
+    (dict(storage=4), capi.LBM_ERR_UNSUPPORTED),
 ])
 def test_footprint_rejects_bad_shape(mutate, code):
     p, _ = _params()

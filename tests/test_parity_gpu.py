@@ -61,9 +61,9 @@ def _print(tag, errs):
     print(tag, " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
 
 
-def _run_pair(w, steps, storage=capi.LBM_F64, chunks=1, lagged=False):
+def _run_pair(w, steps, storage=capi.LBM_F64, chunks=1, lagged=False, shift=capi.LBM_SHIFT_WEIGHTS):
     scheme = capi.LBM_SCHEME_LAGGED if lagged else capi.LBM_SCHEME_TWO_PASS
-    s = capi.Solver.from_workload(w, storage=storage, scheme=scheme)
+    s = capi.Solver.from_workload(w, storage=storage, scheme=scheme, shift=shift)
     o = _oracle_for(w, lagged=int(lagged))
     per = steps // chunks
     for _ in range(chunks):
@@ -324,3 +324,86 @@ def test_d3q27_fp32_tracks_fp64_oracle():
     _print("d3q27 fp32 vs fp64 oracle:", errs)
     assert errs["f"] < 3e-5 and errs["rho"] < 5e-5
     assert max(errs[k] for k in ("v0", "v1", "v2")) < 2e-3
+
+
+# --------------------------------------------------------------------------------------------
+# Shifted 16-bit population storage against the FP64 oracle
+# --------------------------------------------------------------------------------------------
+def _l2_linf(a, b):
+    d = (a - b).ravel()
+    r = b.ravel()
+    return float(np.linalg.norm(d) / np.linalg.norm(r)), float(np.abs(d).max() / np.abs(r).max())
+
+
+_SHIFTED = {"f16": capi.LBM_F16_SHIFTED, "bf16": capi.LBM_BF16_SHIFTED}
+_SHIFTS = {"weights": capi.LBM_SHIFT_WEIGHTS, "porous": capi.LBM_SHIFT_POROUS}
+
+
+# Bounds are about 3x the errors measured on MI355X (v L2 / v Linf / f / mass drift):
+#   f16 porous  2.0e-3 / 1.9e-3 / 1.7e-5 / 8.1e-6     bf16 porous  1.5e-2 / 1.9e-2 / 9.5e-5 / 8.5e-6
+#   f16 weights 4.8e-2 / 3.7e-2 / 6.1e-4 / 7.6e-5     bf16 weights 0.38   / 0.30   / 4.5e-3 / 2.6e-4
+# (FP32 storage: v 1.6e-4..4e-4).  Model: a stored deviation d carries a relative rounding
+# error of 2^-11 (FP16) or 2^-8 (BF16).  With the porous shift d is the flow's own deviation
+# from eps rho0 w_i, ~1e-3 of f here, so FP16 costs about as much as FP32 arithmetic; with the
+# weight shift d includes (eps - 1) rho0 w_i, up to 0.7 w_i at eps = 0.3, and the velocity error
+# grows ~25-fold.
+_SHIFT_BOUNDS = {("f16", "porous"): (6e-3, 6e-3, 5e-5, 3e-5),
+                 ("bf16", "porous"): (5e-2, 6e-2, 3e-4, 3e-5),
+                 ("f16", "weights"): (0.15, 0.12, 2e-3, 3e-4),
+                 ("bf16", "weights"): (1.2, 1.0, 1.5e-2, 1e-3)}
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+@pytest.mark.parametrize("shift", ["weights", "porous"])
+def test_shifted_storage_velocity_error(fmt, shift):
+    """Populations stored as 16-bit shifted deviations, FP32 collision, FP64 statistics, against
+    the FP64 oracle on the random-porosity recipe (32^3, l = 16, nu = 0.01, b = 1e-6, 100
+    steps): the L2 and Linf velocity errors and the mass drift within the stated bounds."""
+    w = workloads.random_porosity_3d(shape=(32, 32, 32), seed=0, ell=16.0)
+    s, o = _run_pair(w, 100, storage=_SHIFTED[fmt], shift=_SHIFTS[shift])
+    _, v_gpu = (t.cpu().numpy() for t in s.moments(torch.float64))
+    _, v_ref, _ = o.moments()
+    l2, linf = _l2_linf(v_gpu, v_ref)
+    mass_gpu, mass_ref = s.residual().mass, o.stats()["mass"]
+    drift = abs(mass_gpu - mass_ref) / mass_ref
+    errs = _field_errors(s, o)
+    print(f"shifted {fmt}/{shift}: v L2 {l2:.3e} Linf {linf:.3e} mass {drift:.3e}", flush=True)
+    _print(f"shifted {fmt}/{shift} fields:", errs)
+    b_l2, b_linf, b_f, b_m = _SHIFT_BOUNDS[(fmt, shift)]
+    assert l2 < b_l2 and linf < b_linf and errs["f"] < b_f and drift < b_m
+
+
+@pytest.mark.parametrize("lagged", [False, True])
+def test_porous_shift_with_solids(lagged):
+    """FP16 storage with the porous shift next to solid cells inside a varying porosity field,
+    both schemes: a value produced by a bounce-back is shifted with the porosity of the cell
+    that bounced it.  A reader that took the upstream (solid) cell's porosity instead would be
+    off by (eps_a - eps_b) w_i ~ 1e-2 of f here, far above the bound."""
+    w = _solids_3d(shape=(10, 12, 40))
+    w.eta_eff = float("nan")
+    s, o = _run_pair(w, 40, storage=capi.LBM_F16_SHIFTED, lagged=lagged,
+                     shift=capi.LBM_SHIFT_POROUS)
+    errs = _field_errors(s, o)
+    _print(f"f16 porous solids lagged={lagged}:", errs)
+    assert errs["f"] < 1e-4 and errs["rho"] < 1e-4
+    assert max(errs[k] for k in ("v0", "v1", "v2")) < 2e-2
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_shifted_checkpoint_is_exact_through_fp64(fmt):
+    """A 16-bit state exported in FP64 (exact decode) and imported again (exact re-encode: the
+    scales are powers of two) continues bit for bit, from either AA phase."""
+    w = _solids_3d(shape=(8, 9, 10))
+    for steps in (6, 7):
+        a = capi.Solver.from_workload(w, storage=_SHIFTED[fmt], shift=capi.LBM_SHIFT_POROUS)
+        b = capi.Solver.from_workload(w, storage=_SHIFTED[fmt], shift=capi.LBM_SHIFT_POROUS)
+        a.step(steps)
+        b.step(steps)
+        ck = b.populations(torch.float64)
+        b.step(3)
+        b.set_populations(ck, step=steps)
+        a.step(5)
+        b.step(5)
+        fa = a.populations(torch.float64).cpu().numpy()
+        fb = b.populations(torch.float64).cpu().numpy()
+        assert np.array_equal(fa, fb)
