@@ -223,6 +223,100 @@ LBM_API int lbm_get_step(const lbm_solver *h, int64_t *step);
  */
 LBM_API int lbm_lattice_info(int lattice, int *c_out, int *opp_out);
 
+/* ------------------------------------------------------------------------------------------
+ * Request server: continuous batching of many independent runs on one GPU.
+ *
+ * Requests (each an lbm_params run with a steady-state tolerance) queue on submission and are
+ * admitted in arrival order as memory of the caller's device pool frees up: a request whose
+ * workspace (lbm_footprint) does not fit lets later, smaller ones pass (backfill) until it has
+ * waited 64 rounds, after which admission waits for it.  Admitted requests keep their
+ * populations resident and advance together in rounds of check_every steps: every pass of a
+ * round is one kernel launch over the tiles of all active runs that share a lattice, storage,
+ * solids flag, scheme and AA phase (kernel boundaries are the per-request step barriers), so
+ * small runs fill the GPU together.  After each round the server takes each run's statistics
+ * (lbm_residual's FP64 reductions) and retires runs whose relative L2 change of v over the
+ * round fell below tol (converged), that reached max_steps (censored) or that hold non-finite
+ * values (failed).  Each run's arithmetic is that of lbm_step, so its result is bitwise the same
+ * alone and in any mix.  All work is enqueued on the server's stream; progress synchronises it
+ * once per round.  A server handle must not be used from two threads at once.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct lbm_server lbm_server;
+
+#define LBM_REQ_QUEUED 0
+#define LBM_REQ_ACTIVE 1
+#define LBM_REQ_CONVERGED 2
+#define LBM_REQ_CENSORED 3   /* reached max_steps before tol */
+#define LBM_REQ_FAILED 4     /* creation failed or the state became non-finite */
+
+typedef struct lbm_request_info {
+    int64_t id;
+    int state;               /* LBM_REQ_* */
+    int64_t steps;           /* time steps taken */
+    double residual;         /* relative L2 change of v over the last round (+inf before two) */
+    double t_submit;         /* seconds since lbm_server_create (steady clock) */
+    double t_admit;          /* -1 until admitted */
+    double t_done;           /* -1 until converged, censored or failed */
+    int64_t cells;           /* nx * ny * nz */
+    size_t workspace_bytes;  /* lbm_footprint of the run */
+} lbm_request_info;
+
+typedef struct lbm_server_stats {
+    int64_t rounds;          /* rounds run */
+    int64_t submitted, admitted, finished;
+    int64_t queued, active;  /* now */
+    double cell_updates;     /* sum over admitted runs of cells x steps */
+    size_t pool_bytes;       /* size of the device pool */
+    size_t pool_used;        /* bytes held by admitted, unreleased runs */
+    size_t pool_peak;        /* maximum of pool_used */
+} lbm_server_stats;
+
+/*
+ * Create a server on the caller's device pool (>= 1 MiB, 256-byte aligned; borrowed until
+ * lbm_server_destroy) and stream.  check_every >= 2 is the round length in steps (even, so
+ * that every run starts each round in the natural AA layout); max_active caps the number of
+ * resident runs (0: only memory and the limit of 4096 bound it).
+ * Errors: LBM_ERR_INVALID_ARG, LBM_ERR_WORKSPACE.
+ */
+LBM_API int lbm_server_create(void *dev_pool, size_t pool_bytes, int64_t check_every,
+                              int max_active, void *hip_stream, lbm_server **out);
+
+/*
+ * Queue a run.  The params and every host array they point to are copied, so the caller may
+ * free them on return.  tol > 0 is the steady-state threshold on the relative L2 change of v
+ * over one round; max_steps >= check_every caps the run.  *id receives the request id (ids
+ * count from 0 in submission order).  Errors: those of lbm_footprint, LBM_ERR_INVALID_ARG,
+ * LBM_ERR_WORKSPACE (the run can never fit in the pool).
+ */
+LBM_API int lbm_server_submit(lbm_server *s, const lbm_params *p, double tol, int64_t max_steps,
+                              int64_t *id);
+
+/*
+ * Run up to max_rounds rounds (admission, check_every steps of every active run, statistics,
+ * retirement); returns early when nothing is active or queued.  The ids of runs that finished
+ * during the call are written to finished_ids (room for max_finished; more are still counted
+ * in *n_finished, which may be NULL).  Synchronises the stream.
+ */
+LBM_API int lbm_server_progress(lbm_server *s, int64_t max_rounds, int64_t *finished_ids,
+                                int max_finished, int *n_finished);
+
+/* Current state of a request. */
+LBM_API int lbm_server_info(const lbm_server *s, int64_t id, lbm_request_info *out);
+
+/*
+ * Solver handle of an active or finished, unreleased request, for lbm_moments,
+ * lbm_get_populations and lbm_residual on the server's stream.  Valid until the request is
+ * released; stepping it directly is not allowed.
+ */
+LBM_API int lbm_server_solver(lbm_server *s, int64_t id, lbm_solver **out);
+
+/* Release a finished request's workspace back to the pool (its info stays available). */
+LBM_API int lbm_server_release(lbm_server *s, int64_t id);
+
+LBM_API int lbm_server_get_stats(const lbm_server *s, lbm_server_stats *out);
+
+/* Destroy the server (NULL is a no-op); the pool and the stream remain the caller's. */
+LBM_API int lbm_server_destroy(lbm_server *s);
+
 /* Release the host-side handle (NULL is a no-op).  The workspace remains the caller's. */
 LBM_API int lbm_destroy(lbm_solver *h);
 

@@ -1,15 +1,16 @@
-"""Build step of the HIP library: one hipcc invocation for gfx950, in-tree output."""
+"""Build step of the HIP library: hipcc for gfx950 over the solver and the request-server
+sources (compiled in parallel, then linked), in-tree output."""
 import os
 import subprocess
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "lbm.hip")
+SRCS = [os.path.join(PKG, "csrc", f) for f in ("lbm.hip", "lbm_server.hip")]
 LIB = os.path.join(PKG, "liblbm.so")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     # expressions are evaluated exactly as written (FP64 results match the CPU reference)
     "-ffp-contract=off",
     # no packed FP32 instructions anywhere in the device code
@@ -20,12 +21,26 @@ HIPCC_FLAGS = [
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    inc = ["-I", os.path.join(ROOT, "include")]
+    objs, procs = [], []
+    for src in SRCS:
+        obj = LIB + "." + os.path.splitext(os.path.basename(src))[0] + ".o"
+        cmd = [hipcc, *HIPCC_FLAGS, *inc, "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd))
+        objs.append(obj)
+    codes = [p.wait() for p in procs]
+    if any(codes):
+        raise subprocess.CalledProcessError(max(codes, key=abs), "hipcc -c")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, SRC]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
     return LIB
 
 

@@ -64,6 +64,31 @@ class lbm_stats(ctypes.Structure):
     ]
 
 
+LBM_REQ_QUEUED = 0
+LBM_REQ_ACTIVE = 1
+LBM_REQ_CONVERGED = 2
+LBM_REQ_CENSORED = 3
+LBM_REQ_FAILED = 4
+
+
+class lbm_request_info(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64), ("state", ctypes.c_int), ("steps", ctypes.c_int64),
+        ("residual", ctypes.c_double), ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("cells", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class lbm_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("rounds", ctypes.c_int64), ("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+        ("finished", ctypes.c_int64), ("queued", ctypes.c_int64), ("active", ctypes.c_int64),
+        ("cell_updates", ctypes.c_double), ("pool_bytes", ctypes.c_size_t),
+        ("pool_used", ctypes.c_size_t), ("pool_peak", ctypes.c_size_t),
+    ]
+
+
 class LbmError(RuntimeError):
     def __init__(self, code: int, func: str, msg: str):
         super().__init__(f"{func} failed ({code}): {msg}")
@@ -98,9 +123,23 @@ def load() -> ctypes.CDLL:
     L.lbm_destroy.argtypes = [vp]
     L.lbm_last_error.restype = ctypes.c_char_p
     L.lbm_last_error.argtypes = []
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    L.lbm_server_create.argtypes = [vp, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int, vp,
+                                    ctypes.POINTER(vp)]
+    L.lbm_server_submit.argtypes = [vp, ctypes.POINTER(lbm_params), ctypes.c_double,
+                                    ctypes.c_int64, i64p]
+    L.lbm_server_progress.argtypes = [vp, ctypes.c_int64, i64p, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int)]
+    L.lbm_server_info.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(lbm_request_info)]
+    L.lbm_server_solver.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(vp)]
+    L.lbm_server_release.argtypes = [vp, ctypes.c_int64]
+    L.lbm_server_get_stats.argtypes = [vp, ctypes.POINTER(lbm_server_stats)]
+    L.lbm_server_destroy.argtypes = [vp]
     for name in ("lbm_footprint", "lbm_create", "lbm_step", "lbm_step_timed", "lbm_moments",
                  "lbm_residual", "lbm_get_populations", "lbm_set_populations", "lbm_get_step",
-                 "lbm_lattice_info", "lbm_destroy"):
+                 "lbm_lattice_info", "lbm_destroy", "lbm_server_create", "lbm_server_submit",
+                 "lbm_server_progress", "lbm_server_info", "lbm_server_solver",
+                 "lbm_server_release", "lbm_server_get_stats", "lbm_server_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -178,6 +217,56 @@ def lbm_destroy(h):
     _check(load().lbm_destroy(h), "lbm_destroy")
 
 
+def lbm_server_create(pool_ptr: int, pool_bytes: int, check_every: int, max_active: int,
+                      stream_ptr: int):
+    h = ctypes.c_void_p()
+    _check(load().lbm_server_create(ctypes.c_void_p(pool_ptr), pool_bytes, int(check_every),
+                                    int(max_active), ctypes.c_void_p(stream_ptr),
+                                    ctypes.byref(h)), "lbm_server_create")
+    return h
+
+
+def lbm_server_submit(s, p: lbm_params, tol: float, max_steps: int) -> int:
+    rid = ctypes.c_int64(-1)
+    _check(load().lbm_server_submit(s, ctypes.byref(p), float(tol), int(max_steps),
+                                    ctypes.byref(rid)), "lbm_server_submit")
+    return rid.value
+
+
+def lbm_server_progress(s, max_rounds: int, max_finished: int = 4096):
+    ids = (ctypes.c_int64 * max(max_finished, 1))()
+    n = ctypes.c_int(0)
+    _check(load().lbm_server_progress(s, int(max_rounds), ids, int(max_finished),
+                                      ctypes.byref(n)), "lbm_server_progress")
+    return [ids[k] for k in range(min(n.value, max_finished))]
+
+
+def lbm_server_info(s, rid: int) -> lbm_request_info:
+    out = lbm_request_info()
+    _check(load().lbm_server_info(s, int(rid), ctypes.byref(out)), "lbm_server_info")
+    return out
+
+
+def lbm_server_solver(s, rid: int):
+    h = ctypes.c_void_p()
+    _check(load().lbm_server_solver(s, int(rid), ctypes.byref(h)), "lbm_server_solver")
+    return h
+
+
+def lbm_server_release(s, rid: int):
+    _check(load().lbm_server_release(s, int(rid)), "lbm_server_release")
+
+
+def lbm_server_get_stats(s) -> lbm_server_stats:
+    out = lbm_server_stats()
+    _check(load().lbm_server_get_stats(s, ctypes.byref(out)), "lbm_server_get_stats")
+    return out
+
+
+def lbm_server_destroy(s):
+    _check(load().lbm_server_destroy(s), "lbm_server_destroy")
+
+
 # --------------------------------------------------------------------------------------------
 # Convenience wrapper: numpy fields in, torch device memory and stream underneath.
 # --------------------------------------------------------------------------------------------
@@ -224,7 +313,7 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
 class Solver:
     """A solver on one GPU: owns its torch workspace, uses torch's current stream."""
 
-    def __init__(self, params: lbm_params, keepalive=None, device="cuda"):
+    def __init__(self, params: lbm_params, keepalive=None, device="cuda", handle=None):
         import torch
         self._torch = torch
         self.params = params
@@ -236,10 +325,14 @@ class Solver:
         self.dtype = torch.float64 if params.storage == LBM_F64 else torch.float32
         self.nbytes = lbm_footprint(params)
         self.device = torch.device(device)
-        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
-        self.stream = torch.cuda.current_stream(self.device)
-        self._h = lbm_create(params, self.workspace.data_ptr(), self.nbytes,
-                             self.stream.cuda_stream)
+        self._owned = handle is None
+        if handle is None:
+            self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+            self._h = lbm_create(params, self.workspace.data_ptr(), self.nbytes,
+                                 self.stream.cuda_stream)
+        else:  # a handle owned elsewhere (a request of a server)
+            self._h = handle
         del keepalive
 
     @classmethod
@@ -253,7 +346,8 @@ class Solver:
 
     def close(self):
         if getattr(self, "_h", None):
-            lbm_destroy(self._h)
+            if getattr(self, "_owned", True):
+                lbm_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -303,3 +397,62 @@ class Solver:
 
     def residual(self, allow_nonfinite: bool = False) -> lbm_stats:
         return lbm_residual(self._h, allow_nonfinite)
+
+
+class Server:
+    """A request server on one GPU: owns its device pool (a torch tensor), uses torch's current
+    stream.  Marshalling only; admission, batching and retirement run in the library."""
+
+    def __init__(self, pool_bytes: int, check_every: int = 100, max_active: int = 0,
+                 device="cuda"):
+        import torch
+        self._torch = torch
+        self.device = torch.device(device)
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.check_every = check_every
+        self._params = {}
+        self._h = lbm_server_create(self.pool.data_ptr(), int(pool_bytes), check_every,
+                                    max_active, self.stream.cuda_stream)
+
+    def submit_params(self, params: lbm_params, tol: float, max_steps: int) -> int:
+        rid = lbm_server_submit(self._h, params, tol, max_steps)
+        self._params[rid] = params
+        return rid
+
+    def submit(self, w, storage: int = LBM_F32, tol: float = 1e-7, max_steps: int = 200000,
+               scheme: int = LBM_SCHEME_TWO_PASS, shift: int = LBM_SHIFT_POROUS) -> int:
+        p, _keep = make_params(w.lattice, storage, w.eps, w.kappa, w.forch, w.mask, RT=w.RT,
+                               nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow,
+                               eta_eff=w.eta_eff, b=w.b, rho0=w.rho0, rho_init=w.rho_init,
+                               v_init=w.v_init, scheme=scheme, shift=shift)
+        rid = self.submit_params(p, tol, max_steps)   # the library copies the arrays
+        return rid
+
+    def progress(self, max_rounds: int = 1):
+        return lbm_server_progress(self._h, max_rounds)
+
+    def info(self, rid: int) -> lbm_request_info:
+        return lbm_server_info(self._h, rid)
+
+    def solver(self, rid: int) -> Solver:
+        """A Solver view of a request (moments, populations) valid until release."""
+        return Solver(self._params[rid], handle=lbm_server_solver(self._h, rid),
+                      device=self.device)
+
+    def release(self, rid: int):
+        lbm_server_release(self._h, rid)
+
+    def stats(self) -> lbm_server_stats:
+        return lbm_server_get_stats(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lbm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

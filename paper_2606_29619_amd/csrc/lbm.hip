@@ -17,146 +17,9 @@
 #include <algorithm>
 
 #include "lbm_device.hpp"
+#include "lbm_host.hpp"
 
-namespace {
-
-thread_local std::string g_err;
-
-int fail(int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return code;
-}
-
-#define HIP_TRY(expr)                                                                   \
-    do {                                                                                \
-        hipError_t e_ = (expr);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail(LBM_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
-    } while (0)
-
-#define LAUNCH_CHECK()                                                                  \
-    do {                                                                                \
-        hipError_t e_ = hipGetLastError();                                              \
-        if (e_ != hipSuccess)                                                           \
-            return fail(LBM_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
-    } while (0)
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-struct Layout {
-    size_t f, eps, muD, muF, mask, m1[2], m2[2], vsnap, part, res, total;
-};
-
-// sp: bytes per population value; s: bytes per value of the static fields and moment records.
-Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool solids, bool lagged) {
-    Layout L{};
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t o = off;
-        off = align256(off + bytes);
-        return o;
-    };
-    // the population region also stages the FP64 inputs at creation (up to 4 arrays of N)
-    L.f = take(std::max((size_t)Q * N * sp, 4 * N * sizeof(double)));
-    L.eps = take(N * s);
-    L.muD = take(N * s);
-    L.muF = take(N * s);
-    L.mask = solids ? take(N) : 0;
-    // packed (rho, v^(1)) and (rho, v) records; the lagged scheme keeps a second pair so that
-    // one step reads the previous records while it writes the new ones
-    L.m1[0] = take(4 * N * s);
-    L.m2[0] = take(4 * N * s);
-    L.m1[1] = lagged ? take(4 * N * s) : L.m1[0];
-    L.m2[1] = lagged ? take(4 * N * s) : L.m2[0];
-    L.vsnap = take((size_t)D * N * s);
-    L.part = take((size_t)lbm::kStatsBlocks * lbm::kStatsSlots * sizeof(double));
-    L.res = take(lbm::kStatsSlots * sizeof(double));
-    L.total = off;
-    return L;
-}
-
-bool is_finite(double x) { return std::isfinite(x); }
-
-}  // namespace
-
-struct lbm_solver {
-    int lattice, D, Q, storage;
-    int nx, ny, nz;
-    int64_t N;
-    bool solids;
-    hipStream_t stream;
-    char *ws;
-    Layout L;
-    int64_t step;
-    int phase;  // AA-pattern layout: 0 natural, 1 swapped
-    int scheme;
-    int cur;        // record pair that holds the previous step's moments (lagged scheme)
-    bool have_prev; // whether that pair is valid (lagged scheme)
-    double RT, nu_f, nu_eff_ref, eta_eff, b[3], rho0;
-    int nu_eff_pow;
-    int shift;          // 16-bit population shift (LBM_SHIFT_*)
-    lbm::Tiling tiles;  // 256-cell tiles, blocked, in XCD-contiguous ranges
-};
-
-namespace {
-
-template <typename T>
-lbm::Phys<T> phys_of(const lbm_solver *h) {
-    lbm::Phys<T> ph;
-    ph.RT = (T)h->RT;
-    ph.omr = (T)(1.0 - 3.0 * h->RT);
-    ph.nu_ref = (T)h->nu_eff_ref;
-    ph.eta_on = std::isnan(h->eta_eff) ? 0 : 1;
-    ph.eta = ph.eta_on ? (T)h->eta_eff : T(0);
-    ph.two_over_D = (T)(2.0 / (double)h->D);
-    for (int a = 0; a < 3; ++a) ph.b[a] = (T)h->b[a];
-    ph.nu_pow = h->nu_eff_pow;
-    ph.rho0 = (T)h->rho0;
-    ph.shift_porous = h->shift == LBM_SHIFT_POROUS ? 1 : 0;
-    return ph;
-}
-
-lbm::Grid grid_of(const lbm_solver *h) { return lbm::Grid{h->nx, h->ny, h->nz, (uint32_t)h->N}; }
-
-
-dim3 flat_grid(int64_t total) { return dim3((unsigned)((total + 255) / 256)); }
-
-lbm::Tiling make_tiling(int nx, int ny, int nz) {
-    lbm::Tiling t;
-    t.tx = nx >= 192 ? 256 : (nx >= 96 ? 128 : 64);
-    t.ty = 256 / t.tx;
-    t.ntx = (nx + t.tx - 1) / t.tx;
-    t.nty = (ny + t.ty - 1) / t.ty;
-    t.ntz = nz;
-    int by = 64, bz = 4;  // tile rows per block along y and z (measured best on 256^3)
-    if (const char *e = std::getenv("LBM_TILE_BLOCK")) {  // "BYxBZ", for tuning sweeps
-        int a = 0, b = 0;
-        if (std::sscanf(e, "%dx%d", &a, &b) == 2 && a >= 1 && b >= 1) { by = a; bz = b; }
-    }
-    t.by = std::min(by, t.nty);
-    t.bz = std::min(bz, t.ntz);
-    t.nby = (t.nty + t.by - 1) / t.by;
-    t.nbz = (t.ntz + t.bz - 1) / t.bz;
-    const int64_t nt = (int64_t)t.ntx * t.by * t.bz * t.nby * t.nbz;
-    t.per = (uint32_t)((nt + 7) / 8);
-    return t;
-}
-
-dim3 cell_tiles(const lbm_solver *h) { return dim3((unsigned)(8 * (int64_t)h->tiles.per)); }
-
-template <typename T>
-T *ws_ptr(const lbm_solver *h, size_t off) {
-    return reinterpret_cast<T *>(h->ws + off);
-}
-
-const uint8_t *mask_ptr(const lbm_solver *h) {
-    return h->solids ? reinterpret_cast<const uint8_t *>(h->ws + h->L.mask) : nullptr;
-}
+namespace lbmh {
 
 // ---- kernel launchers, dispatched on (lattice, arithmetic type T, population storage type P,
 // solids, phase) ------------------------------------------------------------------------------
@@ -223,9 +86,14 @@ void launch_import(const lbm_solver *h, const I *in) {
                        grid_of(h), h->tiles, phys_of<T>(h));
 }
 
+// Statistics blocks: one per 256 cells up to kStatsBlocks (grid-stride beyond).
+int stats_blocks(const lbm_solver *h) {
+    return (int)std::min<int64_t>(lbm::kStatsBlocks, (h->N + 255) / 256);
+}
+
 template <int D, typename T, typename P, bool S, int PH>
 void launch_stats(const lbm_solver *h, size_t m2) {
-    hipLaunchKernelGGL((lbm::k_stats<D, T, P, S, PH>), dim3(lbm::kStatsBlocks), dim3(256), 0,
+    hipLaunchKernelGGL((lbm::k_stats<D, T, P, S, PH>), dim3(stats_blocks(h)), dim3(256), 0,
                        h->stream, ws_ptr<const P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
                        ws_ptr<T>(h, h->L.vsnap), mask_ptr(h), ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<double>(h, h->L.part), grid_of(h), phys_of<T>(h));
@@ -388,7 +256,21 @@ int validate_shape(const lbm_params *p, int *D, int *Q, size_t *sp, size_t *s, i
     return LBM_OK;
 }
 
-}  // namespace
+int enqueue_stats(lbm_solver *h) {
+    const size_t m2 = current_moments(h);
+    LAUNCH_CHECK();
+    dispatch(h, StatsPass{h, m2});
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(lbm::k_stats_final, dim3(1), dim3(256), 0, h->stream,
+                       ws_ptr<const double>(h, h->L.part), stats_blocks(h),
+                       ws_ptr<double>(h, h->L.res));
+    LAUNCH_CHECK();
+    return LBM_OK;
+}
+
+}  // namespace lbmh
+
+using namespace lbmh;
 
 extern "C" {
 
@@ -629,13 +511,8 @@ LBM_API int lbm_residual(lbm_solver *h, lbm_stats *out) {
     int rc = check_handle(h);
     if (rc) return rc;
     if (!out) return fail(LBM_ERR_INVALID_ARG, "out is NULL");
-    const size_t m2 = current_moments(h);
-    LAUNCH_CHECK();
-    dispatch(h, StatsPass{h, m2});
-    LAUNCH_CHECK();
-    hipLaunchKernelGGL(lbm::k_stats_final, dim3(1), dim3(256), 0, h->stream,
-                       ws_ptr<const double>(h, h->L.part), lbm::kStatsBlocks, ws_ptr<double>(h, h->L.res));
-    LAUNCH_CHECK();
+    rc = enqueue_stats(h);
+    if (rc) return rc;
     double r[lbm::kStatsSlots];
     HIP_TRY(hipMemcpyAsync(r, h->ws + h->L.res, sizeof r, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));

@@ -754,9 +754,8 @@ struct Tiling {
     uint32_t per;     // tiles per XCD (padded order)
 };
 
-__device__ __forceinline__ bool tile_cell(const Grid &g, const Tiling &tl, int &x, int &y,
-                                          int &z) {
-    const uint32_t w = blockIdx.x;
+__device__ __forceinline__ bool tile_cell(const Grid &g, const Tiling &tl, uint32_t w, int &x,
+                                          int &y, int &z) {
     const uint32_t t = (w & 7u) * tl.per + (w >> 3);
     const uint32_t rows_per_block = (uint32_t)tl.by * (uint32_t)tl.bz;
     const uint32_t nt = (uint32_t)tl.ntx * rows_per_block * (uint32_t)tl.nby * (uint32_t)tl.nbz;
@@ -772,12 +771,13 @@ __device__ __forceinline__ bool tile_cell(const Grid &g, const Tiling &tl, int &
     return x < g.nx && y < g.ny && z < g.nz;
 }
 
-#define LBM_CELL_PROLOGUE(D)                                         \
+#define LBM_CELL_PROLOGUE_W(D, W)                                    \
     int x, y, z;                                                     \
-    if (!tile_cell(g, tl, x, y, z)) return;                          \
+    if (!tile_cell(g, tl, W, x, y, z)) return;                       \
     Nbr<D> nb;                                                       \
     nb.init(g, x, y, z);                                             \
     const uint32_t n = nb.self();
+#define LBM_CELL_PROLOGUE(D) LBM_CELL_PROLOGUE_W(D, blockIdx.x)
 
 // Density (transformed_density_moment), transformed momentum (transformed_momentum_moment),
 // v^(0) (v_(0)) and the closed-form drag solve v^(1) (v_(1), velocity_coefficients) of a cell
@@ -852,14 +852,14 @@ __device__ __forceinline__ void collide_stream(P *__restrict__ f,
 
 // Pass one of the two-pass scheme: the record (rho, v^(1)) of every cell.
 template <int D, typename T, typename P, bool SOLIDS, int PH>
-__global__ __launch_bounds__(256) void k_moments(const P *__restrict__ f,
+__device__ __forceinline__ void moments_body(const P *__restrict__ f,
                                                  const T *__restrict__ eps,
                                                  const T *__restrict__ muD,
                                                  const T *__restrict__ muF,
                                                  const uint8_t *__restrict__ mask,
                                                  P4<T> *__restrict__ m1_out, Grid g, Tiling tl,
-                                                 Phys<T> ph) {
-    LBM_CELL_PROLOGUE(D)
+                                                 Phys<T> ph, uint32_t wg) {
+    LBM_CELL_PROLOGUE_W(D, wg)
     using L = Lat<D>;
     if constexpr (SOLIDS) {
         if (mask[n]) {
@@ -880,13 +880,13 @@ __global__ __launch_bounds__(256) void k_moments(const P *__restrict__ f,
 // `own_src` and the neighbour records from `m1` (the same buffer in the two-pass scheme; the
 // previous step's records when the lagged scheme reports moments), writes (rho, v).
 template <int D, typename T, bool SOLIDS>
-__global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ own_src,
+__device__ __forceinline__ void vcorrect_body(const P4<T> *__restrict__ own_src,
                                                   const P4<T> *__restrict__ m1,
                                                   const T *__restrict__ eps,
                                                   const uint8_t *__restrict__ mask,
                                                   P4<T> *__restrict__ m2_out, Grid g, Tiling tl,
-                                                  Phys<T> ph) {
-    LBM_CELL_PROLOGUE(D)
+                                                  Phys<T> ph, uint32_t wg) {
+    LBM_CELL_PROLOGUE_W(D, wg)
     if constexpr (SOLIDS) {
         if (mask[n]) {
             *at(m2_out, n) = pack(T(0), T(0), T(0), T(0));
@@ -902,14 +902,14 @@ __global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ own_
 
 // Pass two of the two-pass scheme: forcing from the (rho, v) records, collision, streaming.
 template <int D, typename T, typename P, bool SOLIDS, int PH>
-__global__ __launch_bounds__(256) void k_collide(P *__restrict__ f,
+__device__ __forceinline__ void collide_body(P *__restrict__ f,
                                                  const P4<T> *__restrict__ m2,
                                                  const T *__restrict__ eps,
                                                  const T *__restrict__ muD,
                                                  const T *__restrict__ muF,
                                                  const uint8_t *__restrict__ mask, Grid g,
-                                                 Tiling tl, Phys<T> ph) {
-    LBM_CELL_PROLOGUE(D)
+                                                 Tiling tl, Phys<T> ph, uint32_t wg) {
+    LBM_CELL_PROLOGUE_W(D, wg)
     using L = Lat<D>;
     if constexpr (SOLIDS) {
         if (mask[n]) return;
@@ -936,15 +936,15 @@ __global__ __launch_bounds__(256) void k_collide(P *__restrict__ f,
 // records go to m1n / m2n for the next step.  A steady state of this scheme is a steady state
 // of the two-pass scheme.
 template <int D, typename T, typename P, bool SOLIDS, int PH>
-__global__ __launch_bounds__(256) void k_fused(P *__restrict__ f, const P4<T> *__restrict__ m1p,
+__device__ __forceinline__ void fused_body(P *__restrict__ f, const P4<T> *__restrict__ m1p,
                                                const P4<T> *__restrict__ m2p,
                                                P4<T> *__restrict__ m1n, P4<T> *__restrict__ m2n,
                                                const T *__restrict__ eps,
                                                const T *__restrict__ muD,
                                                const T *__restrict__ muF,
                                                const uint8_t *__restrict__ mask, Grid g,
-                                               Tiling tl, Phys<T> ph) {
-    LBM_CELL_PROLOGUE(D)
+                                               Tiling tl, Phys<T> ph, uint32_t wg) {
+    LBM_CELL_PROLOGUE_W(D, wg)
     using L = Lat<D>;
     if constexpr (SOLIDS) {
         if (mask[n]) {
@@ -968,6 +968,51 @@ __global__ __launch_bounds__(256) void k_fused(P *__restrict__ f, const P4<T> *_
                                         own_base<P>(eps, ph, n), peq, pst);
     store_rec<D>(m1n, n, own1.r, own1.w);
     store_rec<D>(m2n, n, own2.r, own2.w);
+}
+
+// Single-run kernels: workgroup w handles tile w of the run.
+template <int D, typename T, typename P, bool SOLIDS, int PH>
+__global__ __launch_bounds__(256) void k_moments(const P *__restrict__ f,
+                                                 const T *__restrict__ eps,
+                                                 const T *__restrict__ muD,
+                                                 const T *__restrict__ muF,
+                                                 const uint8_t *__restrict__ mask,
+                                                 P4<T> *__restrict__ m1_out, Grid g, Tiling tl,
+                                                 Phys<T> ph) {
+    moments_body<D, T, P, SOLIDS, PH>(f, eps, muD, muF, mask, m1_out, g, tl, ph, blockIdx.x);
+}
+
+template <int D, typename T, bool SOLIDS>
+__global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ own_src,
+                                                  const P4<T> *__restrict__ m1,
+                                                  const T *__restrict__ eps,
+                                                  const uint8_t *__restrict__ mask,
+                                                  P4<T> *__restrict__ m2_out, Grid g, Tiling tl,
+                                                  Phys<T> ph) {
+    vcorrect_body<D, T, SOLIDS>(own_src, m1, eps, mask, m2_out, g, tl, ph, blockIdx.x);
+}
+
+template <int D, typename T, typename P, bool SOLIDS, int PH>
+__global__ __launch_bounds__(256) void k_collide(P *__restrict__ f,
+                                                 const P4<T> *__restrict__ m2,
+                                                 const T *__restrict__ eps,
+                                                 const T *__restrict__ muD,
+                                                 const T *__restrict__ muF,
+                                                 const uint8_t *__restrict__ mask, Grid g,
+                                                 Tiling tl, Phys<T> ph) {
+    collide_body<D, T, P, SOLIDS, PH>(f, m2, eps, muD, muF, mask, g, tl, ph, blockIdx.x);
+}
+
+template <int D, typename T, typename P, bool SOLIDS, int PH>
+__global__ __launch_bounds__(256) void k_fused(P *__restrict__ f, const P4<T> *__restrict__ m1p,
+                                               const P4<T> *__restrict__ m2p,
+                                               P4<T> *__restrict__ m1n, P4<T> *__restrict__ m2n,
+                                               const T *__restrict__ eps,
+                                               const T *__restrict__ muD,
+                                               const T *__restrict__ muF,
+                                               const uint8_t *__restrict__ mask, Grid g,
+                                               Tiling tl, Phys<T> ph) {
+    fused_body<D, T, P, SOLIDS, PH>(f, m1p, m2p, m1n, m2n, eps, muD, muF, mask, g, tl, ph, blockIdx.x);
 }
 
 // Initial populations, eq. (eq_bc_f_bar) with lambda = dt = 1, from the moment fields (rho, v):
@@ -1176,7 +1221,7 @@ __global__ __launch_bounds__(256) void k_stats(const P *__restrict__ f,
     }
 }
 
-__global__ __launch_bounds__(256) void k_stats_final(const double *__restrict__ partial,
+static __global__ __launch_bounds__(256) void k_stats_final(const double *__restrict__ partial,
                                                      int nblocks, double *__restrict__ out) {
     double acc[kStatsSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblocks; b += 256) {

@@ -181,3 +181,59 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.lbm_step(None, 1) == capi.LBM_ERR_INVALID_ARG
     assert lib.lbm_residual(None, None) == capi.LBM_ERR_INVALID_ARG
     assert lib.lbm_destroy(None) == capi.LBM_OK
+
+
+# --------------------------------------------------------------------------------------------
+# Request server: host-side validation and bookkeeping (no device work before progress)
+# --------------------------------------------------------------------------------------------
+_FAKE_POOL = 1 << 40          # 256-byte aligned, never dereferenced by these calls
+
+
+def test_server_rejects_bad_configuration():
+    for args, code in [((_FAKE_POOL, 1 << 30, 99, 0), capi.LBM_ERR_INVALID_ARG),   # odd round
+                       ((_FAKE_POOL, 1 << 30, 0, 0), capi.LBM_ERR_INVALID_ARG),
+                       ((_FAKE_POOL, 1 << 30, 100, -1), capi.LBM_ERR_INVALID_ARG),
+                       ((_FAKE_POOL, 1 << 10, 100, 0), capi.LBM_ERR_WORKSPACE),    # tiny pool
+                       ((_FAKE_POOL + 8, 1 << 30, 100, 0), capi.LBM_ERR_WORKSPACE)]:
+        with pytest.raises(capi.LbmError) as ei:
+            capi.lbm_server_create(*args, 0)
+        assert ei.value.code == code, args
+
+
+def test_server_submit_copies_and_queues():
+    s = capi.lbm_server_create(_FAKE_POOL, 1 << 30, 100, 0, 0)
+    try:
+        p, keep = _params(shape=(4, 5, 6))
+        rid = capi.lbm_server_submit(s, p, 1e-7, 1000)
+        keep[0][:] = 7.0                           # the server holds its own copy
+        p2, keep2 = _params(lattice=capi.LBM_D2Q9, shape=(1, 8, 8))
+        rid2 = capi.lbm_server_submit(s, p2, 1e-6, 200)
+        assert (rid, rid2) == (0, 1)
+        info = capi.lbm_server_info(s, rid)
+        assert info.state == capi.LBM_REQ_QUEUED and info.cells == 120
+        assert info.workspace_bytes == capi.lbm_footprint(_params(shape=(4, 5, 6))[0])
+        assert info.t_admit == -1 and info.t_done == -1 and info.steps == 0
+        st = capi.lbm_server_get_stats(s)
+        assert (st.submitted, st.queued, st.active, st.pool_used) == (2, 2, 0, 0)
+        with pytest.raises(capi.LbmError) as ei:          # not finished
+            capi.lbm_server_release(s, rid)
+        assert ei.value.code == capi.LBM_ERR_STATE
+        with pytest.raises(capi.LbmError) as ei:          # holds no state yet
+            capi.lbm_server_solver(s, rid)
+        assert ei.value.code == capi.LBM_ERR_STATE
+        for bad in [dict(tol=0.0), dict(max_steps=50)]:
+            kw = dict(tol=1e-7, max_steps=1000)
+            kw.update(bad)
+            with pytest.raises(capi.LbmError) as ei:
+                capi.lbm_server_submit(s, p, kw["tol"], kw["max_steps"])
+            assert ei.value.code == capi.LBM_ERR_INVALID_ARG
+        big, keep3 = _params(shape=(96, 96, 96))
+        with pytest.raises(capi.LbmError) as ei:          # can never fit a 64 MiB pool
+            s2 = capi.lbm_server_create(_FAKE_POOL, 64 << 20, 100, 0, 0)
+            try:
+                capi.lbm_server_submit(s2, big, 1e-7, 1000)
+            finally:
+                capi.lbm_server_destroy(s2)
+        assert ei.value.code == capi.LBM_ERR_WORKSPACE
+    finally:
+        capi.lbm_server_destroy(s)

@@ -1,0 +1,161 @@
+"""GPU tests of the request server (continuous batching): every run's result is bitwise the
+one of the same run stepped alone, whatever else shares its batched launches; admission
+respects the device pool; convergence, censoring and failure are reported per request."""
+
+import numpy as np
+import pytest
+
+from paper_2606_29619_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+capi = pytest.importorskip("paper_2606_29619_amd.capi")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    capi.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def _mix():
+    """Runs of every kind a batch can hold: both lattices, all storages, both schemes, with
+    and without solid cells, ragged shapes."""
+    a = workloads.random_porosity_2d(nx=70, ny=45, seed=1, ell=6.0, nu=0.02, b=1e-5)
+    b = workloads.random_porosity_3d(shape=(12, 20, 33), seed=2, ell=4.0, nu=0.03, b=1e-5)
+    c = workloads.random_porosity_3d(shape=(9, 7, 130), seed=3, ell=3.0, nu=0.04, b=2e-5)
+    m = np.zeros(c.shape, np.uint8)
+    m[2:5, 1:4, 10:30] = 1
+    m[:, 0, 60:64] = 1
+    c.mask = m
+    d = workloads.random_porosity_2d(nx=130, ny=64, seed=4, ell=8.0, nu=0.01, b=1e-5)
+    e = workloads.random_porosity_3d(shape=(16, 16, 16), seed=5, ell=5.0, nu=0.02, b=1e-5)
+    e.eta_eff = 0.01
+    return [
+        (a, capi.LBM_F32, capi.LBM_SCHEME_TWO_PASS),
+        (b, capi.LBM_F32, capi.LBM_SCHEME_LAGGED),
+        (c, capi.LBM_F64, capi.LBM_SCHEME_TWO_PASS),
+        (d, capi.LBM_F16_SHIFTED, capi.LBM_SCHEME_TWO_PASS),
+        (e, capi.LBM_BF16_SHIFTED, capi.LBM_SCHEME_LAGGED),
+        (b, capi.LBM_F32, capi.LBM_SCHEME_TWO_PASS),
+        (a, capi.LBM_F64, capi.LBM_SCHEME_LAGGED),
+        (c, capi.LBM_F32, capi.LBM_SCHEME_LAGGED),
+    ]
+
+
+def _alone(w, storage, scheme, steps):
+    s = capi.Solver.from_workload(w, storage=storage, scheme=scheme, shift=capi.LBM_SHIFT_POROUS)
+    s.step(steps)
+    return s
+
+
+def _same(srv_solver, ref):
+    fa = srv_solver.populations(torch.float64).cpu().numpy()
+    fb = ref.populations(torch.float64).cpu().numpy()
+    ra, va = (t.cpu().numpy() for t in srv_solver.moments(torch.float64))
+    rb, vb = (t.cpu().numpy() for t in ref.moments(torch.float64))
+    return np.array_equal(fa, fb) and np.array_equal(ra, rb) and np.array_equal(va, vb)
+
+
+def _drain(srv, max_rounds=10000):
+    done = []
+    for _ in range(max_rounds):
+        done += srv.progress(1)
+        st = srv.stats()
+        if st.queued == 0 and st.active == 0:
+            return done
+    raise AssertionError("server did not drain")
+
+
+def test_each_result_is_bitwise_the_same_alone_and_in_the_mix():
+    """Eight runs of every kind share the batched launches for 300 steps (censored: the
+    tolerance is unreachable); each run's populations and moments equal, bit for bit, those
+    of the same run stepped alone with lbm_step."""
+    srv = capi.Server(pool_bytes=512 << 20, check_every=100)
+    ids = [srv.submit(w, storage=st, scheme=sc, tol=1e-300, max_steps=300)
+           for w, st, sc in _mix()]
+    done = _drain(srv)
+    assert sorted(done) == sorted(ids)
+    for rid, (w, st, sc) in zip(ids, _mix()):
+        info = srv.info(rid)
+        assert info.state == capi.LBM_REQ_CENSORED and info.steps == 300, (rid, info.state)
+        assert info.t_submit <= info.t_admit <= info.t_done
+        ref = _alone(w, st, sc, 300)
+        assert _same(srv.solver(rid), ref), f"request {rid} differs from its run alone"
+        srv.release(rid)
+    st = srv.stats()
+    assert st.pool_used == 0 and st.finished == len(ids) and st.rounds == 3
+    assert st.cell_updates == sum(w.cells for w, _, _ in _mix()) * 300
+
+
+def test_admission_by_footprint_queues_and_backfills():
+    """A pool that holds about two of the runs at a time: requests wait, are admitted as
+    memory frees, never exceed the pool, and still give their runs-alone results."""
+    runs = _mix()[:5]
+    foot = []
+    for w, st, sc in runs:
+        p, _k = capi.make_params(w.lattice, st, w.eps, w.kappa, w.forch, w.mask, scheme=sc)
+        foot.append(capi.lbm_footprint(p))
+    # room for the descriptor table (~1.2 MiB), the largest run and about 1.3 MiB more
+    pool = max(foot) + (5 << 19)
+    srv = capi.Server(pool_bytes=pool, check_every=100)
+    ids = [srv.submit(w, storage=st, scheme=sc, tol=1e-300, max_steps=200) for w, st, sc in runs]
+    max_active = 0
+    finished = []
+    for _ in range(1000):
+        for rid in srv.progress(1):
+            finished.append(rid)
+            ref = _alone(*runs[ids.index(rid)], 200)
+            assert _same(srv.solver(rid), ref)
+            srv.release(rid)
+        st = srv.stats()
+        max_active = max(max_active, st.active)
+        assert st.pool_peak <= pool
+        if st.queued == 0 and st.active == 0:
+            break
+    assert sorted(finished) == sorted(ids)
+    assert 1 <= max_active < len(runs)
+    assert max(srv.info(rid).t_admit for rid in ids) > min(srv.info(rid).t_done for rid in ids)
+    for rid in ids:
+        info = srv.info(rid)
+        assert info.state == capi.LBM_REQ_CENSORED and info.t_admit >= info.t_submit
+
+
+def test_convergence_is_detected_per_request():
+    """A strongly damped small run converges (relative change of v over a round below tol)
+    after a whole number of rounds, while a weakly damped one in the same batch goes on; the
+    converged state equals the run alone after the same steps."""
+    fast = workloads.random_porosity_2d(nx=32, ny=24, seed=7, ell=4.0, phi_min=0.2, nu=0.1,
+                                        b=1e-5)
+    slow = workloads.random_porosity_3d(shape=(24, 24, 24), seed=8, ell=8.0, phi_min=0.5,
+                                        nu=0.005, b=1e-6)
+    srv = capi.Server(pool_bytes=256 << 20, check_every=100)
+    f_id = srv.submit(fast, storage=capi.LBM_F64, tol=1e-6, max_steps=20000)
+    s_id = srv.submit(slow, storage=capi.LBM_F32, tol=1e-12, max_steps=400)
+    _drain(srv)
+    fi, si = srv.info(f_id), srv.info(s_id)
+    assert fi.state == capi.LBM_REQ_CONVERGED and fi.residual < 1e-6
+    assert fi.steps % 100 == 0 and 200 <= fi.steps < 20000
+    assert si.state == capi.LBM_REQ_CENSORED and si.steps == 400 and si.residual > 1e-12
+    ref = _alone(fast, capi.LBM_F64, capi.LBM_SCHEME_TWO_PASS, fi.steps)
+    assert _same(srv.solver(f_id), ref)
+
+
+def test_diverging_request_fails_without_disturbing_others():
+    """The literal porosity step diverges (non-finite within tens of steps): its request is
+    reported failed after its first round; a healthy request in the same batch completes and
+    matches its run alone."""
+    bad = workloads.channel_step_2d(smooth_width=0)
+    good = workloads.random_porosity_2d(nx=48, ny=40, seed=9, ell=5.0, nu=0.03, b=1e-5)
+    srv = capi.Server(pool_bytes=128 << 20, check_every=100)
+    b_id = srv.submit(bad, storage=capi.LBM_F64, tol=1e-9, max_steps=1000)
+    g_id = srv.submit(good, storage=capi.LBM_F64, tol=1e-300, max_steps=300)
+    _drain(srv)
+    assert srv.info(b_id).state == capi.LBM_REQ_FAILED and srv.info(b_id).steps == 100
+    gi = srv.info(g_id)
+    assert gi.state == capi.LBM_REQ_CENSORED and gi.steps == 300
+    assert _same(srv.solver(g_id), _alone(good, capi.LBM_F64, capi.LBM_SCHEME_TWO_PASS, 300))
