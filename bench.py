@@ -55,7 +55,8 @@ def method_bytes_per_cell(Q, D, sp, s, lagged=False):
 
 def source_hash():
     h = hashlib.sha256()
-    for rel in ("paper_2606_29619_amd/csrc/lbm_device.hpp", "paper_2606_29619_amd/csrc/lbm.hip"):
+    for rel in ("paper_2606_29619_amd/csrc/lbm_device.hpp", "paper_2606_29619_amd/csrc/lbm_host.hpp",
+                "paper_2606_29619_amd/csrc/lbm.hip"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -97,6 +98,34 @@ def cpu_baseline(budget_s=15.0):
                       f"(seed 0), {k} timed steps after 1 warm-up step, {dt:.1f} s"}
 
 
+def serving_sample(n_requests, max_steps):
+    """The first n_requests of the serving stream (seed 0), FP32 and FP16-shifted storage:
+    a closed batch measures the server's capacity (requests/s), then the same requests arrive
+    as a Poisson process at 1.0x that rate.  Runs stop at steady state (relative L2 change of
+    v over 100 steps below 1e-7) or at max_steps (censored)."""
+    import torch
+    from paper_2606_29619_amd import capi, serving, workloads
+    stream = workloads.request_stream(n_requests, 0)
+    out = {"sample": f"first {n_requests} requests of the 512-request stream (seed 0), "
+                     f"step cap {max_steps}, tol 1e-7 per 100 steps; open run at 1.0x the "
+                     f"closed-batch capacity", "cells_total": None}
+    cache = {}
+    for name, st in (("f32", capi.LBM_F32), ("f16_shifted", capi.LBM_F16_SHIFTED)):
+        closed = serving.serve(stream, st, None, 1e-7, max_steps, cache=cache)
+        rate = closed["requests"] / closed["wall_s"]
+        opened = serving.serve(stream, st, rate, 1e-7, max_steps, cache=cache)
+        keep = ("served_MLUPS", "wall_s", "converged", "censored", "failed",
+                "p50_time_to_steady_s", "p99_time_to_steady_s", "p50_time_in_system_s",
+                "p99_time_in_system_s")
+        out[name] = {"closed": {k: closed[k] for k in keep},
+                     "open": dict({k: opened[k] for k in keep}, arrival_rate_per_s=round(rate, 4))}
+        print(f"[bench] serving {name}: closed {closed['served_MLUPS']} MLUPS, open p99 in "
+              f"system {opened['p99_time_in_system_s']:.2f} s", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    out["cells_total"] = int(sum(cache[k].cells for k in cache))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +140,10 @@ def main():
                     help="two-pass: the method as written (headline); lagged: single fused pass "
                          "with previous-step neighbour moments")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the bounded serving-stream sample")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-max-steps", type=int, default=5000)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB "
                          "(counter calibration for profiling runs)")
@@ -217,6 +250,8 @@ def main():
         torch.cuda.synchronize()
         line["copy_probe_bytes"] = {"read": nb, "write": nb}
         del a, b
+    if not args.no_serving:
+        line["serving"] = serving_sample(args.serve_requests, args.serve_max_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
