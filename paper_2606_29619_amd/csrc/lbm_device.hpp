@@ -188,6 +188,56 @@ struct Nbr {
 };
 
 // ------------------------------------------------------------------------------------------
+// Porosity of the cell's periodic 3x3(x3) neighbourhood.  The tiled kernels stage the porosity
+// of their tile and its one-cell halo in LDS once (coalesced rows) and read every neighbour
+// from there; the other kernels read global memory.  at(dx, dy, dz) with |d| <= 1.
+// ------------------------------------------------------------------------------------------
+template <int D, typename T>
+struct EpsGlobal {
+    const T *eps;
+    const Nbr<D> *nb;
+    __device__ __forceinline__ T at(int dx, int dy, int dz) const {
+        return ld(eps, nb->at(dx, dy, dz));
+    }
+};
+
+template <int D, typename T>
+struct EpsTile {
+    // the largest halo: a 256 x 1 tile, (256 + 2) x 3 rows per plane, 3 planes in 3D
+    static constexpr int kSize = D == 3 ? 258 * 3 * 3 : 258 * 3;
+    const T *lds;
+    int lx, ly;      // the cell within the tile
+    int row, rows;   // halo row length (tx + 2) and rows per plane (ty + 2)
+    __device__ __forceinline__ T at(int dx, int dy, int dz) const {
+        const int pz = D == 3 ? dz + 1 : 0;
+        return lds[(pz * rows + ly + 1 + dy) * row + lx + 1 + dx];
+    }
+};
+
+// Stage the porosity of the tile with origin (x0, y0) in plane z0 and its periodic halo.
+// Every thread of the workgroup takes part; the caller synchronises afterwards.
+template <int D, typename T>
+__device__ __forceinline__ void stage_eps(const T *__restrict__ eps, const Grid &g, int tx,
+                                          int ty, int x0, int y0, int z0, T *lds) {
+    const int row = tx + 2, rows = ty + 2;
+    const int t = (int)threadIdx.x;
+    const int c0 = x0 + t - 1, c1 = x0 + t + 255;  // columns of this thread (row <= 258)
+    const uint32_t gx0 = (uint32_t)(c0 < 0 ? c0 + g.nx : c0 % g.nx);
+    const uint32_t gx1 = (uint32_t)(c1 % g.nx);
+    constexpr int planes = D == 3 ? 3 : 1;
+    for (int pz = 0; pz < planes; ++pz) {
+        const int zz = D == 3 ? wrapk(z0, pz - 1, g.nz) : z0;
+        for (int py = 0; py < rows; ++py) {
+            const int yy = wrapk(y0, py - 1, g.ny);
+            const uint32_t base = (uint32_t)g.nx * ((uint32_t)yy + (uint32_t)g.ny * (uint32_t)zz);
+            T *dst = lds + (pz * rows + py) * row;
+            if (t < row) dst[t] = ld(eps, base + gx0);
+            if (t + 256 < row) dst[t + 256] = ld(eps, base + gx1);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Population storage formats.  FP64 and FP32 slots hold f-bar itself.  The 16-bit formats
 // (FP16, BF16) hold the deviation from a shift, scaled per direction,
 //     slot = (f-bar_i - sigma_i) * 2^k_i,    sigma_i = base * w_i,
@@ -235,14 +285,14 @@ __device__ __forceinline__ constexpr float enc_scale() {
     return p;
 }
 
-// Shift sigma_I = base * w_I of a value produced by cell m (16-bit formats; FP32 product).
+// Shift sigma_I = base * w_I of a value produced by a cell of porosity e_src (16-bit formats;
+// FP32 product).
 template <int D, int I, typename P, typename T>
-__device__ __forceinline__ float shift_sigma(const T *__restrict__ eps, const Phys<T> &ph,
-                                             uint32_t m) {
+__device__ __forceinline__ float shift_sigma(T e_src, const Phys<T> &ph) {
     if constexpr (!PopFmt<P>::shifted) {
         return 0.0f;
     } else {
-        const float base = ph.shift_porous ? ph.rho0 * ld(eps, m) : ph.rho0;
+        const float base = ph.shift_porous ? ph.rho0 * e_src : ph.rho0;
         return base * weight<D, I>();
     }
 }
@@ -308,21 +358,29 @@ __device__ __forceinline__ P load_raw(const P *__restrict__ f, const uint8_t *__
     }
 }
 
-// Shift of the f_I found at cell n (0 for FP64/FP32 storage).
-template <int D, bool SOLIDS, int I, typename P, typename T>
-__device__ __forceinline__ float load_sigma(const uint8_t *__restrict__ mask,
-                                            const T *__restrict__ eps, const Phys<T> &ph,
-                                            const Nbr<D> &nb) {
-    if constexpr (!PopFmt<P>::shifted) return 0.0f;
-    else return shift_sigma<D, I, P>(eps, ph, source_cell<D, SOLIDS, I>(mask, nb));
+// Shift of the f_I found at cell n (0 for FP64/FP32 storage): the porosity of its source cell,
+// the upstream neighbour n - c_I or n itself after a bounce-back.
+template <int D, bool SOLIDS, int I, typename P, typename T, typename E>
+__device__ __forceinline__ float load_sigma(const uint8_t *__restrict__ mask, const E &ev,
+                                            const Phys<T> &ph, const Nbr<D> &nb) {
+    if constexpr (!PopFmt<P>::shifted) {
+        return 0.0f;
+    } else {
+        using L = Lat<D>;
+        constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+        if (!ph.shift_porous) return shift_sigma<D, I, P>(T(1), ph);
+        const bool own = (cx == 0 && cy == 0 && cz == 0) ||
+                         (SOLIDS && source_cell<D, SOLIDS, I>(mask, nb) == nb.self());
+        return shift_sigma<D, I, P>(own ? ev.at(0, 0, 0) : ev.at(-cx, -cy, -cz), ph);
+    }
 }
 
-template <int D, bool SOLIDS, int PH, int I, typename T, typename P>
+template <int D, bool SOLIDS, int PH, int I, typename T, typename P, typename E>
 __device__ __forceinline__ T load_pop(const P *__restrict__ f, const uint8_t *__restrict__ mask,
-                                      const T *__restrict__ eps, const Phys<T> &ph,
-                                      const Grid &g, const Nbr<D> &nb) {
+                                      const E &ev, const Phys<T> &ph, const Grid &g,
+                                      const Nbr<D> &nb) {
     const P raw = load_raw<D, SOLIDS, PH, I>(f, mask, g, nb);
-    return decode<D, I, T>(raw, load_sigma<D, SOLIDS, I, P>(mask, eps, ph, nb));
+    return decode<D, I, T>(raw, load_sigma<D, SOLIDS, I, P>(mask, ev, ph, nb));
 }
 
 // Store of the post-collision f_I of the cell; base is the cell's own shift base
@@ -349,12 +407,11 @@ __device__ __forceinline__ void store_pop(P *__restrict__ f, const uint8_t *__re
     }
 }
 
-// Shift base of the cell itself for store_pop.
+// Shift base of the cell itself (porosity e0) for store_pop.
 template <typename P, typename T>
-__device__ __forceinline__ float own_base(const T *__restrict__ eps, const Phys<T> &ph,
-                                          uint32_t n) {
+__device__ __forceinline__ float own_base(T e0, const Phys<T> &ph) {
     if constexpr (!PopFmt<P>::shifted) return 0.0f;
-    else return ph.shift_porous ? ph.rho0 * ld(eps, n) : ph.rho0;
+    else return ph.shift_porous ? ph.rho0 * e0 : ph.rho0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -385,14 +442,13 @@ __device__ __forceinline__ Visc<T> viscosity(const Phys<T> &ph, T e) {
 
 // Porosity gradient and Hessian by central differences (eps is defined on every cell); the
 // mixed derivatives come from the four diagonal neighbours, computed once for a < b.
-template <int D, typename T>
-__device__ __forceinline__ void porosity_derivatives(const T *__restrict__ eps, const Nbr<D> &nb,
-                                                     T e0, T ge[3], T H[3][3]) {
+template <int D, typename T, typename E>
+__device__ __forceinline__ void porosity_derivatives(const E &ev, T e0, T ge[3], T H[3][3]) {
     unroll<0, D>([&](auto ia) {
         constexpr int a = decltype(ia)::value;
         constexpr int px = a == 0, py = a == 1, pz = a == 2;
-        const T ep = ld(eps, nb.at(px, py, pz));
-        const T em = ld(eps, nb.at(-px, -py, -pz));
+        const T ep = ev.at(px, py, pz);
+        const T em = ev.at(-px, -py, -pz);
         ge[a] = (ep - em) * T(0.5);
         H[a][a] = (ep - T(2) * e0) + em;
     });
@@ -403,10 +459,10 @@ __device__ __forceinline__ void porosity_derivatives(const T *__restrict__ eps, 
             // offsets of the diagonal neighbour (ka along a, kb along b)
             constexpr int ax0 = a == 0, ay0 = a == 1, az0 = a == 2;
             constexpr int bx0 = b == 0, by0 = b == 1, bz0 = b == 2;
-            const T pp = ld(eps, nb.at(ax0 + bx0, ay0 + by0, az0 + bz0));
-            const T pm = ld(eps, nb.at(ax0 - bx0, ay0 - by0, az0 - bz0));
-            const T mp = ld(eps, nb.at(-ax0 + bx0, -ay0 + by0, -az0 + bz0));
-            const T mm = ld(eps, nb.at(-ax0 - bx0, -ay0 - by0, -az0 - bz0));
+            const T pp = ev.at(ax0 + bx0, ay0 + by0, az0 + bz0);
+            const T pm = ev.at(ax0 - bx0, ay0 - by0, az0 - bz0);
+            const T mp = ev.at(-ax0 + bx0, -ay0 + by0, -az0 + bz0);
+            const T mm = ev.at(-ax0 - bx0, -ay0 - by0, -az0 - bz0);
             const T h = (((pp - pm) - mp) + mm) * T(0.25);
             H[a][b] = h;
             H[b][a] = h;
@@ -458,15 +514,14 @@ struct Rec {
 };
 
 template <int D, typename T>
-__device__ __forceinline__ Rec<T> load_rec(const P4<T> *__restrict__ m,
-                                           const T *__restrict__ eps, uint32_t idx) {
+__device__ __forceinline__ Rec<T> load_rec(const P4<T> *__restrict__ m, uint32_t idx, T e) {
     const P4<T> q4 = ld(m, idx);
     Rec<T> q;
     q.r = q4.x;
     q.w[0] = q4.y;
     q.w[1] = q4.z;
     q.w[2] = q4.w;
-    q.e = ld(eps, idx);
+    q.e = e;
     return q;
 }
 
@@ -478,17 +533,17 @@ __device__ __forceinline__ void rec_m(const Rec<T> &q, T m[3]) {
 }
 
 // Load the axis neighbours of the cell with their fluid flags.
-template <int D, typename T, bool SOLIDS>
-__device__ __forceinline__ void load_stencil(const P4<T> *__restrict__ mom,
-                                             const T *__restrict__ eps,
+template <int D, typename T, bool SOLIDS, typename E>
+__device__ __forceinline__ void load_stencil(const P4<T> *__restrict__ mom, const E &ev,
                                              const uint8_t *__restrict__ mask, const Grid &g,
                                              const Nbr<D> &nb, Rec<T> rec[3][2], bool fl[3][2]) {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            const uint32_t m = nb.axis(g, a, s ? 1 : -1);
-            rec[a][s] = load_rec<D>(mom, eps, m);
+            const int k = s ? 1 : -1;
+            const uint32_t m = nb.axis(g, a, k);
+            rec[a][s] = load_rec<D>(mom, m, ev.at(a == 0 ? k : 0, a == 1 ? k : 0, a == 2 ? k : 0));
             fl[a][s] = SOLIDS ? !mask[m] : true;
         }
     }
@@ -523,12 +578,12 @@ __device__ __forceinline__ void delta_nu(const P4<T> *__restrict__ mom,
             if (fl[a][1] && !fl[a][0]) {
                 const uint32_t p2 = nb.axis(g, a, 2);
                 f5[4] = !mask[p2];
-                if (f5[4]) rec_m<D>(load_rec<D>(mom, eps, p2), m2p);
+                if (f5[4]) rec_m<D>(load_rec<D>(mom, p2, ld(eps, p2)), m2p);
             }
             if (fl[a][0] && !fl[a][1]) {
                 const uint32_t m2 = nb.axis(g, a, -2);
                 f5[0] = !mask[m2];
-                if (f5[0]) rec_m<D>(load_rec<D>(mom, eps, m2), m2m);
+                if (f5[0]) rec_m<D>(load_rec<D>(mom, m2, ld(eps, m2)), m2m);
             }
 #pragma unroll
             for (int b = 0; b < D; ++b) {
@@ -576,12 +631,12 @@ __device__ __forceinline__ T record_deriv(const P4<T> *__restrict__ mom,
     if (fl[a][1] && !fl[a][0]) {
         const uint32_t p2 = nb.axis(g, a, 2);
         f5[4] = !mask[p2];
-        if (f5[4]) v5[4] = fn(load_rec<D>(mom, eps, p2));
+        if (f5[4]) v5[4] = fn(load_rec<D>(mom, p2, ld(eps, p2)));
     }
     if (fl[a][0] && !fl[a][1]) {
         const uint32_t m2 = nb.axis(g, a, -2);
         f5[0] = !mask[m2];
-        if (f5[0]) v5[0] = fn(load_rec<D>(mom, eps, m2));
+        if (f5[0]) v5[0] = fn(load_rec<D>(mom, m2, ld(eps, m2)));
     }
     return deriv_rule(v5, f5);
 }
@@ -591,8 +646,8 @@ __device__ __forceinline__ T record_deriv(const P4<T> *__restrict__ mom,
 // P_alpha_alpha_eq) and xi*, P* (xi_alpha_*, P_aa_*) with lambda = 1.  `own` is the cell's
 // record; the neighbour records come from `mom` (the same step's, or the previous step's in
 // the lagged scheme).
-template <int D, typename T, bool SOLIDS>
-__device__ __forceinline__ void forcing_args(const P4<T> *__restrict__ mom,
+template <int D, typename T, bool SOLIDS, typename E>
+__device__ __forceinline__ void forcing_args(const P4<T> *__restrict__ mom, const E &ev,
                                              const T *__restrict__ eps,
                                              const T *__restrict__ muD,
                                              const T *__restrict__ muF,
@@ -604,7 +659,7 @@ __device__ __forceinline__ void forcing_args(const P4<T> *__restrict__ mom,
     const uint32_t n = nb.self();
     Rec<T> rec[3][2];
     bool fl[3][2];
-    load_stencil<D, T, SOLIDS>(mom, eps, mask, g, nb, rec, fl);
+    load_stencil<D, T, SOLIDS>(mom, ev, mask, g, nb, rec, fl);
     T dm[3] = {T(0), T(0), T(0)};
     delta_nu<D, T, SOLIDS>(mom, eps, mask, g, nb, own, rec, fl, ge, H, vs, dm);
     T s = T(0);
@@ -688,20 +743,18 @@ struct CellStatic {
     Visc<T> vs;
 };
 
-template <int D, typename T>
-__device__ __forceinline__ CellStatic<D, T> cell_static(const T *__restrict__ eps,
-                                                        const Nbr<D> &nb, const Phys<T> &ph,
-                                                        T e0) {
+template <int D, typename T, typename E>
+__device__ __forceinline__ CellStatic<D, T> cell_static(const E &ev, const Phys<T> &ph, T e0) {
     CellStatic<D, T> c;
-    porosity_derivatives<D>(eps, nb, e0, c.ge, c.H);
+    porosity_derivatives<D>(ev, e0, c.ge, c.H);
     c.vs = viscosity(ph, e0);
     return c;
 }
 
 // Velocity correction (v_final): v = v^(1) + Delta_nu(rho v^(1) / eps) / (2 rho) from the
 // cell's own record (rho, v^(1)) and the neighbour records in `m1`.
-template <int D, typename T, bool SOLIDS>
-__device__ __forceinline__ void corrected_velocity(const P4<T> *__restrict__ m1,
+template <int D, typename T, bool SOLIDS, typename E>
+__device__ __forceinline__ void corrected_velocity(const P4<T> *__restrict__ m1, const E &ev,
                                                    const T *__restrict__ eps,
                                                    const uint8_t *__restrict__ mask,
                                                    const Grid &g, const Nbr<D> &nb,
@@ -709,7 +762,7 @@ __device__ __forceinline__ void corrected_velocity(const P4<T> *__restrict__ m1,
                                                    T v[3]) {
     Rec<T> rec[3][2];
     bool fl[3][2];
-    load_stencil<D, T, SOLIDS>(m1, eps, mask, g, nb, rec, fl);
+    load_stencil<D, T, SOLIDS>(m1, ev, mask, g, nb, rec, fl);
     T dn[3];
     delta_nu<D, T, SOLIDS>(m1, eps, mask, g, nb, own, rec, fl, cs.ge, cs.H, cs.vs, dn);
 #pragma unroll
@@ -719,8 +772,8 @@ __device__ __forceinline__ void corrected_velocity(const P4<T> *__restrict__ m1,
 }
 
 // Equilibria of the cell (prod_form) for the equilibrium and shifted-equilibrium arguments.
-template <int D, typename T, bool SOLIDS>
-__device__ __forceinline__ void cell_equilibria(const P4<T> *__restrict__ m2,
+template <int D, typename T, bool SOLIDS, typename E>
+__device__ __forceinline__ void cell_equilibria(const P4<T> *__restrict__ m2, const E &ev,
                                                 const T *__restrict__ eps,
                                                 const T *__restrict__ muD,
                                                 const T *__restrict__ muF,
@@ -729,8 +782,8 @@ __device__ __forceinline__ void cell_equilibria(const P4<T> *__restrict__ m2,
                                                 const Rec<T> &own, const CellStatic<D, T> &cs,
                                                 ProductForm<D, T> &peq, ProductForm<D, T> &pst) {
     T xi[3], P[3], xs[3], Ps[3];
-    forcing_args<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, cs.ge, cs.H, cs.vs, xi,
-                               P, xs, Ps);
+    forcing_args<D, T, SOLIDS>(m2, ev, eps, muD, muF, mask, g, ph, nb, own, cs.ge, cs.H, cs.vs,
+                               xi, P, xs, Ps);
     const T er = own.e * own.r;
     peq.init(er, xi, P);
     pst.init(er, xs, Ps);
@@ -754,36 +807,71 @@ struct Tiling {
     uint32_t per;     // tiles per XCD (padded order)
 };
 
-__device__ __forceinline__ bool tile_cell(const Grid &g, const Tiling &tl, uint32_t w, int &x,
-                                          int &y, int &z) {
+// Cell of this thread in tile w: returns -1 when the whole tile lies outside the order (the
+// same for every thread of the workgroup), 0 when the thread's cell is outside the grid (ragged
+// edge), 1 otherwise; (x0, y0) is the tile origin.
+__device__ __forceinline__ int tile_cell(const Grid &g, const Tiling &tl, uint32_t w, int &x,
+                                         int &y, int &z, int &x0, int &y0) {
     const uint32_t t = (w & 7u) * tl.per + (w >> 3);
     const uint32_t rows_per_block = (uint32_t)tl.by * (uint32_t)tl.bz;
     const uint32_t nt = (uint32_t)tl.ntx * rows_per_block * (uint32_t)tl.nby * (uint32_t)tl.nbz;
-    if (t >= nt) return false;
+    if (t >= nt) return -1;
     const uint32_t tx = t % (uint32_t)tl.ntx;
     const uint32_t r = t / (uint32_t)tl.ntx;
     const uint32_t blk = r / rows_per_block, in = r % rows_per_block;
     const uint32_t ty = (blk % (uint32_t)tl.nby) * (uint32_t)tl.by + in % (uint32_t)tl.by;
     const uint32_t tz = (blk / (uint32_t)tl.nby) * (uint32_t)tl.bz + in / (uint32_t)tl.by;
-    x = (int)(tx * (uint32_t)tl.tx + threadIdx.x % (uint32_t)tl.tx);
-    y = (int)(ty * (uint32_t)tl.ty + threadIdx.x / (uint32_t)tl.tx);
+    x0 = (int)(tx * (uint32_t)tl.tx);
+    y0 = (int)(ty * (uint32_t)tl.ty);
     z = (int)tz;
-    return x < g.nx && y < g.ny && z < g.nz;
+    if (y0 >= g.ny || z >= g.nz) return -1;  // padding of a partial block
+    x = x0 + (int)(threadIdx.x % (uint32_t)tl.tx);
+    y = y0 + (int)(threadIdx.x / (uint32_t)tl.tx);
+    return x < g.nx && y < g.ny ? 1 : 0;
 }
 
+// Cell prologue of the kernels that read porosity from global memory.
 #define LBM_CELL_PROLOGUE_W(D, W)                                    \
-    int x, y, z;                                                     \
-    if (!tile_cell(g, tl, W, x, y, z)) return;                       \
+    int x, y, z, x0_, y0_;                                           \
+    if (tile_cell(g, tl, W, x, y, z, x0_, y0_) != 1) return;         \
     Nbr<D> nb;                                                       \
     nb.init(g, x, y, z);                                             \
-    const uint32_t n = nb.self();
+    const uint32_t n = nb.self();                                    \
+    const EpsGlobal<D, T> ev{eps, &nb};
 #define LBM_CELL_PROLOGUE(D) LBM_CELL_PROLOGUE_W(D, blockIdx.x)
+
+template <int D, bool STAGE, typename T>
+__device__ __forceinline__ auto make_eps_view(const T *eps, const Nbr<D> *nb, const T *lds, int lx,
+                                              int ly, const Tiling &tl) {
+    if constexpr (STAGE) return EpsTile<D, T>{lds, lx, ly, tl.tx + 2, tl.ty + 2};
+    else return EpsGlobal<D, T>{eps, nb};
+}
+
+// Prologue of the tiled passes.  With STAGE the workgroup first stages the porosity of its
+// tile and halo in LDS (all threads, then a barrier) and threads outside the grid leave after
+// it.  Staging pays where a cell reads the porosity of all its neighbours (the porous shift of
+// 16-bit storage); where it reads only the derivative stencil, the barrier's exposed latency
+// costs more than the gathers it saves (measured on the two-pass FP32 kernels).
+#define LBM_TILE_PROLOGUE(D, W, STAGE)                               \
+    int x, y, z, x0_, y0_;                                           \
+    const int act_ = tile_cell(g, tl, W, x, y, z, x0_, y0_);         \
+    if (act_ < 0) return;                                            \
+    __shared__ T eps_lds_[(STAGE) ? EpsTile<D, T>::kSize : 1];       \
+    if constexpr (STAGE) {                                           \
+        stage_eps<D>(eps, g, tl.tx, tl.ty, x0_, y0_, z, eps_lds_);   \
+        __syncthreads();                                             \
+    }                                                                \
+    if (!act_) return;                                               \
+    Nbr<D> nb;                                                       \
+    nb.init(g, x, y, z);                                             \
+    const uint32_t n = nb.self();                                    \
+    const auto ev = make_eps_view<D, (STAGE)>(eps, &nb, eps_lds_, x - x0_, y - y0_, tl);
 
 // Density (transformed_density_moment), transformed momentum (transformed_momentum_moment),
 // v^(0) (v_(0)) and the closed-form drag solve v^(1) (v_(1), velocity_coefficients) of a cell
 // from its populations fi: returns the record (rho, eps, v^(1)).
-template <int D, typename T>
-__device__ __forceinline__ Rec<T> cell_moments(const T fi[], const T *__restrict__ eps,
+template <int D, typename T, typename E>
+__device__ __forceinline__ Rec<T> cell_moments(const T fi[], const E &ev,
                                                const T *__restrict__ muD,
                                                const T *__restrict__ muF, const Nbr<D> &nb,
                                                const Phys<T> &ph) {
@@ -799,13 +887,13 @@ __device__ __forceinline__ Rec<T> cell_moments(const T fi[], const T *__restrict
             else if constexpr (L::c[i][a] == -1) Pi[a] = Pi[a] - fi[i];
         });
     });
-    const T e = ld(eps, n);
+    const T e = ev.at(0, 0, 0);
     const T rho = dv(S, e);
     T v0[3];
     unroll<0, D>([&](auto ia) {
         constexpr int a = decltype(ia)::value;
         constexpr int px = a == 0, py = a == 1, pz = a == 2;
-        const T ge = (ld(eps, nb.at(px, py, pz)) - ld(eps, nb.at(-px, -py, -pz))) * T(0.5);
+        const T ge = (ev.at(px, py, pz) - ev.at(-px, -py, -pz)) * T(0.5);
         v0[a] = dv(Pi[a], rho) + T(0.5) * (e * ph.b[a] + ph.RT * ge);
     });
     const T c1 = T(1) + T(0.5) * ld(muD, n);
@@ -859,7 +947,7 @@ __device__ __forceinline__ void moments_body(const P *__restrict__ f,
                                                  const uint8_t *__restrict__ mask,
                                                  P4<T> *__restrict__ m1_out, Grid g, Tiling tl,
                                                  Phys<T> ph, uint32_t wg) {
-    LBM_CELL_PROLOGUE_W(D, wg)
+    LBM_TILE_PROLOGUE(D, wg, (PopFmt<P>::shifted))
     using L = Lat<D>;
     if constexpr (SOLIDS) {
         if (mask[n]) {
@@ -870,9 +958,9 @@ __device__ __forceinline__ void moments_body(const P *__restrict__ f,
     T fi[L::Q];
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, eps, ph, g, nb);
+        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
     });
-    const Rec<T> q = cell_moments<D>(fi, eps, muD, muF, nb, ph);
+    const Rec<T> q = cell_moments<D>(fi, ev, muD, muF, nb, ph);
     store_rec<D>(m1_out, n, q.r, q.w);
 }
 
@@ -886,17 +974,17 @@ __device__ __forceinline__ void vcorrect_body(const P4<T> *__restrict__ own_src,
                                                   const uint8_t *__restrict__ mask,
                                                   P4<T> *__restrict__ m2_out, Grid g, Tiling tl,
                                                   Phys<T> ph, uint32_t wg) {
-    LBM_CELL_PROLOGUE_W(D, wg)
+    LBM_TILE_PROLOGUE(D, wg, (false))
     if constexpr (SOLIDS) {
         if (mask[n]) {
             *at(m2_out, n) = pack(T(0), T(0), T(0), T(0));
             return;
         }
     }
-    const Rec<T> own = load_rec<D>(own_src, eps, n);
-    const CellStatic<D, T> cs = cell_static<D>(eps, nb, ph, own.e);
+    const Rec<T> own = load_rec<D>(own_src, n, ev.at(0, 0, 0));
+    const CellStatic<D, T> cs = cell_static<D>(ev, ph, own.e);
     T v[3];
-    corrected_velocity<D, T, SOLIDS>(m1, eps, mask, g, nb, own, cs, v);
+    corrected_velocity<D, T, SOLIDS>(m1, ev, eps, mask, g, nb, own, cs, v);
     store_rec<D>(m2_out, n, own.r, v);
 }
 
@@ -909,25 +997,25 @@ __device__ __forceinline__ void collide_body(P *__restrict__ f,
                                                  const T *__restrict__ muF,
                                                  const uint8_t *__restrict__ mask, Grid g,
                                                  Tiling tl, Phys<T> ph, uint32_t wg) {
-    LBM_CELL_PROLOGUE_W(D, wg)
+    LBM_TILE_PROLOGUE(D, wg, (false))
     using L = Lat<D>;
     if constexpr (SOLIDS) {
         if (mask[n]) return;
     }
-    const Rec<T> own = load_rec<D>(m2, eps, n);
-    const CellStatic<D, T> cs = cell_static<D>(eps, nb, ph, own.e);
+    const Rec<T> own = load_rec<D>(m2, n, ev.at(0, 0, 0));
+    const CellStatic<D, T> cs = cell_static<D>(ev, ph, own.e);
     ProductForm<D, T> peq, pst;
-    cell_equilibria<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
+    cell_equilibria<D, T, SOLIDS>(m2, ev, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
     // The populations are loaded only now, after the forcing arguments: fewer registers are
     // live across the stencil work, so more waves share each SIMD.
     __builtin_amdgcn_sched_barrier(0);
     T fi[L::Q];
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, eps, ph, g, nb);
+        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
     });
     collide_stream<D, T, P, SOLIDS, PH>(f, mask, g, nb, fi, cs.vs.beta,
-                                        own_base<P>(eps, ph, n), peq, pst);
+                                        own_base<P>(ev.at(0, 0, 0), ph), peq, pst);
 }
 
 // One pass of the lagged scheme: the cell's own moments, velocity correction and forcing are
@@ -944,7 +1032,7 @@ __device__ __forceinline__ void fused_body(P *__restrict__ f, const P4<T> *__res
                                                const T *__restrict__ muF,
                                                const uint8_t *__restrict__ mask, Grid g,
                                                Tiling tl, Phys<T> ph, uint32_t wg) {
-    LBM_CELL_PROLOGUE_W(D, wg)
+    LBM_TILE_PROLOGUE(D, wg, (PopFmt<P>::shifted))
     using L = Lat<D>;
     if constexpr (SOLIDS) {
         if (mask[n]) {
@@ -956,16 +1044,16 @@ __device__ __forceinline__ void fused_body(P *__restrict__ f, const P4<T> *__res
     T fi[L::Q];
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, eps, ph, g, nb);
+        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
     });
-    const Rec<T> own1 = cell_moments<D>(fi, eps, muD, muF, nb, ph);
-    const CellStatic<D, T> cs = cell_static<D>(eps, nb, ph, own1.e);
+    const Rec<T> own1 = cell_moments<D>(fi, ev, muD, muF, nb, ph);
+    const CellStatic<D, T> cs = cell_static<D>(ev, ph, own1.e);
     Rec<T> own2 = own1;
-    corrected_velocity<D, T, SOLIDS>(m1p, eps, mask, g, nb, own1, cs, own2.w);
+    corrected_velocity<D, T, SOLIDS>(m1p, ev, eps, mask, g, nb, own1, cs, own2.w);
     ProductForm<D, T> peq, pst;
-    cell_equilibria<D, T, SOLIDS>(m2p, eps, muD, muF, mask, g, ph, nb, own2, cs, peq, pst);
+    cell_equilibria<D, T, SOLIDS>(m2p, ev, eps, muD, muF, mask, g, ph, nb, own2, cs, peq, pst);
     collide_stream<D, T, P, SOLIDS, PH>(f, mask, g, nb, fi, cs.vs.beta,
-                                        own_base<P>(eps, ph, n), peq, pst);
+                                        own_base<P>(ev.at(0, 0, 0), ph), peq, pst);
     store_rec<D>(m1n, n, own1.r, own1.w);
     store_rec<D>(m2n, n, own2.r, own2.w);
 }
@@ -1037,14 +1125,14 @@ __global__ __launch_bounds__(256) void k_init(P *__restrict__ f,
             return;
         }
     }
-    const Rec<T> own = load_rec<D>(m2, eps, n);
-    const CellStatic<D, T> cs = cell_static<D>(eps, nb, ph, own.e);
+    const Rec<T> own = load_rec<D>(m2, n, ev.at(0, 0, 0));
+    const CellStatic<D, T> cs = cell_static<D>(ev, ph, own.e);
     ProductForm<D, T> peq, pst;
-    cell_equilibria<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
+    cell_equilibria<D, T, SOLIDS>(m2, ev, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
         const T v = T(1.5) * peq.template at<i>() - T(0.5) * pst.template at<i>();
-        *at(plane(f, i, g.N), n) = encode<D, i, P>(v, load_sigma<D, SOLIDS, i, P>(mask, eps, ph, nb));
+        *at(plane(f, i, g.N), n) = encode<D, i, P>(v, load_sigma<D, SOLIDS, i, P>(mask, ev, ph, nb));
     });
 }
 
@@ -1100,7 +1188,7 @@ __global__ __launch_bounds__(256) void k_export(const P *__restrict__ f,
         } else {
             const P raw = load_raw<D, SOLIDS, PH, i>(f, mask, g, nb);
             out[(int64_t)i * g.N + n] =
-                decode<D, i, O>(raw, load_sigma<D, SOLIDS, i, P>(mask, eps, ph, nb));
+                decode<D, i, O>(raw, load_sigma<D, SOLIDS, i, P>(mask, ev, ph, nb));
         }
     });
 }
@@ -1115,7 +1203,7 @@ __global__ __launch_bounds__(256) void k_import(P *__restrict__ f, const I *__re
     using L = Lat<D>;
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        const float sig = load_sigma<D, SOLIDS, i, P>(mask, eps, ph, nb);
+        const float sig = load_sigma<D, SOLIDS, i, P>(mask, ev, ph, nb);
         if constexpr (PopFmt<P>::shifted) {
             *at(plane(f, i, g.N), n) = encode<D, i, P>(in[(int64_t)i * g.N + n], sig);
         } else {
@@ -1180,10 +1268,11 @@ __global__ __launch_bounds__(256) void k_stats(const P *__restrict__ f,
         const int z = (int)(n / ((uint32_t)g.nx * (uint32_t)g.ny));
         Nbr<D> nb;
         nb.init(g, x, y, z);
+        const EpsGlobal<D, T> ev{eps, &nb};
         T cell = T(0);
         unroll<0, L::Q>([&](auto ii) {
             constexpr int i = decltype(ii)::value;
-            cell = cell + load_pop<D, SOLIDS, PH, i>(f, mask, eps, ph, g, nb);
+            cell = cell + load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
         });
         const double cm = (double)cell;
         acc[0] += cm;
