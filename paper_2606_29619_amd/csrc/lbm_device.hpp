@@ -154,22 +154,37 @@ struct Nbr {
     uint32_t xs[3];
     uint32_t row[3][3];
     int x, y, z;
+    // The row bases use one multiply per axis: the +-1 neighbours differ from the centre by the
+    // row (plane) stride, or by the wrapped distance on the periodic seam.
     __device__ __forceinline__ void init(const Grid &g, int x_, int y_, int z_) {
         x = x_;
         y = y_;
         z = z_;
+        const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
+        xs[0] = (uint32_t)(x == 0 ? g.nx - 1 : x - 1);
+        xs[1] = (uint32_t)x;
+        xs[2] = (uint32_t)(x + 1 == g.nx ? 0 : x + 1);
+        const uint32_t sy = nx * (ny - 1u);
+        const uint32_t r1 = nx * (uint32_t)y;
+        const uint32_t ry[3] = {y == 0 ? r1 + sy : r1 - nx, r1, y + 1 == g.ny ? r1 - sy : r1 + nx};
+        uint32_t rz[3] = {0u, 0u, 0u};
+        if constexpr (D == 3) {
+            const uint32_t pl = nx * ny;
+            const uint32_t sz = pl * ((uint32_t)g.nz - 1u);
+            const uint32_t z1 = pl * (uint32_t)z;
+            rz[0] = z == 0 ? z1 + sz : z1 - pl;
+            rz[1] = z1;
+            rz[2] = z + 1 == g.nz ? z1 - sz : z1 + pl;
+        } else {
+            rz[1] = nx * ny * (uint32_t)z;
+        }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) xs[k] = (uint32_t)wrap1(x, k - 1, g.nx);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const uint32_t yy = (uint32_t)wrap1(y, j - 1, g.ny);
+        for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 if (D == 2 && k != 1) continue;
-                const uint32_t zz = D == 3 ? (uint32_t)wrap1(z, k - 1, g.nz) : (uint32_t)z;
-                row[j][k] = (uint32_t)g.nx * (yy + (uint32_t)g.ny * zz);
+                row[j][k] = ry[j] + rz[k];
             }
-        }
     }
     __device__ __forceinline__ uint32_t at(int cx, int cy, int cz) const {
         return xs[cx + 1] + row[cy + 1][cz + 1];
@@ -801,6 +816,7 @@ __device__ __forceinline__ void cell_equilibria(const P4<T> *__restrict__ m2, co
 // ------------------------------------------------------------------------------------------
 struct Tiling {
     int tx, ty;       // tile shape, tx * ty = 256
+    int ltx;          // log2(tx)
     int ntx, nty, ntz;
     int by, bz;       // block of tile rows
     int nby, nbz;     // blocks along y and z
@@ -825,8 +841,8 @@ __device__ __forceinline__ int tile_cell(const Grid &g, const Tiling &tl, uint32
     y0 = (int)(ty * (uint32_t)tl.ty);
     z = (int)tz;
     if (y0 >= g.ny || z >= g.nz) return -1;  // padding of a partial block
-    x = x0 + (int)(threadIdx.x % (uint32_t)tl.tx);
-    y = y0 + (int)(threadIdx.x / (uint32_t)tl.tx);
+    x = x0 + (int)(threadIdx.x & (uint32_t)(tl.tx - 1));
+    y = y0 + (int)(threadIdx.x >> (uint32_t)tl.ltx);
     return x < g.nx && y < g.ny ? 1 : 0;
 }
 

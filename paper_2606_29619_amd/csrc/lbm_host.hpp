@@ -126,6 +126,7 @@ inline dim3 flat_grid(int64_t total) { return dim3((unsigned)((total + 255) / 25
 inline lbm::Tiling make_tiling(int nx, int ny, int nz) {
     lbm::Tiling t;
     t.tx = nx >= 192 ? 256 : (nx >= 96 ? 128 : 64);
+    t.ltx = t.tx == 256 ? 8 : (t.tx == 128 ? 7 : 6);
     t.ty = 256 / t.tx;
     t.ntx = (nx + t.tx - 1) / t.tx;
     t.nty = (ny + t.ty - 1) / t.ty;
