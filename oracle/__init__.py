@@ -46,6 +46,9 @@ class _Params(ctypes.Structure):
         ("eps", ctypes.POINTER(ctypes.c_double)), ("kappa", ctypes.POINTER(ctypes.c_double)),
         ("cf", ctypes.POINTER(ctypes.c_double)), ("mask", ctypes.POINTER(ctypes.c_uint8)),
         ("rho_init", ctypes.POINTER(ctypes.c_double)), ("v_init", ctypes.POINTER(ctypes.c_double)),
+        ("bc_type", ctypes.POINTER(ctypes.c_uint8)), ("bc_normal", ctypes.POINTER(ctypes.c_uint8)),
+        ("bc_vel", ctypes.POINTER(ctypes.c_double)), ("bc_rho", ctypes.POINTER(ctypes.c_double)),
+        ("bc_scheme", ctypes.c_int), ("bc_density", ctypes.c_int),
     ]
 
 
@@ -140,6 +143,14 @@ class OracleConfig:
     lagged: int = 0
     rho_init: Optional[np.ndarray] = None
     v_init: Optional[np.ndarray] = None   # [D, nz, ny, nx]
+    # wet-node boundaries (Sec. 3.4): node type 0 bulk, 1 velocity, 2 pressure, 3 outflow;
+    # outward normal 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z
+    bc_type: Optional[np.ndarray] = None
+    bc_normal: Optional[np.ndarray] = None
+    bc_vel: Optional[np.ndarray] = None    # [D, nz, ny, nx]
+    bc_rho: Optional[np.ndarray] = None
+    bc_scheme: int = 1                     # 0 equilibrium, 1 NEEM, 2 TMS
+    bc_density: int = 0                    # 0 mass continuity, 1 bounce-back
 
 
 class Oracle:
@@ -184,6 +195,18 @@ class Oracle:
             self.mask = np.zeros(self.shape, dtype=bool)
         p.rho_init = _dp(arr(cfg.rho_init))
         p.v_init = _dp(arr(cfg.v_init, (cfg.D,) + self.shape))
+
+        def u8(a):
+            if a is None:
+                return ctypes.POINTER(ctypes.c_uint8)()
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.uint8).reshape(self.shape))
+            self._keep.append(a)
+            return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+        p.bc_type, p.bc_normal = u8(cfg.bc_type), u8(cfg.bc_normal)
+        p.bc_vel = _dp(arr(cfg.bc_vel, (cfg.D,) + self.shape))
+        p.bc_rho = _dp(arr(cfg.bc_rho))
+        p.bc_scheme, p.bc_density = cfg.bc_scheme, cfg.bc_density
         err = ctypes.create_string_buffer(256)
         h = lib().orc_create(ctypes.byref(p), err, 256)
         if not h:

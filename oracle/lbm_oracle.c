@@ -48,6 +48,16 @@ typedef struct {
     const uint8_t *mask;/* [N] 1 = solid, NULL = no solids */
     const double *rho_init; /* [N] or NULL */
     const double *v_init;   /* [D][N] superficial velocity or NULL (zero) */
+    /* Wet-node boundaries (Sec. 3.4); bc_type NULL = none.  A boundary node is a fluid cell
+     * whose outward neighbour (along its normal) is solid and whose inward neighbour is a bulk
+     * fluid cell. */
+    const uint8_t *bc_type;   /* [N] 0 bulk, 1 velocity node, 2 pressure node, 3 outflow node */
+    const uint8_t *bc_normal; /* [N] outward normal: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z */
+    const double *bc_vel;     /* [D][N] prescribed superficial velocity (velocity nodes), or NULL */
+    const double *bc_rho;     /* [N] prescribed intrinsic density (pressure nodes), or NULL */
+    int bc_scheme;            /* 0 equilibrium (eq_bc_f_bar), 1 NEEM (NEEM_bc_f_bar), 2 TMS */
+    int bc_density;           /* velocity nodes: 0 mass continuity (bc_density_impermWall),
+                                 1 bounce-back (bc_density_BounceBack) */
 } orc_params;
 
 typedef struct {
@@ -69,6 +79,8 @@ typedef struct {
     int have_prev;
     double *vsnap;          /* residual snapshot [D][N] */
     long *nbr;              /* [3][2][N] index of the periodic neighbour n -/+ e_a */
+    long *bnodes;           /* boundary node indices, nb of them */
+    long nb;
     long t;
 } orc_solver;
 
@@ -315,6 +327,7 @@ void orc_destroy(orc_solver *S)
     free(S->F); free(S->G); free(S->eps); free(S->muD); free(S->muF); free(S->nu);
     free(S->dnu); free(S->beta); free(S->ge); free(S->H); free(S->solid); free(S->rho);
     free(S->v1); free(S->v); free(S->m); free(S->g); free(S->prho); free(S->pv1); free(S->pv);
+    free(S->bnodes);
     free(S->vw);
     free(S->vsnap);
     free(S->nbr);
@@ -406,6 +419,15 @@ orc_solver *orc_create(const orc_params *p, char *err, int errlen)
         S->beta[n] = 1.0 / (1.0 + (2.0 * nu) / p->RT);
     }
     build_neighbours(S);
+    if (p->bc_type) {
+        long k = 0;
+        for (n = 0; n < N; ++n) k += p->bc_type[n] ? 1 : 0;
+        S->bnodes = (long *)xcalloc(k > 0 ? k : 1, sizeof(long));
+        S->nb = k;
+        k = 0;
+        for (n = 0; n < N; ++n)
+            if (p->bc_type[n]) S->bnodes[k++] = n;
+    }
     porosity_derivatives(S);
     init_populations(S);
     return S;
@@ -484,6 +506,130 @@ static void correct_velocity(orc_solver *S)
         }
         for (a = 0; a < D; ++a) S->v[a * N + n] = S->v1[a * N + n] + dn[a] / (2.0 * S->rho[n]);
     }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Wet-node boundaries (Sec. 3.4).  For a boundary node with outward unit normal n, the        */
+/* post-advection populations split into P- (c_i . n < 0: incoming from outside, unknown),     */
+/* P0 (c_i . n = 0) and P+ (c_i . n > 0), eq. (bc_rho_components_def).                         */
+/* ------------------------------------------------------------------------------------------ */
+static void bc_normal_vec(const orc_solver *S, long b, int *nv)
+{
+    int code = S->p.bc_normal[b];
+    nv[0] = nv[1] = nv[2] = 0;
+    nv[code / 2] = (code % 2) ? 1 : -1;
+}
+
+static int c_dot(const orc_solver *S, int i, const int *nv)
+{
+    return S->c[i][0] * nv[0] + S->c[i][1] * nv[1] + S->c[i][2] * nv[2];
+}
+
+/* The bulk node next to boundary node b along its inward normal. */
+static long bc_inner(const orc_solver *S, long b, const int *nv)
+{
+    int m[3] = {-nv[0], -nv[1], -nv[2]};
+    return shift3(S, b, m);
+}
+
+/* Zero-gradient outflow, eq. (f_bar_outflow_BC): the unknown incoming populations copy those
+ * of the inner node. */
+static void apply_outflow(orc_solver *S)
+{
+    long k, N = S->N;
+    int i, nv[3];
+    for (k = 0; k < S->nb; ++k) {
+        long b = S->bnodes[k], f;
+        if (S->p.bc_type[b] != 3) continue;
+        bc_normal_vec(S, b, nv);
+        f = bc_inner(S, b, nv);
+        for (i = 0; i < S->Q; ++i)
+            if (c_dot(S, i, nv) < 0) S->F[(long)i * N + b] = S->F[(long)i * N + f];
+    }
+}
+
+/* Density and velocity of the velocity and pressure nodes, written over the bulk moments.
+ * Velocity node: v_b prescribed; rho_b from mass continuity, eq. (bc_density_impermWall),
+ *   rho_b = (S0 + 2 S+) / (eps_b + v_b,perp - a_b,perp / 2), S0 and S+ the sums of the known
+ *   populations in P0 and P+, with a_b,perp = eps_b b_perp - mu_D v_perp - mu_F |v_b| v_perp
+ *   + RT (d eps / dn) (eq. accel_approx_boundary without its viscous term, which vanishes where
+ *   the porosity is flat at the boundary); or from bounce-back, eq. (bc_density_BounceBack),
+ *   which with halfway bounce-back in the streaming is the sum of all post-advection
+ *   populations over eps_b.
+ * Pressure node: rho_b prescribed, tangential velocity zero, and the same continuity relation
+ *   solved for v_perp: v_perp (1 + mu_D / 2) + (mu_F / 2) |v_perp| v_perp = R with
+ *   R = (S0 + 2 S+) / rho_b - eps_b + (eps_b b_perp + RT d eps / dn) / 2, in closed form as in
+ *   eq. (v_(1)). */
+static void boundary_records(orc_solver *S)
+{
+    int D = S->D, a, i, nv[3];
+    long k, N = S->N;
+    for (k = 0; k < S->nb; ++k) {
+        long b = S->bnodes[k];
+        int type = S->p.bc_type[b];
+        double e = S->eps[b], s0 = 0.0, sp = 0.0, gperp = 0.0, bperp = 0.0, vb[3] = {0.0, 0.0, 0.0};
+        if (type != 1 && type != 2) continue;
+        bc_normal_vec(S, b, nv);
+        for (i = 0; i < S->Q; ++i) {
+            int cn = c_dot(S, i, nv);
+            double f = S->F[(long)i * N + b];
+            if (cn == 0) s0 = s0 + f;
+            else if (cn > 0) sp = sp + f;
+        }
+        for (a = 0; a < D; ++a) {
+            gperp = gperp + (double)nv[a] * S->ge[a * N + b];
+            bperp = bperp + (double)nv[a] * S->p.b[a];
+        }
+        if (type == 1) {
+            double vperp = 0.0, vm = 0.0, aperp, rho;
+            for (a = 0; a < D; ++a) vb[a] = S->p.bc_vel ? S->p.bc_vel[a * N + b] : 0.0;
+            for (a = 0; a < D; ++a) vperp = vperp + (double)nv[a] * vb[a];
+            for (a = 0; a < D; ++a) vm = vm + vb[a] * vb[a];
+            vm = sqrt(vm);
+            if (S->p.bc_density == 1) {
+                double sum = 0.0;
+                for (i = 0; i < S->Q; ++i) sum = sum + S->F[(long)i * N + b];
+                rho = sum / e;
+            } else {
+                aperp = ((e * bperp - S->muD[b] * vperp) - (S->muF[b] * vm) * vperp) +
+                        S->p.RT * gperp;
+                rho = (s0 + 2.0 * sp) / ((e + vperp) - 0.5 * aperp);
+            }
+            S->rho[b] = rho;
+        } else {
+            double rho = S->p.bc_rho[b];
+            double R = ((s0 + 2.0 * sp) / rho - e) + 0.5 * (e * bperp + S->p.RT * gperp);
+            double c1 = 1.0 + 0.5 * S->muD[b], c2 = 0.5 * S->muF[b];
+            double vperp = (2.0 * R) / (c1 + sqrt(c1 * c1 + (4.0 * c2) * fabs(R)));
+            for (a = 0; a < D; ++a) vb[a] = (double)nv[a] * vperp;
+            S->rho[b] = rho;
+        }
+        for (a = 0; a < D; ++a) S->v1[a * N + b] = vb[a];
+    }
+}
+
+/* The corrected velocity of velocity and pressure nodes is their boundary velocity. */
+static void boundary_velocity(orc_solver *S)
+{
+    int D = S->D, a;
+    long k, N = S->N;
+    for (k = 0; k < S->nb; ++k) {
+        long b = S->bnodes[k];
+        if (S->p.bc_type[b] != 1 && S->p.bc_type[b] != 2) continue;
+        for (a = 0; a < D; ++a) S->v[a * N + b] = S->v1[a * N + b];
+    }
+}
+
+/* Equilibrium f^eq(eps, rho, w) of eqs. (1d_scaled_eq)-(P_alpha_alpha_eq) at velocity w. */
+static void equilibrium_at(const orc_solver *S, double e, double rho, const double *w, double *f)
+{
+    double xi[3], P[3];
+    int a;
+    for (a = 0; a < S->D; ++a) {
+        xi[a] = w[a] / e;
+        P[a] = xi[a] * xi[a] + S->p.RT;
+    }
+    product_form(S->D, S->Q, (const int (*)[3])S->c, e, rho, xi, P, f);
 }
 
 /* Forcing quantities at every fluid cell from the moment fields (rho, v):
@@ -622,6 +768,81 @@ static void init_populations(orc_solver *S)
     S->t = 0;
 }
 
+/* Reconstruction of all post-advection populations of the velocity and pressure nodes from
+ * the boundary state (rho_b, v_b) and acceleration a_b, with lambda = dt = 1 and
+ * f^tgt = f^eq(eps_b, rho_b, v_b), f^* = f^eq(eps_b, rho_b, v_b + a_b):
+ *   equilibrium, eq. (eq_bc_f_bar):  f-bar_i = (3/2) f^tgt_i - (1/2) f^*_i;
+ *   NEEM, eqs. (NEEM_bc_f_bar), (zeta_beta_NEEM), with the inner node x_f:
+ *     f-bar_i = zeta f-bar_i(x_f) + (3/2)[f^tgt_i - zeta f^eq_i(x_f)] + (1/2)[zeta f^*_i(x_f) - f^*_i];
+ *   TMS, steps 1-3 of Sec. 3.4.4: local (rho_loc, v_loc) from the known populations, then
+ *     f-bar_i = (f^tgt_i - f^loc_i)/(1 - beta_b) + (3/2) f^tgt_i - (1/2) f^*_i for i in P-,
+ *     f-bar_i = (f^tgt_i - f^loc_i)/(1 - beta_b) + f-bar_i for the others. */
+static void reconstruct_boundaries(orc_solver *S, const double *acc)
+{
+    int D = S->D, Q = S->Q, a, i, nv[3];
+    long k, N = S->N;
+    for (k = 0; k < S->nb; ++k) {
+        long b = S->bnodes[k];
+        double e = S->eps[b], rho = S->rho[b], vb[3], vs[3];
+        double ftgt[ORC_MAXQ], fst[ORC_MAXQ];
+        if (S->p.bc_type[b] != 1 && S->p.bc_type[b] != 2) continue;
+        bc_normal_vec(S, b, nv);
+        for (a = 0; a < D; ++a) {
+            vb[a] = S->v[a * N + b];
+            vs[a] = vb[a] + acc[a * N + b];
+        }
+        equilibrium_at(S, e, rho, vb, ftgt);
+        equilibrium_at(S, e, rho, vs, fst);
+        if (S->p.bc_scheme == 0) {
+            for (i = 0; i < Q; ++i) S->F[(long)i * N + b] = 1.5 * ftgt[i] - 0.5 * fst[i];
+        } else if (S->p.bc_scheme == 1) {
+            long f = bc_inner(S, b, nv);
+            double ef = S->eps[f], rf = S->rho[f], vf[3], vfs[3];
+            double feqf[ORC_MAXQ], fstf[ORC_MAXQ];
+            double zeta = (1.0 - S->beta[f]) / (1.0 - S->beta[b]);
+            for (a = 0; a < D; ++a) {
+                vf[a] = S->v[a * N + f];
+                vfs[a] = vf[a] + acc[a * N + f];
+            }
+            equilibrium_at(S, ef, rf, vf, feqf);
+            equilibrium_at(S, ef, rf, vfs, fstf);
+            for (i = 0; i < Q; ++i)
+                S->F[(long)i * N + b] = (zeta * S->F[(long)i * N + f] +
+                                         1.5 * (ftgt[i] - zeta * feqf[i])) +
+                                        0.5 * (zeta * fstf[i] - fst[i]);
+        } else {
+            double omb = 1.0 - S->beta[b], s0 = 0.0, s1[3] = {0.0, 0.0, 0.0}, rloc, vloc[3];
+            double floc[ORC_MAXQ];
+            for (i = 0; i < Q; ++i) {
+                double d;
+                if (c_dot(S, i, nv) < 0) continue;
+                d = (S->F[(long)i * N + b] - 1.5 * ftgt[i]) + 0.5 * fst[i];
+                s0 = s0 + d;
+                for (a = 0; a < D; ++a) s1[a] = s1[a] + (double)S->c[i][a] * d;
+            }
+            rloc = (e * rho + omb * s0) / e;
+            for (a = 0; a < D; ++a) vloc[a] = (rho * vb[a] + omb * s1[a]) / rloc;
+            equilibrium_at(S, e, rloc, vloc, floc);
+            for (i = 0; i < Q; ++i) {
+                double neq = (ftgt[i] - floc[i]) / omb;
+                if (c_dot(S, i, nv) < 0) S->F[(long)i * N + b] = neq + (1.5 * ftgt[i] - 0.5 * fst[i]);
+                else S->F[(long)i * N + b] = neq + S->F[(long)i * N + b];
+            }
+        }
+    }
+}
+
+/* Moments of the current state: outflow copies, bulk moments and drag solve, boundary
+ * records, velocity correction. */
+static void compute_moments(orc_solver *S)
+{
+    apply_outflow(S);
+    moments_v1(S);
+    boundary_records(S);
+    correct_velocity(S);
+    boundary_velocity(S);
+}
+
 /* Post-collision populations (dicrete_scheme, momentum_rate) with lambda = dt = 1:
  * f-bar^pc_i = f-bar_i + 2 beta (f^eq_i - f-bar_i) + (1 - beta)(f^*_i - f^eq_i). */
 static void collide_cell(const orc_solver *S, long n, const forcing_out *o, double *fpc)
@@ -650,11 +871,12 @@ static void step_once(orc_solver *S)
     long n, N = S->N;
     forcing_out o;
     double *tmp;
-    moments_v1(S);
-    correct_velocity(S);
+    compute_moments(S);
     alloc_forcing(D * N, &o);
+    if (S->nb) o.acc = (double *)xcalloc(D * N, sizeof(double));
     if (S->p.lagged && S->have_prev) forcing(S, S->rho, S->v, S->prho, S->pv, &o);
     else forcing(S, S->rho, S->v, S->rho, S->v, &o);
+    if (S->nb) reconstruct_boundaries(S, o.acc);
     for (n = 0; n < N; ++n) {
         double fpc[ORC_MAXQ];
         if (S->solid[n]) continue;
@@ -690,8 +912,7 @@ void orc_moments(orc_solver *S, double *rho_out, double *v_out, double *v1_out)
 {
     long N = S->N;
     int D = S->D;
-    moments_v1(S);
-    correct_velocity(S);
+    compute_moments(S);
     if (rho_out) memcpy(rho_out, S->rho, sizeof(double) * (size_t)N);
     if (v_out) memcpy(v_out, S->v, sizeof(double) * (size_t)(D * N));
     if (v1_out) memcpy(v1_out, S->v1, sizeof(double) * (size_t)(D * N));
@@ -718,8 +939,7 @@ void orc_forcing_fields(orc_solver *S, double *acc, double *phx, double *pheta, 
     int D = S->D;
     long N = S->N;
     forcing_out o;
-    moments_v1(S);
-    correct_velocity(S);
+    compute_moments(S);
     alloc_forcing(D * N, &o);
     o.acc = acc; o.phx = phx; o.pheta = pheta;
     forcing(S, S->rho, S->v, S->rho, S->v, &o);
@@ -758,8 +978,7 @@ void orc_post_collision(orc_solver *S, long ncells, const long *cells, double *f
     int D = S->D, Q = S->Q;
     long k, N = S->N;
     forcing_out o;
-    moments_v1(S);
-    correct_velocity(S);
+    compute_moments(S);
     alloc_forcing(D * N, &o);
     forcing(S, S->rho, S->v, S->rho, S->v, &o);
     for (k = 0; k < ncells; ++k) {
@@ -784,8 +1003,7 @@ void orc_stats(orc_solver *S, double *out)
     int D = S->D, Q = S->Q, i, a;
     long n, N = S->N;
     double mass = 0.0, mom[3] = {0.0, 0.0, 0.0}, vmax = 0.0, d2 = 0.0, s2 = 0.0, bad = 0.0;
-    moments_v1(S);
-    correct_velocity(S);
+    compute_moments(S);
     for (n = 0; n < N; ++n) {
         double cell = 0.0, vv = 0.0;
         if (S->solid[n]) continue;

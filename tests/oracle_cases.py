@@ -109,3 +109,42 @@ def measure_decay(o, setup, steps, L):
         return -np.polyfit(t[100:], np.log(amps[100:]), 1)[0]
     pk = np.array([i for i in range(1, steps - 1) if amps[i] > amps[i - 1] and amps[i] >= amps[i + 1]])
     return -np.polyfit(t[pk], np.log(amps[pk]), 1)[0]
+
+
+def wall_channel(D, H, eps, kappa, nu, b, v_bot, v_top, scheme=1, density=0, nx=4, nz=1,
+                 rho_init=None, cf=0.0):
+    """Channel periodic in x (and z) between two wet-node walls (Sec. 3.4) at y = 0 and y = H
+    (grid rows 1 and H + 1; rows 0 and H + 2 are solid), walls moving along x with v_bot and
+    v_top.  Node j of the channel lies at y = j."""
+    ny = H + 3
+    shape = (nz if D == 3 else 1, ny, nx)
+    e = np.full(shape, float(eps))
+    k = np.full(shape, float(kappa))
+    c = np.full(shape, float(cf))
+    mask = np.zeros(shape, np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, -1, :] = 1
+    bct = np.zeros(shape, np.uint8)
+    bcn = np.zeros(shape, np.uint8)
+    bct[:, 1, :] = 1
+    bct[:, -2, :] = 1
+    bcn[:, 1, :] = 2       # outward normal -y
+    bcn[:, -2, :] = 3      # outward normal +y
+    vel = np.zeros((D,) + shape)
+    vel[0, :, 1, :] = v_bot
+    vel[0, :, -2, :] = v_top
+    rinit = None
+    if rho_init is not None:
+        rinit = np.ones(shape)
+        rinit[:, 1:-1, :] = np.asarray(rho_init).reshape(1, H + 1, 1)
+    cfg = oracle.OracleConfig(D=D, eps=e, kappa=k, cf=c, mask=mask, nu_f=nu, nu_eff_ref=nu,
+                              b=tuple(b) + (0.0,) * (3 - len(b)), rho_init=rinit,
+                              bc_type=bct, bc_normal=bcn, bc_vel=vel, bc_scheme=scheme,
+                              bc_density=density)
+    return oracle.Oracle(cfg)
+
+
+def wall_profile(o):
+    """(rho, v_x) along the channel nodes y = 0..H."""
+    rho, v, _ = o.moments()
+    return rho[0, 1:-1, 0], v[0, 0, 1:-1, 0]
