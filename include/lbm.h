@@ -88,6 +88,37 @@ extern "C" {
 #define LBM_SCHEME_TWO_PASS 0
 #define LBM_SCHEME_LAGGED 1
 
+/*
+ * Wet-node boundaries (Sec. 3.4), two-pass scheme.  A boundary node is a fluid cell with an
+ * outward normal along one axis; its outward neighbour must be solid (mask = 1) and its inward
+ * neighbour a bulk fluid cell.  Node types (lbm_params.bc_type):
+ *   LBM_NODE_VELOCITY: superficial velocity v_b prescribed; density from mass continuity,
+ *     eq. (bc_density_impermWall) with a_b,perp = eps_b b_perp - mu_D v_perp - mu_F |v_b| v_perp
+ *     + RT d(eps)/dn (eq. accel_approx_boundary without its viscous term), or from bounce-back,
+ *     eq. (bc_density_BounceBack); all populations rebuilt by lbm_params.bc_scheme;
+ *   LBM_NODE_PRESSURE: intrinsic density rho_b prescribed, tangential velocity zero, normal
+ *     velocity from the same continuity relation; populations rebuilt by bc_scheme;
+ *   LBM_NODE_OUTFLOW: zero-gradient outflow, eq. (f_bar_outflow_BC).
+ * Schemes: LBM_BC_EQUILIBRIUM (eq_bc_f_bar), LBM_BC_NEEM (NEEM_bc_f_bar, zeta_beta_NEEM),
+ * LBM_BC_TMS (Sec. 3.4.4, f_i_neq_TMS).  Links of bulk cells into solid cells keep halfway
+ * bounce-back.
+ */
+#define LBM_NODE_BULK 0
+#define LBM_NODE_VELOCITY 1
+#define LBM_NODE_PRESSURE 2
+#define LBM_NODE_OUTFLOW 3
+#define LBM_NORMAL_XM 0   /* outward normal -x */
+#define LBM_NORMAL_XP 1
+#define LBM_NORMAL_YM 2
+#define LBM_NORMAL_YP 3
+#define LBM_NORMAL_ZM 4
+#define LBM_NORMAL_ZP 5
+#define LBM_BC_EQUILIBRIUM 0
+#define LBM_BC_NEEM 1
+#define LBM_BC_TMS 2
+#define LBM_BC_RHO_CONTINUITY 0
+#define LBM_BC_RHO_BOUNCE_BACK 1
+
 /* Output element type for lbm_moments / lbm_get_populations / lbm_set_populations. */
 #define LBM_DTYPE_F64 0
 #define LBM_DTYPE_F32 1
@@ -125,6 +156,12 @@ typedef struct lbm_params {
     const uint8_t *mask;  /* [N] 1 = solid cell, 0 = fluid; NULL = no solid cells */
     const double *rho_init; /* [N] initial intrinsic density > 0, or NULL (uniform rho0) */
     const double *v_init;   /* [D][N] initial superficial velocity, or NULL (zero) */
+    const uint8_t *bc_type;     /* [N] LBM_NODE_*, or NULL (no wet-node boundaries) */
+    const uint8_t *bc_normal;   /* [N] LBM_NORMAL_* of each boundary node */
+    const double *bc_velocity;  /* [D][N] v_b of velocity nodes, or NULL (zero) */
+    const double *bc_density;   /* [N] rho_b of pressure nodes, or NULL (rho0) */
+    int bc_scheme;              /* LBM_BC_EQUILIBRIUM, LBM_BC_NEEM or LBM_BC_TMS */
+    int bc_rho_rule;            /* LBM_BC_RHO_CONTINUITY or LBM_BC_RHO_BOUNCE_BACK */
 } lbm_params;
 
 /* Global statistics of the current state, accumulated in FP64 on the device. */
@@ -145,8 +182,8 @@ typedef struct lbm_solver lbm_solver;
 
 /*
  * Bytes of device workspace lbm_create needs for these parameters (pure host computation, no
- * device work).  Only lattice, storage, scheme, shift, nx, ny, nz and whether mask is non-NULL
- * are read.
+ * device work).  Only lattice, storage, scheme, shift, nx, ny, nz, whether mask is non-NULL and
+ * the number of boundary nodes in bc_type are read.
  * Errors: LBM_ERR_INVALID_ARG for NULL pointers or bad lattice, storage or dimensions.
  */
 LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes);
@@ -202,7 +239,8 @@ LBM_API int lbm_residual(lbm_solver *h, lbm_stats *out);
 /*
  * Copy the populations f-bar_i(x) of the current state in natural layout [Q][N] (the value
  * that streamed into cell x along c_i) into a caller device buffer of dtype.  Solid cells get
- * 0.  With lbm_set_populations this is the checkpoint of the state.  Asynchronous.
+ * 0; the incoming populations of outflow nodes are their zero-gradient copies.  With
+ * lbm_set_populations this is the checkpoint of the state.  Asynchronous.
  */
 LBM_API int lbm_get_populations(lbm_solver *h, void *dev_out, int dtype);
 

@@ -918,8 +918,11 @@ void orc_moments(orc_solver *S, double *rho_out, double *v_out, double *v1_out)
     if (v1_out) memcpy(v1_out, S->v1, sizeof(double) * (size_t)(D * N));
 }
 
-void orc_get_state(const orc_solver *S, double *f_out)
+/* The current populations; the unknown incoming populations of outflow nodes are the ones the
+ * next step uses (the outflow copy is applied first). */
+void orc_get_state(orc_solver *S, double *f_out)
 {
+    apply_outflow(S);
     memcpy(f_out, S->F, sizeof(double) * (size_t)(S->Q * S->N));
 }
 

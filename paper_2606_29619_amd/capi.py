@@ -33,6 +33,10 @@ LBM_F16_SHIFTED = 2
 LBM_BF16_SHIFTED = 3
 LBM_SHIFT_WEIGHTS = 0
 LBM_SHIFT_POROUS = 1
+LBM_NODE_BULK, LBM_NODE_VELOCITY, LBM_NODE_PRESSURE, LBM_NODE_OUTFLOW = 0, 1, 2, 3
+LBM_NORMAL_XM, LBM_NORMAL_XP, LBM_NORMAL_YM, LBM_NORMAL_YP, LBM_NORMAL_ZM, LBM_NORMAL_ZP = range(6)
+LBM_BC_EQUILIBRIUM, LBM_BC_NEEM, LBM_BC_TMS = 0, 1, 2
+LBM_BC_RHO_CONTINUITY, LBM_BC_RHO_BOUNCE_BACK = 0, 1
 LBM_SCHEME_TWO_PASS = 0
 LBM_SCHEME_LAGGED = 1
 LBM_DTYPE_F64 = 0
@@ -53,6 +57,9 @@ class lbm_params(ctypes.Structure):
         ("eps", _dp), ("kappa", _dp), ("forch", _dp),
         ("mask", ctypes.POINTER(ctypes.c_uint8)),
         ("rho_init", _dp), ("v_init", _dp),
+        ("bc_type", ctypes.POINTER(ctypes.c_uint8)), ("bc_normal", ctypes.POINTER(ctypes.c_uint8)),
+        ("bc_velocity", _dp), ("bc_density", _dp),
+        ("bc_scheme", ctypes.c_int), ("bc_rho_rule", ctypes.c_int),
     ]
 
 
@@ -275,7 +282,11 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
                 nu_f: float = 1.0 / 6.0, nu_eff_ref: float = 1.0 / 6.0, nu_eff_pow: int = 0,
                 eta_eff: float = math.nan, b=(0.0, 0.0, 0.0), rho0: float = 1.0,
                 rho_init: Optional[np.ndarray] = None, v_init: Optional[np.ndarray] = None,
-                scheme: int = LBM_SCHEME_TWO_PASS, shift: int = LBM_SHIFT_WEIGHTS):
+                scheme: int = LBM_SCHEME_TWO_PASS, shift: int = LBM_SHIFT_WEIGHTS,
+                bc_type: Optional[np.ndarray] = None, bc_normal: Optional[np.ndarray] = None,
+                bc_velocity: Optional[np.ndarray] = None,
+                bc_density: Optional[np.ndarray] = None, bc_scheme: int = LBM_BC_NEEM,
+                bc_rho_rule: int = LBM_BC_RHO_CONTINUITY):
     """Build an lbm_params from numpy arrays shaped [nz, ny, nx]; returns (params, keepalive)."""
     eps = np.ascontiguousarray(eps, dtype=np.float64)
     if eps.ndim == 2:
@@ -307,6 +318,18 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
     D = 2 if lattice == LBM_D2Q9 else 3
     p.rho_init = arr(rho_init, eps.shape)
     p.v_init = arr(v_init, (D,) + eps.shape)
+
+    def u8(a):
+        if a is None:
+            return ctypes.POINTER(ctypes.c_uint8)()
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.uint8).reshape(eps.shape))
+        keep.append(a)
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+    p.bc_type, p.bc_normal = u8(bc_type), u8(bc_normal)
+    p.bc_velocity = arr(bc_velocity, (D,) + eps.shape)
+    p.bc_density = arr(bc_density, eps.shape)
+    p.bc_scheme, p.bc_rho_rule = bc_scheme, bc_rho_rule
     return p, keep
 
 
@@ -341,7 +364,13 @@ class Solver:
         p, keep = make_params(w.lattice, storage, w.eps, w.kappa, w.forch, w.mask, RT=w.RT,
                               nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow,
                               eta_eff=w.eta_eff, b=w.b, rho0=w.rho0, rho_init=w.rho_init,
-                              v_init=w.v_init, scheme=scheme, shift=shift)
+                              v_init=w.v_init, scheme=scheme, shift=shift,
+                              bc_type=getattr(w, "bc_type", None),
+                              bc_normal=getattr(w, "bc_normal", None),
+                              bc_velocity=getattr(w, "bc_velocity", None),
+                              bc_density=getattr(w, "bc_density", None),
+                              bc_scheme=getattr(w, "bc_scheme", LBM_BC_NEEM),
+                              bc_rho_rule=getattr(w, "bc_rho_rule", LBM_BC_RHO_CONTINUITY))
         return cls(p, keep, **kw)
 
     def close(self):
@@ -425,7 +454,13 @@ class Server:
         p, _keep = make_params(w.lattice, storage, w.eps, w.kappa, w.forch, w.mask, RT=w.RT,
                                nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow,
                                eta_eff=w.eta_eff, b=w.b, rho0=w.rho0, rho_init=w.rho_init,
-                               v_init=w.v_init, scheme=scheme, shift=shift)
+                               v_init=w.v_init, scheme=scheme, shift=shift,
+                              bc_type=getattr(w, "bc_type", None),
+                              bc_normal=getattr(w, "bc_normal", None),
+                              bc_velocity=getattr(w, "bc_velocity", None),
+                              bc_density=getattr(w, "bc_density", None),
+                              bc_scheme=getattr(w, "bc_scheme", LBM_BC_NEEM),
+                              bc_rho_rule=getattr(w, "bc_rho_rule", LBM_BC_RHO_CONTINUITY))
         rid = self.submit_params(p, tol, max_steps)   # the library copies the arrays
         return rid
 

@@ -16,6 +16,7 @@
 #include <vector>
 #include <algorithm>
 
+#include "lbm_bc.hpp"
 #include "lbm_device.hpp"
 #include "lbm_host.hpp"
 
@@ -98,6 +99,63 @@ void launch_stats(const lbm_solver *h, size_t m2) {
                        ws_ptr<T>(h, h->L.vsnap), mask_ptr(h), ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<double>(h, h->L.part), grid_of(h), phys_of<T>(h));
 }
+
+// ---- wet-node boundary kernels (one thread per boundary node; boundaries imply solids) -----
+template <typename T>
+lbm::BNodes<T> bnodes_of(const lbm_solver *h) {
+    return lbm::BNodes<T>{ws_ptr<const uint32_t>(h, h->L.bcell), ws_ptr<const uint32_t>(h, h->L.bcode),
+                          ws_ptr<const lbm::P4<T>>(h, h->L.bval), h->nb};
+}
+
+struct BcOutflowPass {
+    const lbm_solver *h;
+    template <int D, typename T, typename P, bool S, int PH>
+    void operator()() {
+        if constexpr (S)
+            hipLaunchKernelGGL((lbm::k_bc_outflow<D, T, P, S, PH>), flat_grid(h->nb), dim3(256), 0,
+                               h->stream, ws_ptr<P>(h, h->L.f), mask_ptr(h),
+                               ws_ptr<const T>(h, h->L.eps), bnodes_of<T>(h), grid_of(h),
+                               phys_of<T>(h));
+    }
+};
+struct BcRecordsPass {
+    const lbm_solver *h;
+    size_t m1;
+    template <int D, typename T, typename P, bool S, int PH>
+    void operator()() {
+        if constexpr (S)
+            hipLaunchKernelGGL((lbm::k_bc_records<D, T, P, S, PH>), flat_grid(h->nb), dim3(256), 0,
+                               h->stream, ws_ptr<const P>(h, h->L.f), mask_ptr(h),
+                               ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
+                               ws_ptr<const T>(h, h->L.muF), ws_ptr<lbm::P4<T>>(h, m1),
+                               bnodes_of<T>(h), grid_of(h), phys_of<T>(h),
+                               h->bc_rho_rule == LBM_BC_RHO_BOUNCE_BACK ? 1 : 0);
+    }
+};
+struct BcFixPass {
+    const lbm_solver *h;
+    size_t m1, m2;
+    template <int D, typename T, typename P, bool S, int PH>
+    void operator()() {
+        if constexpr (S)
+            hipLaunchKernelGGL((lbm::k_bc_fix<T>), flat_grid(h->nb), dim3(256), 0, h->stream,
+                               ws_ptr<const lbm::P4<T>>(h, m1), ws_ptr<lbm::P4<T>>(h, m2),
+                               bnodes_of<T>(h));
+    }
+};
+struct BcRebuildPass {
+    const lbm_solver *h;
+    size_t m2;
+    template <int D, typename T, typename P, bool S, int PH>
+    void operator()() {
+        if constexpr (S)
+            hipLaunchKernelGGL((lbm::k_bc_rebuild<D, T, P, S, PH>), flat_grid(h->nb), dim3(256), 0,
+                               h->stream, ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
+                               ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
+                               ws_ptr<const T>(h, h->L.muF), mask_ptr(h), bnodes_of<T>(h),
+                               grid_of(h), phys_of<T>(h), h->bc_scheme);
+    }
+};
 
 // Calls fn.template operator()<D, T, P, S, PH>() for the handle's configuration.
 template <typename F>
@@ -192,8 +250,11 @@ size_t current_moments(lbm_solver *h) {
         return h->L.m2[nx];
     }
     const int c = h->cur;
+    if (h->bc_outflow) dispatch(h, BcOutflowPass{h});
     dispatch(h, MomentsPass{h, h->L.m1[c]});
+    if (h->bc_vp) dispatch(h, BcRecordsPass{h, h->L.m1[c]});
     dispatch(h, VcorrectPass{h, h->L.m1[c], h->L.m1[c], h->L.m2[c]});
+    if (h->bc_vp) dispatch(h, BcFixPass{h, h->L.m1[c], h->L.m2[c]});
     return h->L.m2[c];
 }
 
@@ -209,10 +270,16 @@ hipError_t one_step(lbm_solver *h, hipEvent_t *ev) {
         h->cur = nx;
     } else {
         const int c = h->cur;
+        // wet-node boundaries: outflow copies, boundary records and population rebuild around
+        // the bulk passes (they are timed with the pass they follow)
+        if (h->bc_outflow) dispatch(h, BcOutflowPass{h});
         dispatch(h, MomentsPass{h, h->L.m1[c]});
+        if (h->bc_vp) dispatch(h, BcRecordsPass{h, h->L.m1[c]});
         if (ev) e = hipEventRecord(ev[0], h->stream);
         dispatch(h, VcorrectPass{h, h->L.m1[c], h->L.m1[c], h->L.m2[c]});
+        if (h->bc_vp) dispatch(h, BcFixPass{h, h->L.m1[c], h->L.m2[c]});
         if (ev && e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
+        if (h->bc_vp) dispatch(h, BcRebuildPass{h, h->L.m2[c]});
         dispatch(h, CollidePass{h, h->L.m2[c]});
         if (ev && e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
         h->have_prev = true;  // this step's records are the next step's history
@@ -253,6 +320,57 @@ int validate_shape(const lbm_params *p, int *D, int *Q, size_t *sp, size_t *s, i
     if ((uint64_t)*N * 4 * *s >= ((uint64_t)1 << 32))
         return fail(LBM_ERR_UNSUPPORTED, "%lld cells of 4 x %zu-byte moment records exceed 4 GiB",
                     (long long)*N, *s);
+    return LBM_OK;
+}
+
+// Boundary nodes of a run: validates them and returns their count (host only).
+int boundary_nodes(const lbm_params *p, int D, int64_t N, uint32_t *count, bool *outflow,
+                   bool *vp) {
+    *count = 0;
+    *outflow = *vp = false;
+    if (!p->bc_type) return LBM_OK;
+    if (p->scheme != LBM_SCHEME_TWO_PASS)
+        return fail(LBM_ERR_UNSUPPORTED, "wet-node boundaries need LBM_SCHEME_TWO_PASS");
+    if (p->bc_scheme < LBM_BC_EQUILIBRIUM || p->bc_scheme > LBM_BC_TMS)
+        return fail(LBM_ERR_INVALID_ARG, "bad bc_scheme %d", p->bc_scheme);
+    if (p->bc_rho_rule != LBM_BC_RHO_CONTINUITY && p->bc_rho_rule != LBM_BC_RHO_BOUNCE_BACK)
+        return fail(LBM_ERR_INVALID_ARG, "bad bc_rho_rule %d", p->bc_rho_rule);
+    if (!p->bc_normal) return fail(LBM_ERR_INVALID_ARG, "bc_normal is required with bc_type");
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    auto cell = [&](int x, int y, int z) {
+        x = (x % nx + nx) % nx;
+        y = (y % ny + ny) % ny;
+        z = (z % nz + nz) % nz;
+        return (int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z);
+    };
+    uint32_t k = 0;
+    for (int64_t n = 0; n < N; ++n) {
+        const int t = p->bc_type[n];
+        if (t == LBM_NODE_BULK) continue;
+        if (t > LBM_NODE_OUTFLOW) return fail(LBM_ERR_INVALID_ARG, "bc_type[%lld] = %d", (long long)n, t);
+        const int nm = p->bc_normal[n];
+        if (nm >= 2 * D) return fail(LBM_ERR_INVALID_ARG, "bc_normal[%lld] = %d", (long long)n, nm);
+        if (p->mask && p->mask[n]) return fail(LBM_ERR_INVALID_ARG, "boundary node %lld is solid", (long long)n);
+        const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
+        int o[3] = {0, 0, 0};
+        o[nm >> 1] = (nm & 1) ? 1 : -1;
+        const int64_t out = cell(x + o[0], y + o[1], z + o[2]);
+        const int64_t in = cell(x - o[0], y - o[1], z - o[2]);
+        if (!p->mask || !p->mask[out])
+            return fail(LBM_ERR_INVALID_ARG, "the outward neighbour of boundary node %lld must be solid", (long long)n);
+        if (p->mask[in] || p->bc_type[in] != LBM_NODE_BULK)
+            return fail(LBM_ERR_INVALID_ARG, "the inward neighbour of boundary node %lld must be a bulk fluid cell", (long long)n);
+        if (t == LBM_NODE_VELOCITY && p->bc_velocity)
+            for (int a = 0; a < D; ++a)
+                if (!is_finite(p->bc_velocity[(int64_t)a * N + n]))
+                    return fail(LBM_ERR_INVALID_ARG, "bc_velocity must be finite");
+        if (t == LBM_NODE_PRESSURE && p->bc_density && !(is_finite(p->bc_density[n]) && p->bc_density[n] > 0))
+            return fail(LBM_ERR_INVALID_ARG, "bc_density[%lld] must be finite and > 0", (long long)n);
+        if (t == LBM_NODE_OUTFLOW) *outflow = true;
+        else *vp = true;
+        ++k;
+    }
+    *count = k;
     return LBM_OK;
 }
 
@@ -302,7 +420,12 @@ LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes) {
     if (!workspace_bytes) return fail(LBM_ERR_INVALID_ARG, "workspace_bytes is NULL");
     int rc = validate_shape(p, &D, &Q, &sp, &s, &N);
     if (rc) return rc;
-    *workspace_bytes = make_layout(Q, D, (size_t)N, sp, s, p->mask != nullptr, p->scheme == LBM_SCHEME_LAGGED).total;
+    uint32_t nb = 0;
+    bool bo, bv;
+    rc = boundary_nodes(p, D, N, &nb, &bo, &bv);
+    if (rc) return rc;
+    *workspace_bytes = make_layout(Q, D, (size_t)N, sp, s, p->mask != nullptr,
+                                   p->scheme == LBM_SCHEME_LAGGED, nb).total;
     return LBM_OK;
 }
 
@@ -346,7 +469,11 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     }
     if (!any_fluid) return fail(LBM_ERR_INVALID_ARG, "no fluid cell");
     const bool solids = p->mask != nullptr;
-    const Layout L = make_layout(Q, D, (size_t)N, sp, s, solids, p->scheme == LBM_SCHEME_LAGGED);
+    uint32_t nb = 0;
+    bool bc_outflow = false, bc_vp = false;
+    rc = boundary_nodes(p, D, N, &nb, &bc_outflow, &bc_vp);
+    if (rc) return rc;
+    const Layout L = make_layout(Q, D, (size_t)N, sp, s, solids, p->scheme == LBM_SCHEME_LAGGED, nb);
     if (!dev_workspace) return fail(LBM_ERR_INVALID_ARG, "dev_workspace is NULL");
     if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
         return fail(LBM_ERR_WORKSPACE, "dev_workspace must be 256-byte aligned");
@@ -379,6 +506,11 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->eta_eff = p->eta_eff;
     h->rho0 = p->rho0;
     h->shift = p->shift;
+    h->nb = nb;
+    h->bc_outflow = bc_outflow;
+    h->bc_vp = bc_vp;
+    h->bc_scheme = p->bc_scheme;
+    h->bc_rho_rule = p->bc_rho_rule;
     for (int a = 0; a < 3; ++a) h->b[a] = a < D ? p->b[a] : 0.0;
 
     auto cleanup = [&](int code) {
@@ -414,6 +546,35 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
         if ((e = hipMemcpyAsync(st + N, p->v_init, (size_t)D * NB, hipMemcpyHostToDevice, h->stream)) != hipSuccess)
             return cleanup(fail(LBM_ERR_HIP, "upload of v_init failed: %s", hipGetErrorString(e)));
         v_st = st + N;
+    }
+    // boundary-node list: cell, type | normal << 8, (v_b, rho_b) in the value type
+    std::vector<uint32_t> bcell, bcode;
+    std::vector<char> bval;
+    if (nb) {
+        bcell.reserve(nb);
+        bcode.reserve(nb);
+        bval.resize((size_t)nb * 4 * s);
+        uint32_t k = 0;
+        for (int64_t n = 0; n < N; ++n) {
+            if (!p->bc_type[n]) continue;
+            bcell.push_back((uint32_t)n);
+            bcode.push_back((uint32_t)p->bc_type[n] | ((uint32_t)p->bc_normal[n] << 8));
+            double v4[4] = {0.0, 0.0, 0.0, p->bc_density ? p->bc_density[n] : p->rho0};
+            if (p->bc_velocity)
+                for (int a = 0; a < D; ++a) v4[a] = p->bc_velocity[(int64_t)a * N + n];
+            for (int j = 0; j < 4; ++j) {
+                if (s == 8) std::memcpy(bval.data() + ((size_t)k * 4 + j) * 8, &v4[j], 8);
+                else {
+                    const float x = (float)v4[j];
+                    std::memcpy(bval.data() + ((size_t)k * 4 + j) * 4, &x, 4);
+                }
+            }
+            ++k;
+        }
+        if ((e = hipMemcpyAsync(h->ws + L.bcell, bcell.data(), nb * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(h->ws + L.bcode, bcode.data(), nb * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(h->ws + L.bval, bval.data(), bval.size(), hipMemcpyHostToDevice, h->stream)) != hipSuccess)
+            return cleanup(fail(LBM_ERR_HIP, "upload of boundary nodes failed: %s", hipGetErrorString(e)));
     }
     const uint8_t *mk = mask_ptr(h);
     const bool lag = p->scheme == LBM_SCHEME_LAGGED;
@@ -535,6 +696,8 @@ LBM_API int lbm_get_populations(lbm_solver *h, void *dev_out, int dtype) {
     if (rc) return rc;
     if (!dev_out) return fail(LBM_ERR_INVALID_ARG, "dev_out is NULL");
     if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_INVALID_ARG, "bad dtype");
+    // the unknown incoming populations of outflow nodes are those the next step uses
+    if (h->bc_outflow) dispatch(h, BcOutflowPass{h});
     dispatch(h, ExportPass{h, dev_out, dtype});
     LAUNCH_CHECK();
     return LBM_OK;

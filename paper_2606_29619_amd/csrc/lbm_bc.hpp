@@ -1,0 +1,325 @@
+// lbm_bc.hpp -- wet-node boundary conditions (Sec. 3.4) for the two-pass scheme.
+//
+// A boundary node is a fluid cell with an outward normal n along one axis whose outward
+// neighbour is solid and whose inward neighbour x_f = x_b - n is a bulk fluid cell.  Its
+// post-advection populations split into P- (c_i . n < 0, incoming from outside: unknown), P0
+// (c_i . n = 0) and P+ (c_i . n > 0), eq. (bc_rho_components_def).  Three node types:
+//   velocity node: v_b prescribed, rho_b from mass continuity (bc_density_impermWall) or from
+//                  bounce-back (bc_density_BounceBack); populations rebuilt by the run's scheme;
+//   pressure node: rho_b prescribed, tangential velocity 0, normal velocity from the same
+//                  continuity relation; populations rebuilt by the run's scheme;
+//   outflow node:  P- populations copied from x_f (f_bar_outflow_BC).
+// Per step: outflow copies -> bulk moments -> boundary records (rho_b, v_b) -> velocity
+// correction -> records fixed to (rho_b, v_b) -> population rebuild -> collide-stream.  The
+// node kernels run one thread per boundary node.  A node's populations are read from, and
+// rebuilt into, the slots its own bulk update reads (each slot is read by exactly one cell), so
+// the rebuild touches no other cell's state; NEEM and the outflow copy read x_f's slots, which
+// no boundary kernel writes.
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+enum : uint32_t { kNodeVelocity = 1, kNodePressure = 2, kNodeOutflow = 3 };
+
+// One boundary node: cell index, type | normal << 8, and the prescribed (v_x, v_y, v_z, rho).
+template <typename T>
+struct BNodes {
+    const uint32_t *cell;
+    const uint32_t *code;
+    const P4<T> *val;
+    uint32_t count;
+};
+
+__device__ __forceinline__ void normal_of(uint32_t code, int nv[3]) {
+    const int k = (int)(code >> 8);
+    nv[0] = nv[1] = nv[2] = 0;
+    nv[k >> 1] = (k & 1) ? 1 : -1;
+}
+
+template <int D, int I>
+__device__ __forceinline__ int c_dot(const int nv[3]) {
+    using L = Lat<D>;
+    return L::c[I][0] * nv[0] + L::c[I][1] * nv[1] + L::c[I][2] * nv[2];
+}
+
+__device__ __forceinline__ void cell_xyz(const Grid &g, uint32_t n, int &x, int &y, int &z) {
+    x = (int)(n % (uint32_t)g.nx);
+    y = (int)((n / (uint32_t)g.nx) % (uint32_t)g.ny);
+    z = (int)(n / ((uint32_t)g.nx * (uint32_t)g.ny));
+}
+
+// Slot from which cell n reads f_I (the address load_raw uses), for writing rebuilt values.
+template <int D, bool SOLIDS, int PH, int I, typename P>
+__device__ __forceinline__ P *read_slot(P *__restrict__ f, const uint8_t *__restrict__ mask,
+                                        const Grid &g, const Nbr<D> &nb) {
+    using L = Lat<D>;
+    constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+    const uint32_t n = nb.self();
+    if constexpr (PH == 0 || (cx == 0 && cy == 0 && cz == 0)) {
+        return at(plane(f, I, g.N), n);
+    } else {
+        const uint32_t s = nb.at(-cx, -cy, -cz);
+        if constexpr (SOLIDS) {
+            if (mask[s]) return at(plane(f, I, g.N), n);
+        }
+        return at(plane(f, L::opp[I], g.N), s);
+    }
+}
+
+// Write value v of f_I into cell n's read slot, encoded as that slot is decoded.
+template <int D, bool SOLIDS, int PH, int I, typename T, typename P, typename E>
+__device__ __forceinline__ void write_read_slot(P *__restrict__ f,
+                                                const uint8_t *__restrict__ mask, const E &ev,
+                                                const Phys<T> &ph, const Grid &g,
+                                                const Nbr<D> &nb, T v) {
+    *read_slot<D, SOLIDS, PH, I>(f, mask, g, nb) =
+        encode<D, I, P>(v, load_sigma<D, SOLIDS, I, P>(mask, ev, ph, nb));
+}
+
+// Zero-gradient outflow: f_I(x_b) = f_I(x_f) for I in P-.
+template <int D, typename T, typename P, bool SOLIDS, int PH>
+__global__ __launch_bounds__(256) void k_bc_outflow(P *__restrict__ f,
+                                                    const uint8_t *__restrict__ mask,
+                                                    const T *__restrict__ eps, BNodes<T> bn,
+                                                    Grid g, Phys<T> ph) {
+    const uint32_t k = blockIdx.x * 256u + threadIdx.x;
+    if (k >= bn.count) return;
+    const uint32_t code = bn.code[k];
+    if ((code & 0xffu) != kNodeOutflow) return;
+    int nv[3];
+    normal_of(code, nv);
+    int x, y, z;
+    cell_xyz(g, bn.cell[k], x, y, z);
+    Nbr<D> nb, nf;
+    nb.init(g, x, y, z);
+    nf.init(g, wrapk(x, -nv[0], g.nx), wrapk(y, -nv[1], g.ny), wrapk(z, -nv[2], g.nz));
+    const EpsGlobal<D, T> eb{eps, &nb}, ef{eps, &nf};
+    unroll<0, Lat<D>::Q>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        if (c_dot<D, i>(nv) < 0) {
+            const T v = load_pop<D, SOLIDS, PH, i>(f, mask, ef, ph, g, nf);
+            write_read_slot<D, SOLIDS, PH, i>(f, mask, eb, ph, g, nb, v);
+        }
+    });
+}
+
+// Records (rho_b, v_b) of velocity and pressure nodes, written over the bulk moment pass.
+//   velocity node: rho_b = (S0 + 2 S+) / (eps_b + v_perp - a_perp / 2) with
+//     a_perp = eps_b b_perp - mu_D v_perp - mu_F |v_b| v_perp + RT d(eps)/dn (eq.
+//     accel_approx_boundary without its viscous term), or the bounce-back density;
+//   pressure node: v_perp (1 + mu_D / 2) + (mu_F / 2) |v_perp| v_perp = R,
+//     R = (S0 + 2 S+) / rho_b - eps_b + (eps_b b_perp + RT d(eps)/dn) / 2, closed form as v_(1).
+template <int D, typename T, typename P, bool SOLIDS, int PH>
+__global__ __launch_bounds__(256) void k_bc_records(const P *__restrict__ f,
+                                                    const uint8_t *__restrict__ mask,
+                                                    const T *__restrict__ eps,
+                                                    const T *__restrict__ muD,
+                                                    const T *__restrict__ muF,
+                                                    P4<T> *__restrict__ m1, BNodes<T> bn, Grid g,
+                                                    Phys<T> ph, int bounce_back_density) {
+    const uint32_t k = blockIdx.x * 256u + threadIdx.x;
+    if (k >= bn.count) return;
+    const uint32_t code = bn.code[k];
+    const uint32_t type = code & 0xffu;
+    if (type != kNodeVelocity && type != kNodePressure) return;
+    int nv[3];
+    normal_of(code, nv);
+    int x, y, z;
+    const uint32_t n = bn.cell[k];
+    cell_xyz(g, n, x, y, z);
+    Nbr<D> nb;
+    nb.init(g, x, y, z);
+    const EpsGlobal<D, T> ev{eps, &nb};
+    T s0 = T(0), sp = T(0), sum = T(0);
+    unroll<0, Lat<D>::Q>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        const T fi = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
+        sum = sum + fi;
+        const int cn = c_dot<D, i>(nv);
+        if (cn == 0) s0 = s0 + fi;
+        else if (cn > 0) sp = sp + fi;
+    });
+    const int ax = (int)(code >> 9);
+    const T sgn = (code >> 8) & 1u ? T(1) : T(-1);
+    const T e = ev.at(0, 0, 0);
+    const int ox = ax == 0, oy = ax == 1, oz = ax == 2;
+    const T gperp = sgn * ((ev.at(ox, oy, oz) - ev.at(-ox, -oy, -oz)) * T(0.5));
+    const T bperp = sgn * ph.b[ax];
+    const P4<T> pv = bn.val[k];
+    T vb[3] = {pv.x, pv.y, pv.z};
+    T rho;
+    if (type == kNodeVelocity) {
+        const T vperp = sgn * vb[ax];
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) s = s + vb[a] * vb[a];
+        const T vm = sq(s);
+        if (bounce_back_density) {
+            rho = dv(sum, e);
+        } else {
+            const T aperp = ((e * bperp - ld(muD, n) * vperp) - (ld(muF, n) * vm) * vperp) +
+                            ph.RT * gperp;
+            rho = dv(s0 + T(2) * sp, (e + vperp) - T(0.5) * aperp);
+        }
+    } else {
+        rho = pv.w;
+        const T R = (dv(s0 + T(2) * sp, rho) - e) + T(0.5) * (e * bperp + ph.RT * gperp);
+        const T c1 = T(1) + T(0.5) * ld(muD, n), c2 = T(0.5) * ld(muF, n);
+        const T vperp = dv(T(2) * R, c1 + sq(c1 * c1 + (T(4) * c2) * (R < T(0) ? -R : R)));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) vb[a] = T(0);
+        vb[ax] = sgn * vperp;
+    }
+    *at(m1, n) = pack(rho, vb[0], vb[1], D == 3 ? vb[2] : T(0));
+}
+
+// After the velocity correction: the corrected velocity of velocity and pressure nodes is v_b.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bc_fix(const P4<T> *__restrict__ m1,
+                                                P4<T> *__restrict__ m2, BNodes<T> bn) {
+    const uint32_t k = blockIdx.x * 256u + threadIdx.x;
+    if (k >= bn.count) return;
+    const uint32_t type = bn.code[k] & 0xffu;
+    if (type != kNodeVelocity && type != kNodePressure) return;
+    const uint32_t n = bn.cell[k];
+    *at(m2, n) = ld(m1, n);
+}
+
+// Equilibrium populations (prod_form) at velocity w: xi = w / eps, P = xi^2 + RT.
+template <int D, typename T>
+__device__ __forceinline__ void eq_at(T e, T rho, const T w[3], T RT, ProductForm<D, T> &pf) {
+    T xi[3] = {T(0), T(0), T(0)}, P[3] = {RT, RT, RT};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        xi[a] = dv(w[a], e);
+        P[a] = xi[a] * xi[a] + RT;
+    }
+    pf.init(e * rho, xi, P);
+}
+
+// Acceleration of cell nb from the (rho, v) records.
+template <int D, typename T, bool SOLIDS>
+__device__ __forceinline__ void node_accel(const P4<T> *__restrict__ m2,
+                                           const T *__restrict__ eps, const T *__restrict__ muD,
+                                           const T *__restrict__ muF,
+                                           const uint8_t *__restrict__ mask, const Grid &g,
+                                           const Phys<T> &ph, const Nbr<D> &nb,
+                                           const EpsGlobal<D, T> &ev, Rec<T> &own, Visc<T> &vs,
+                                           T acc[3]) {
+    own = load_rec<D>(m2, nb.self(), ev.at(0, 0, 0));
+    const CellStatic<D, T> cs = cell_static<D>(ev, ph, own.e);
+    vs = cs.vs;
+    Rec<T> rec[3][2];
+    bool fl[3][2];
+    load_stencil<D, T, SOLIDS>(m2, ev, mask, g, nb, rec, fl);
+    accel_of<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, rec, fl, cs.ge, cs.H, cs.vs,
+                           acc);
+}
+
+// Rebuild of all post-advection populations of velocity and pressure nodes, lambda = dt = 1,
+// f^tgt = f^eq(eps_b, rho_b, v_b), f^* = f^eq(eps_b, rho_b, v_b + a_b):
+//   scheme 0, eq. (eq_bc_f_bar): f_i = (3/2) f^tgt_i - (1/2) f^*_i;
+//   scheme 1, eqs. (NEEM_bc_f_bar), (zeta_beta_NEEM):
+//     f_i = zeta f_i(x_f) + (3/2)[f^tgt_i - zeta f^eq_i(x_f)] + (1/2)[zeta f^*_i(x_f) - f^*_i];
+//   scheme 2, TMS (Sec. 3.4.4, steps 1-3).
+template <int D, typename T, typename P, bool SOLIDS, int PH>
+__global__ __launch_bounds__(256) void k_bc_rebuild(P *__restrict__ f,
+                                                    const P4<T> *__restrict__ m2,
+                                                    const T *__restrict__ eps,
+                                                    const T *__restrict__ muD,
+                                                    const T *__restrict__ muF,
+                                                    const uint8_t *__restrict__ mask,
+                                                    BNodes<T> bn, Grid g, Phys<T> ph,
+                                                    int scheme) {
+    using L = Lat<D>;
+    const uint32_t k = blockIdx.x * 256u + threadIdx.x;
+    if (k >= bn.count) return;
+    const uint32_t code = bn.code[k];
+    const uint32_t type = code & 0xffu;
+    if (type != kNodeVelocity && type != kNodePressure) return;
+    int nv[3];
+    normal_of(code, nv);
+    int x, y, z;
+    cell_xyz(g, bn.cell[k], x, y, z);
+    Nbr<D> nb;
+    nb.init(g, x, y, z);
+    const EpsGlobal<D, T> ev{eps, &nb};
+    Rec<T> own;
+    Visc<T> vs;
+    T acc[3];
+    node_accel<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, ev, own, vs, acc);
+    T vstar[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) vstar[a] = own.w[a] + acc[a];
+    ProductForm<D, T> ftgt, fst;
+    eq_at<D>(own.e, own.r, own.w, ph.RT, ftgt);
+    eq_at<D>(own.e, own.r, vstar, ph.RT, fst);
+    if (scheme == 0) {
+        unroll<0, L::Q>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            const T v = T(1.5) * ftgt.template at<i>() - T(0.5) * fst.template at<i>();
+            write_read_slot<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb, v);
+        });
+    } else if (scheme == 1) {
+        Nbr<D> nf;
+        nf.init(g, wrapk(x, -nv[0], g.nx), wrapk(y, -nv[1], g.ny), wrapk(z, -nv[2], g.nz));
+        const EpsGlobal<D, T> evf{eps, &nf};
+        Rec<T> ownf;
+        Visc<T> vsf;
+        T accf[3];
+        node_accel<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nf, evf, ownf, vsf, accf);
+        T vfs[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int a = 0; a < D; ++a) vfs[a] = ownf.w[a] + accf[a];
+        ProductForm<D, T> feqf, fstf;
+        eq_at<D>(ownf.e, ownf.r, ownf.w, ph.RT, feqf);
+        eq_at<D>(ownf.e, ownf.r, vfs, ph.RT, fstf);
+        const T zeta = dv(T(1) - vsf.beta, T(1) - vs.beta);
+        T fb[L::Q];
+        unroll<0, L::Q>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            const T ff = load_pop<D, SOLIDS, PH, i>(f, mask, evf, ph, g, nf);
+            fb[i] = (zeta * ff + T(1.5) * (ftgt.template at<i>() - zeta * feqf.template at<i>())) +
+                    T(0.5) * (zeta * fstf.template at<i>() - fst.template at<i>());
+        });
+        unroll<0, L::Q>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            write_read_slot<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb, fb[i]);
+        });
+    } else {
+        const T omb = T(1) - vs.beta;
+        T fi[L::Q];
+        T s0 = T(0), s1[3] = {T(0), T(0), T(0)};
+        unroll<0, L::Q>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
+            if (c_dot<D, i>(nv) >= 0) {
+                const T d = (fi[i] - T(1.5) * ftgt.template at<i>()) + T(0.5) * fst.template at<i>();
+                s0 = s0 + d;
+                unroll<0, D>([&](auto ia) {
+                    constexpr int a = decltype(ia)::value;
+                    if constexpr (L::c[i][a] == 1) s1[a] = s1[a] + d;
+                    else if constexpr (L::c[i][a] == -1) s1[a] = s1[a] - d;
+                });
+            }
+        });
+        const T rloc = dv(own.e * own.r + omb * s0, own.e);
+        T vloc[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int a = 0; a < D; ++a) vloc[a] = dv(own.r * own.w[a] + omb * s1[a], rloc);
+        ProductForm<D, T> floc;
+        eq_at<D>(own.e, rloc, vloc, ph.RT, floc);
+        unroll<0, L::Q>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            const T neq = dv(ftgt.template at<i>() - floc.template at<i>(), omb);
+            const T v = c_dot<D, i>(nv) < 0
+                            ? neq + (T(1.5) * ftgt.template at<i>() - T(0.5) * fst.template at<i>())
+                            : neq + fi[i];
+            write_read_slot<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb, v);
+        });
+    }
+}
+
+}  // namespace lbm

@@ -656,6 +656,32 @@ __device__ __forceinline__ T record_deriv(const P4<T> *__restrict__ mom,
     return deriv_rule(v5, f5);
 }
 
+// Acceleration (accel) with Delta_nu(rho v / eps) from the record stencil (porosity_correction).
+template <int D, typename T, bool SOLIDS>
+__device__ __forceinline__ void accel_of(const P4<T> *__restrict__ mom,
+                                         const T *__restrict__ eps, const T *__restrict__ muD,
+                                         const T *__restrict__ muF,
+                                         const uint8_t *__restrict__ mask, const Grid &g,
+                                         const Phys<T> &ph, const Nbr<D> &nb, const Rec<T> &own,
+                                         const Rec<T> rec[3][2], const bool fl[3][2],
+                                         const T ge[3], const T H[3][3], const Visc<T> &vs,
+                                         T acc[3]) {
+    const uint32_t n = nb.self();
+    T dm[3] = {T(0), T(0), T(0)};
+    delta_nu<D, T, SOLIDS>(mom, eps, mask, g, nb, own, rec, fl, ge, H, vs, dm);
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) s = s + own.w[a] * own.w[a];
+    const T vm = sq(s);
+    const T md = ld(muD, n), mf = ld(muF, n);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[a] = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        acc[a] = (((own.e * ph.b[a] - md * own.w[a]) - (mf * vm) * own.w[a]) + ph.RT * ge[a]) +
+                 dv(dm[a], own.r);
+}
+
 // Equilibrium and shifted-equilibrium arguments of one cell from the moment fields (rho, v):
 // acceleration (accel), Phi^ext (ex_corr), Phi^eta (eta_corr), then xi, P (xi_alpha_eq,
 // P_alpha_alpha_eq) and xi*, P* (xi_alpha_*, P_aa_*) with lambda = 1.  `own` is the cell's
@@ -671,22 +697,11 @@ __device__ __forceinline__ void forcing_args(const P4<T> *__restrict__ mom, cons
                                              const Rec<T> &own, const T ge[3], const T H[3][3],
                                              const Visc<T> &vs, T xi[3], T P[3], T xs[3],
                                              T Ps[3]) {
-    const uint32_t n = nb.self();
     Rec<T> rec[3][2];
     bool fl[3][2];
     load_stencil<D, T, SOLIDS>(mom, ev, mask, g, nb, rec, fl);
-    T dm[3] = {T(0), T(0), T(0)};
-    delta_nu<D, T, SOLIDS>(mom, eps, mask, g, nb, own, rec, fl, ge, H, vs, dm);
-    T s = T(0);
-#pragma unroll
-    for (int a = 0; a < D; ++a) s = s + own.w[a] * own.w[a];
-    const T vm = sq(s);
-    const T md = ld(muD, n), mf = ld(muF, n);
     T acc[3];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-        acc[a] = (((own.e * ph.b[a] - md * own.w[a]) - (mf * vm) * own.w[a]) + ph.RT * ge[a]) +
-                 dv(dm[a], own.r);
+    accel_of<D, T, SOLIDS>(mom, eps, muD, muF, mask, g, ph, nb, own, rec, fl, ge, H, vs, acc);
     T phx[3];
 #pragma unroll
     for (int a = 0; a < D; ++a) {

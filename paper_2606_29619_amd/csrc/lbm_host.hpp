@@ -46,11 +46,14 @@ inline int fail(int code, const char *fmt, ...) {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t f, eps, muD, muF, mask, m1[2], m2[2], vsnap, part, res, total;
+    size_t f, eps, muD, muF, mask, m1[2], m2[2], vsnap, part, res;
+    size_t bcell, bcode, bval;  // boundary-node list (wet-node boundaries)
+    size_t total;
 };
 
 // sp: bytes per population value; s: bytes per value of the static fields and moment records.
-inline Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool solids, bool lagged) {
+inline Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool solids, bool lagged,
+                          size_t nbnodes = 0) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -73,6 +76,9 @@ inline Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool soli
     L.vsnap = take((size_t)D * N * s);
     L.part = take((size_t)lbm::kStatsBlocks * lbm::kStatsSlots * sizeof(double));
     L.res = take(lbm::kStatsSlots * sizeof(double));
+    L.bcell = nbnodes ? take(nbnodes * sizeof(uint32_t)) : 0;
+    L.bcode = nbnodes ? take(nbnodes * sizeof(uint32_t)) : 0;
+    L.bval = nbnodes ? take(nbnodes * 4 * s) : 0;
     L.total = off;
     return L;
 }
@@ -97,6 +103,9 @@ struct lbm_solver {
     double RT, nu_f, nu_eff_ref, eta_eff, b[3], rho0;
     int nu_eff_pow;
     int shift;          // 16-bit population shift (LBM_SHIFT_*)
+    uint32_t nb;        // boundary nodes
+    bool bc_outflow, bc_vp;  // outflow nodes, velocity or pressure nodes present
+    int bc_scheme, bc_rho_rule;
     lbm::Tiling tiles;  // 256-cell tiles, blocked, in XCD-contiguous ranges
 };
 

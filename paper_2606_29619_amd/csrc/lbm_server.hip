@@ -401,6 +401,8 @@ LBM_API int lbm_server_submit(lbm_server *s, const lbm_params *p, double tol, in
     if (!p || !id) return fail(LBM_ERR_INVALID_ARG, "null argument");
     if (!(tol > 0) || max_steps < s->check_every)
         return fail(LBM_ERR_INVALID_ARG, "tol must be > 0 and max_steps >= check_every");
+    if (p->bc_type)
+        return fail(LBM_ERR_UNSUPPORTED, "the server runs periodic / bounce-back runs (no bc_type)");
     size_t bytes = 0;
     rc = lbm_footprint(p, &bytes);
     if (rc) return rc;

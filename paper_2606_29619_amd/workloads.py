@@ -52,6 +52,14 @@ class Workload:
     rho_init: Optional[np.ndarray] = None
     v_init: Optional[np.ndarray] = None
     meta: dict = field(default_factory=dict)
+    # wet-node boundaries: node type (0 bulk, 1 velocity, 2 pressure, 3 outflow), outward
+    # normal (0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z), prescribed velocity [D] and density
+    bc_type: Optional[np.ndarray] = None
+    bc_normal: Optional[np.ndarray] = None
+    bc_velocity: Optional[np.ndarray] = None
+    bc_density: Optional[np.ndarray] = None
+    bc_scheme: int = 1          # 0 equilibrium, 1 NEEM, 2 TMS
+    bc_rho_rule: int = 0        # 0 mass continuity, 1 bounce-back
 
     @property
     def D(self) -> int:
@@ -224,3 +232,65 @@ def request_stream(n_requests=512, seed=0):
         t += q["arrival"]
         q["arrival_time"] = t
     return reqs
+
+
+def couette_gravity_2d(H=32, eps=0.5, Da=1e-2, nu=0.1, Gamma=1.0, V0=0.01, nx=4,
+                       scheme=1, rho_rule=0):
+    """Couette flow under gravity between wet-node walls (Sec. 5.1): walls at y = 0 and y = H
+    (grid rows 1 and H + 1, solid rows outside) moving with -V0 and +V0, gravity -g y with
+    g H / RT = Gamma, homogeneous porosity with kappa = Da H^2, mu_F = 0; initial density the
+    exponential profile normalised to mean 1."""
+    RT = 1.0 / 3.0
+    ny = H + 3
+    shape = (1, ny, nx)
+    g = Gamma * RT / H
+    mask = np.zeros(shape, np.uint8)
+    mask[:, 0, :] = mask[:, -1, :] = 1
+    bct = np.zeros(shape, np.uint8)
+    bcn = np.zeros(shape, np.uint8)
+    bct[:, 1, :] = bct[:, -2, :] = 1
+    bcn[:, 1, :], bcn[:, -2, :] = 2, 3
+    vel = np.zeros((2,) + shape)
+    vel[0, :, 1, :], vel[0, :, -2, :] = -V0, V0
+    y = np.arange(H + 1.0)
+    prof = np.exp(-g * y / RT)
+    rho = np.ones(shape)
+    rho[:, 1:-1, :] = (prof / prof.mean())[None, :, None]
+    return Workload(name=f"Couette with gravity D2Q9 H={H}", lattice=9,
+                    eps=np.full(shape, float(eps)), kappa=np.full(shape, Da * H * H),
+                    forch=np.zeros(shape), mask=mask, nu_f=nu, nu_eff_ref=nu, nu_eff_pow=0,
+                    b=(0.0, -g, 0.0), rho_init=rho, bc_type=bct, bc_normal=bcn,
+                    bc_velocity=vel, bc_scheme=scheme, bc_rho_rule=rho_rule,
+                    meta={"H": H, "g": g, "V0": V0, "Da": Da})
+
+
+def pressure_channel(D=2, L=64, H=16, W=8, drho=1e-3, outflow=False, body=0.0, eps=None,
+                     kappa=None, forch=None, nu=0.1):
+    """Channel along x between solid walls (halfway bounce-back): pressure nodes at x = 1
+    (rho = 1 + drho/2) and at x = L + 1 (rho = 1 - drho/2), or a zero-gradient outflow there;
+    columns 0 and L + 2 solid.  D = 3 adds solid walls in z (W fluid cells wide)."""
+    nx, ny = L + 3, H + 2
+    nz = W + 2 if D == 3 else 1
+    shape = (nz, ny, nx)
+    mask = np.zeros(shape, np.uint8)
+    mask[:, 0, :] = mask[:, -1, :] = 1
+    mask[:, :, 0] = mask[:, :, -1] = 1
+    if D == 3:
+        mask[0] = mask[-1] = 1
+    inner = (slice(1, -1) if D == 3 else slice(None), slice(1, -1))
+    bct = np.zeros(shape, np.uint8)
+    bcn = np.zeros(shape, np.uint8)
+    bct[inner + (1,)], bcn[inner + (1,)] = 2, 0
+    bct[inner + (-2,)], bcn[inner + (-2,)] = (3 if outflow else 2), 1
+    brho = np.ones(shape)
+    brho[..., 1] = 1 + drho / 2
+    brho[..., -2] = 1 - drho / 2
+    x = np.arange(nx)
+    rho = np.broadcast_to((1 + drho / 2 - drho * (x - 1) / L), shape).copy()
+    e = np.ones(shape) if eps is None else eps
+    k = np.full(shape, np.inf) if kappa is None else kappa
+    c = np.zeros(shape) if forch is None else forch
+    return Workload(name=f"pressure channel D{D} {L}x{H}", lattice=9 if D == 2 else 27,
+                    eps=e, kappa=k, forch=c, mask=mask, nu_f=nu, nu_eff_ref=nu, nu_eff_pow=0,
+                    b=(body, 0.0, 0.0), rho_init=rho, bc_type=bct, bc_normal=bcn,
+                    bc_density=brho, meta={"L": L, "H": H, "drho": drho})

@@ -237,3 +237,56 @@ def test_server_submit_copies_and_queues():
         assert ei.value.code == capi.LBM_ERR_WORKSPACE
     finally:
         capi.lbm_server_destroy(s)
+
+
+# --------------------------------------------------------------------------------------------
+# Wet-node boundaries: host-side validation
+# --------------------------------------------------------------------------------------------
+def _bc_params(**over):
+    from paper_2606_29619_amd import workloads
+    w = workloads.couette_gravity_2d(H=8)
+    kw = dict(bc_type=w.bc_type, bc_normal=w.bc_normal, bc_velocity=w.bc_velocity)
+    kw.update(over)
+    return capi.make_params(capi.LBM_D2Q9, capi.LBM_F64, w.eps, w.kappa, w.forch, w.mask,
+                            rho_init=w.rho_init, **kw), w
+
+
+def test_boundary_footprint_and_validation():
+    (p, keep), w = _bc_params()
+    (p0, keep0), _ = _bc_params(bc_type=None)
+    nb = int((w.bc_type > 0).sum())
+    assert capi.lbm_footprint(p) - capi.lbm_footprint(p0) >= nb * (4 + 4 + 32)
+    # lagged scheme: not supported with wet-node boundaries
+    p.scheme = capi.LBM_SCHEME_LAGGED
+    with pytest.raises(capi.LbmError) as ei:
+        capi.lbm_footprint(p)
+    assert ei.value.code == capi.LBM_ERR_UNSUPPORTED
+    # a boundary node whose outward neighbour is fluid
+    bct = w.bc_type.copy()
+    bct[0, 3, 1] = 1
+    (p2, keep2), _ = _bc_params(bc_type=bct)
+    with pytest.raises(capi.LbmError) as ei:
+        capi.lbm_create(p2, 1 << 40, 1 << 30, 0)
+    assert ei.value.code == capi.LBM_ERR_INVALID_ARG and "outward" in str(ei.value)
+    # a bad normal code and a bad scheme
+    bcn = w.bc_normal.copy()
+    bcn[0, 1, 0] = 4                   # -z on a D2Q9 grid
+    (p3, keep3), _ = _bc_params(bc_normal=bcn)
+    with pytest.raises(capi.LbmError) as ei:
+        capi.lbm_footprint(p3)
+    assert ei.value.code == capi.LBM_ERR_INVALID_ARG
+    (p4, keep4), _ = _bc_params(bc_scheme=7)
+    with pytest.raises(capi.LbmError) as ei:
+        capi.lbm_footprint(p4)
+    assert ei.value.code == capi.LBM_ERR_INVALID_ARG
+
+
+def test_server_rejects_boundary_runs():
+    (p, keep), _ = _bc_params()
+    s = capi.lbm_server_create(_FAKE_POOL, 1 << 30, 100, 0, 0)
+    try:
+        with pytest.raises(capi.LbmError) as ei:
+            capi.lbm_server_submit(s, p, 1e-7, 1000)
+        assert ei.value.code == capi.LBM_ERR_UNSUPPORTED
+    finally:
+        capi.lbm_server_destroy(s)

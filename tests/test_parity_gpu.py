@@ -35,7 +35,9 @@ def _oracle_for(w, **extra):
     cfg = oracle.OracleConfig(D=w.D, eps=w.eps, kappa=w.kappa, cf=w.forch, mask=w.mask,
                               RT=w.RT, nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref,
                               nu_eff_pow=w.nu_eff_pow, eta_eff=w.eta_eff, b=w.b, rho0=w.rho0,
-                              rho_init=w.rho_init, v_init=w.v_init, **extra)
+                              rho_init=w.rho_init, v_init=w.v_init, bc_type=w.bc_type,
+                              bc_normal=w.bc_normal, bc_vel=w.bc_velocity, bc_rho=w.bc_density,
+                              bc_scheme=w.bc_scheme, bc_density=w.bc_rho_rule, **extra)
     return oracle.Oracle(cfg)
 
 
