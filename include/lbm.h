@@ -162,6 +162,11 @@ typedef struct lbm_params {
     const double *bc_density;   /* [N] rho_b of pressure nodes, or NULL (rho0) */
     int bc_scheme;              /* LBM_BC_EQUILIBRIUM, LBM_BC_NEEM or LBM_BC_TMS */
     int bc_rho_rule;            /* LBM_BC_RHO_CONTINUITY or LBM_BC_RHO_BOUNCE_BACK */
+    int picard_iters;           /* 0..64: Picard iterations of the second-order velocity
+                                   evaluation (App. F) after the one-shot correction, two-pass
+                                   scheme only; each is one stencil pass over the moment records
+                                   (and, with boundaries, their records fixed again) */
+    double picard_omega;        /* under-relaxation omega in (0, 1] of the iterations */
 } lbm_params;
 
 /* Global statistics of the current state, accumulated in FP64 on the device. */

@@ -49,6 +49,7 @@ class _Params(ctypes.Structure):
         ("bc_type", ctypes.POINTER(ctypes.c_uint8)), ("bc_normal", ctypes.POINTER(ctypes.c_uint8)),
         ("bc_vel", ctypes.POINTER(ctypes.c_double)), ("bc_rho", ctypes.POINTER(ctypes.c_double)),
         ("bc_scheme", ctypes.c_int), ("bc_density", ctypes.c_int),
+        ("picard_iters", ctypes.c_int), ("picard_omega", ctypes.c_double),
     ]
 
 
@@ -151,6 +152,8 @@ class OracleConfig:
     bc_rho: Optional[np.ndarray] = None
     bc_scheme: int = 1                     # 0 equilibrium, 1 NEEM, 2 TMS
     bc_density: int = 0                    # 0 mass continuity, 1 bounce-back
+    picard_iters: int = 0                  # App. F: Picard iterations after the one-shot step
+    picard_omega: float = 1.0
 
 
 class Oracle:
@@ -207,6 +210,7 @@ class Oracle:
         p.bc_vel = _dp(arr(cfg.bc_vel, (cfg.D,) + self.shape))
         p.bc_rho = _dp(arr(cfg.bc_rho))
         p.bc_scheme, p.bc_density = cfg.bc_scheme, cfg.bc_density
+        p.picard_iters, p.picard_omega = cfg.picard_iters, cfg.picard_omega
         err = ctypes.create_string_buffer(256)
         h = lib().orc_create(ctypes.byref(p), err, 256)
         if not h:

@@ -58,6 +58,10 @@ typedef struct {
     int bc_scheme;            /* 0 equilibrium (eq_bc_f_bar), 1 NEEM (NEEM_bc_f_bar), 2 TMS */
     int bc_density;           /* velocity nodes: 0 mass continuity (bc_density_impermWall),
                                  1 bounce-back (bc_density_BounceBack) */
+    /* Second-order velocity evaluation (App. F): Picard iterations after the one-shot
+     * correction (0 = one-shot only) and the under-relaxation factor omega in (0, 1]. */
+    int picard_iters;
+    double picard_omega;
 } orc_params;
 
 typedef struct {
@@ -72,6 +76,7 @@ typedef struct {
     double *H;              /* [D*D][N] Hessian of eps */
     uint8_t *solid;         /* [N] */
     double *rho, *v1, *v;   /* moments: rho [N], v^(1) [D][N], corrected v [D][N] */
+    double *v0;             /* base predictor v_0 [D][N] (v_(0)) */
     double *m;              /* scratch vector field [D][N] */
     double *g;              /* scratch scalar field [N] */
     double *prho, *pv1, *pv;/* previous-step rho, v^(1) and v (lagged mode) */
@@ -327,7 +332,7 @@ void orc_destroy(orc_solver *S)
     free(S->F); free(S->G); free(S->eps); free(S->muD); free(S->muF); free(S->nu);
     free(S->dnu); free(S->beta); free(S->ge); free(S->H); free(S->solid); free(S->rho);
     free(S->v1); free(S->v); free(S->m); free(S->g); free(S->prho); free(S->pv1); free(S->pv);
-    free(S->bnodes);
+    free(S->bnodes); free(S->v0);
     free(S->vw);
     free(S->vsnap);
     free(S->nbr);
@@ -384,11 +389,12 @@ orc_solver *orc_create(const orc_params *p, char *err, int errlen)
     S->pv1 = (double *)xcalloc(D * N, sizeof(double));
     S->pv = (double *)xcalloc(D * N, sizeof(double));
     S->vw = (double *)xcalloc(D * N, sizeof(double));
+    S->v0 = (double *)xcalloc(D * N, sizeof(double));
     S->vsnap = (double *)xcalloc(D * N, sizeof(double));
     S->nbr = (long *)xcalloc(6 * N, sizeof(long));
     if (!S->F || !S->G || !S->eps || !S->muD || !S->muF || !S->nu || !S->dnu || !S->beta ||
         !S->ge || !S->H || !S->solid || !S->rho || !S->v1 || !S->v || !S->m || !S->g ||
-        !S->prho || !S->pv1 || !S->pv || !S->vw || !S->vsnap || !S->nbr) {
+        !S->prho || !S->pv1 || !S->pv || !S->vw || !S->vsnap || !S->nbr || !S->v0) {
         snprintf(err, (size_t)errlen, "out of host memory");
         orc_destroy(S);
         return NULL;
@@ -458,6 +464,7 @@ static void moments_v1(orc_solver *S)
         for (a = 0; a < D; ++a)
             v0[a] = Pi[a] / rho + 0.5 * (e * S->p.b[a] + S->p.RT * S->ge[a * N + n]);
         drag_solve(D, v0, S->muD[n], S->muF[n], v1);
+        for (a = 0; a < D; ++a) S->v0[a * N + n] = v0[a];
         S->rho[n] = rho;
         for (a = 0; a < D; ++a) S->v1[a * N + n] = v1[a];
     }
@@ -832,6 +839,38 @@ static void reconstruct_boundaries(orc_solver *S, const double *acc)
     }
 }
 
+/* Second-order velocity evaluation (App. F): starting from the one-shot velocity, Picard
+ * iterations of the implicit relation c_1 v + c_2 |v| v = v_0 + Delta_nu(rho v / eps) / (2 rho):
+ *   s^(k) = v_0 + Delta_nu(rho v^(k) / eps) / (2 rho),  v^(k+1) = 2 s^(k) / (c_1 + sqrt(c_1^2 +
+ *   4 c_2 |s^(k)|)), optionally under-relaxed, v^(k+1) <- (1 - omega) v^(k) + omega v^(k+1);
+ * a fixed number of iterations, every cell from the previous iterate (Jacobi order).  Boundary
+ * velocity and pressure nodes keep their boundary velocity. */
+static void picard_velocity(orc_solver *S)
+{
+    int D = S->D, a, it;
+    long n, N = S->N;
+    double omega = S->p.picard_omega;
+    double *vn = S->vw;
+    for (it = 0; it < S->p.picard_iters; ++it) {
+        momentum_over_eps(S, S->rho, S->v);
+        for (n = 0; n < N; ++n) {
+            double dn[3], sv[3], vk[3];
+            int bnode = S->p.bc_type && (S->p.bc_type[n] == 1 || S->p.bc_type[n] == 2);
+            if (S->solid[n] || bnode) {
+                for (a = 0; a < D; ++a) vn[a * N + n] = S->v[a * N + n];
+                continue;
+            }
+            delta_nu_field(S, S->m, n, dn);
+            for (a = 0; a < D; ++a) sv[a] = S->v0[a * N + n] + dn[a] / (2.0 * S->rho[n]);
+            drag_solve(D, sv, S->muD[n], S->muF[n], vk);
+            for (a = 0; a < D; ++a)
+                vn[a * N + n] = omega == 1.0 ? vk[a]
+                                             : (1.0 - omega) * S->v[a * N + n] + omega * vk[a];
+        }
+        memcpy(S->v, vn, sizeof(double) * (size_t)(D * N));
+    }
+}
+
 /* Moments of the current state: outflow copies, bulk moments and drag solve, boundary
  * records, velocity correction. */
 static void compute_moments(orc_solver *S)
@@ -841,6 +880,7 @@ static void compute_moments(orc_solver *S)
     boundary_records(S);
     correct_velocity(S);
     boundary_velocity(S);
+    if (S->p.picard_iters > 0) picard_velocity(S);
 }
 
 /* Post-collision populations (dicrete_scheme, momentum_rate) with lambda = dt = 1:

@@ -60,6 +60,7 @@ class lbm_params(ctypes.Structure):
         ("bc_type", ctypes.POINTER(ctypes.c_uint8)), ("bc_normal", ctypes.POINTER(ctypes.c_uint8)),
         ("bc_velocity", _dp), ("bc_density", _dp),
         ("bc_scheme", ctypes.c_int), ("bc_rho_rule", ctypes.c_int),
+        ("picard_iters", ctypes.c_int), ("picard_omega", ctypes.c_double),
     ]
 
 
@@ -286,7 +287,8 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
                 bc_type: Optional[np.ndarray] = None, bc_normal: Optional[np.ndarray] = None,
                 bc_velocity: Optional[np.ndarray] = None,
                 bc_density: Optional[np.ndarray] = None, bc_scheme: int = LBM_BC_NEEM,
-                bc_rho_rule: int = LBM_BC_RHO_CONTINUITY):
+                bc_rho_rule: int = LBM_BC_RHO_CONTINUITY, picard_iters: int = 0,
+                picard_omega: float = 1.0):
     """Build an lbm_params from numpy arrays shaped [nz, ny, nx]; returns (params, keepalive)."""
     eps = np.ascontiguousarray(eps, dtype=np.float64)
     if eps.ndim == 2:
@@ -330,6 +332,7 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
     p.bc_velocity = arr(bc_velocity, (D,) + eps.shape)
     p.bc_density = arr(bc_density, eps.shape)
     p.bc_scheme, p.bc_rho_rule = bc_scheme, bc_rho_rule
+    p.picard_iters, p.picard_omega = picard_iters, picard_omega
     return p, keep
 
 
@@ -370,7 +373,9 @@ class Solver:
                               bc_velocity=getattr(w, "bc_velocity", None),
                               bc_density=getattr(w, "bc_density", None),
                               bc_scheme=getattr(w, "bc_scheme", LBM_BC_NEEM),
-                              bc_rho_rule=getattr(w, "bc_rho_rule", LBM_BC_RHO_CONTINUITY))
+                              bc_rho_rule=getattr(w, "bc_rho_rule", LBM_BC_RHO_CONTINUITY),
+                              picard_iters=getattr(w, "picard_iters", 0),
+                              picard_omega=getattr(w, "picard_omega", 1.0))
         return cls(p, keep, **kw)
 
     def close(self):
@@ -460,7 +465,9 @@ class Server:
                               bc_velocity=getattr(w, "bc_velocity", None),
                               bc_density=getattr(w, "bc_density", None),
                               bc_scheme=getattr(w, "bc_scheme", LBM_BC_NEEM),
-                              bc_rho_rule=getattr(w, "bc_rho_rule", LBM_BC_RHO_CONTINUITY))
+                              bc_rho_rule=getattr(w, "bc_rho_rule", LBM_BC_RHO_CONTINUITY),
+                              picard_iters=getattr(w, "picard_iters", 0),
+                              picard_omega=getattr(w, "picard_omega", 1.0))
         rid = self.submit_params(p, tol, max_steps)   # the library copies the arrays
         return rid
 

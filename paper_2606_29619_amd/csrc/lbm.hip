@@ -27,10 +27,21 @@ namespace lbmh {
 template <int D, typename T, typename P, bool S, int PH>
 void launch_moments(const lbm_solver *h, size_t m1_out) {
     auto ph = phys_of<T>(h);
+    lbm::P4<T> *m0 = h->picard_iters ? ws_ptr<lbm::P4<T>>(h, h->L.m0) : nullptr;
     hipLaunchKernelGGL((lbm::k_moments<D, T, P, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
                        ws_ptr<const P>(h, h->L.f), ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
-                       ws_ptr<lbm::P4<T>>(h, m1_out), grid_of(h), h->tiles, ph);
+                       ws_ptr<lbm::P4<T>>(h, m1_out), m0, grid_of(h), h->tiles, ph);
+}
+
+template <int D, typename T, bool S>
+void launch_picard(const lbm_solver *h, size_t vin, size_t vout) {
+    auto ph = phys_of<T>(h);
+    hipLaunchKernelGGL((lbm::k_picard<D, T, S>), cell_tiles(h), dim3(256), 0, h->stream,
+                       ws_ptr<const lbm::P4<T>>(h, vin), ws_ptr<const lbm::P4<T>>(h, h->L.m0),
+                       ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
+                       ws_ptr<const T>(h, h->L.muF), mask_ptr(h), ws_ptr<lbm::P4<T>>(h, vout),
+                       grid_of(h), h->tiles, ph, (T)h->picard_omega);
 }
 
 template <int D, typename T, bool S>
@@ -201,6 +212,12 @@ struct CollidePass {
     template <int D, typename T, typename P, bool S, int PH>
     void operator()() { launch_collide<D, T, P, S, PH>(h, m2); }
 };
+struct PicardPass {
+    const lbm_solver *h;
+    size_t vin, vout;
+    template <int D, typename T, typename P, bool S, int PH>
+    void operator()() { launch_picard<D, T, S>(h, vin, vout); }
+};
 struct FusedPass {
     const lbm_solver *h;
     int prev, next;
@@ -239,6 +256,20 @@ struct ImportPass {
     }
 };
 
+// Velocity of the two-pass step after the one-shot correction into m2: the boundary records,
+// then the Picard iterations (App. F), each followed by the boundary records again.  Returns
+// the buffer that holds the final (rho, v) records.
+size_t velocity_stage(lbm_solver *h, size_t m1, size_t m2) {
+    if (h->bc_vp) dispatch(h, BcFixPass{h, m1, m2});
+    size_t a = m2, b = h->L.mx;
+    for (int k = 0; k < h->picard_iters; ++k) {
+        dispatch(h, PicardPass{h, a, b});
+        if (h->bc_vp) dispatch(h, BcFixPass{h, m1, b});
+        std::swap(a, b);
+    }
+    return a;
+}
+
 // Moments of the current state into internal packed records; returns the offset of the
 // (rho, v) records.  Under the lagged scheme with a valid history the correction takes its
 // neighbour values from the previous step's records, which stay untouched.
@@ -254,8 +285,7 @@ size_t current_moments(lbm_solver *h) {
     dispatch(h, MomentsPass{h, h->L.m1[c]});
     if (h->bc_vp) dispatch(h, BcRecordsPass{h, h->L.m1[c]});
     dispatch(h, VcorrectPass{h, h->L.m1[c], h->L.m1[c], h->L.m2[c]});
-    if (h->bc_vp) dispatch(h, BcFixPass{h, h->L.m1[c], h->L.m2[c]});
-    return h->L.m2[c];
+    return velocity_stage(h, h->L.m1[c], h->L.m2[c]);
 }
 
 // Enqueue one time step; ev (optional) receives events after each kernel class.
@@ -277,10 +307,10 @@ hipError_t one_step(lbm_solver *h, hipEvent_t *ev) {
         if (h->bc_vp) dispatch(h, BcRecordsPass{h, h->L.m1[c]});
         if (ev) e = hipEventRecord(ev[0], h->stream);
         dispatch(h, VcorrectPass{h, h->L.m1[c], h->L.m1[c], h->L.m2[c]});
-        if (h->bc_vp) dispatch(h, BcFixPass{h, h->L.m1[c], h->L.m2[c]});
+        const size_t mv = velocity_stage(h, h->L.m1[c], h->L.m2[c]);
         if (ev && e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
-        if (h->bc_vp) dispatch(h, BcRebuildPass{h, h->L.m2[c]});
-        dispatch(h, CollidePass{h, h->L.m2[c]});
+        if (h->bc_vp) dispatch(h, BcRebuildPass{h, mv});
+        dispatch(h, CollidePass{h, mv});
         if (ev && e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
         h->have_prev = true;  // this step's records are the next step's history
     }
@@ -309,6 +339,12 @@ int validate_shape(const lbm_params *p, int *D, int *Q, size_t *sp, size_t *s, i
         return fail(LBM_ERR_INVALID_ARG, "shift must be LBM_SHIFT_WEIGHTS or LBM_SHIFT_POROUS, got %d", p->shift);
     if (p->scheme != LBM_SCHEME_TWO_PASS && p->scheme != LBM_SCHEME_LAGGED)
         return fail(LBM_ERR_INVALID_ARG, "scheme must be LBM_SCHEME_TWO_PASS or LBM_SCHEME_LAGGED, got %d", p->scheme);
+    if (p->picard_iters < 0 || p->picard_iters > 64)
+        return fail(LBM_ERR_INVALID_ARG, "picard_iters must be in 0..64, got %d", p->picard_iters);
+    if (p->picard_iters && !(p->picard_omega > 0.0 && p->picard_omega <= 1.0))
+        return fail(LBM_ERR_INVALID_ARG, "picard_omega must be in (0, 1]");
+    if (p->picard_iters && p->scheme != LBM_SCHEME_TWO_PASS)
+        return fail(LBM_ERR_UNSUPPORTED, "Picard iterations need LBM_SCHEME_TWO_PASS");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LBM_ERR_INVALID_ARG, "dimensions must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
     if (*D == 2 && p->nz != 1) return fail(LBM_ERR_INVALID_ARG, "D2Q9 needs nz = 1 (got %d)", p->nz);
@@ -425,7 +461,7 @@ LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes) {
     rc = boundary_nodes(p, D, N, &nb, &bo, &bv);
     if (rc) return rc;
     *workspace_bytes = make_layout(Q, D, (size_t)N, sp, s, p->mask != nullptr,
-                                   p->scheme == LBM_SCHEME_LAGGED, nb).total;
+                                   p->scheme == LBM_SCHEME_LAGGED, nb, p->picard_iters > 0).total;
     return LBM_OK;
 }
 
@@ -473,7 +509,8 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     bool bc_outflow = false, bc_vp = false;
     rc = boundary_nodes(p, D, N, &nb, &bc_outflow, &bc_vp);
     if (rc) return rc;
-    const Layout L = make_layout(Q, D, (size_t)N, sp, s, solids, p->scheme == LBM_SCHEME_LAGGED, nb);
+    const Layout L = make_layout(Q, D, (size_t)N, sp, s, solids, p->scheme == LBM_SCHEME_LAGGED, nb,
+                                 p->picard_iters > 0);
     if (!dev_workspace) return fail(LBM_ERR_INVALID_ARG, "dev_workspace is NULL");
     if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
         return fail(LBM_ERR_WORKSPACE, "dev_workspace must be 256-byte aligned");
@@ -511,6 +548,8 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->bc_vp = bc_vp;
     h->bc_scheme = p->bc_scheme;
     h->bc_rho_rule = p->bc_rho_rule;
+    h->picard_iters = p->picard_iters;
+    h->picard_omega = p->picard_omega;
     for (int a = 0; a < 3; ++a) h->b[a] = a < D ? p->b[a] : 0.0;
 
     auto cleanup = [&](int code) {

@@ -905,7 +905,7 @@ template <int D, typename T, typename E>
 __device__ __forceinline__ Rec<T> cell_moments(const T fi[], const E &ev,
                                                const T *__restrict__ muD,
                                                const T *__restrict__ muF, const Nbr<D> &nb,
-                                               const Phys<T> &ph) {
+                                               const Phys<T> &ph, T *v0_out = nullptr) {
     using L = Lat<D>;
     const uint32_t n = nb.self();
     T S = T(0), Pi[3] = {T(0), T(0), T(0)};
@@ -941,6 +941,10 @@ __device__ __forceinline__ Rec<T> cell_moments(const T fi[], const E &ev,
     for (int a = 0; a < 3; ++a) q.w[a] = T(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) q.w[a] = dv(T(2) * v0[a], den);
+    if (v0_out) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v0_out[a] = a < D ? v0[a] : T(0);
+    }
     return q;
 }
 
@@ -976,7 +980,8 @@ __device__ __forceinline__ void moments_body(const P *__restrict__ f,
                                                  const T *__restrict__ muD,
                                                  const T *__restrict__ muF,
                                                  const uint8_t *__restrict__ mask,
-                                                 P4<T> *__restrict__ m1_out, Grid g, Tiling tl,
+                                                 P4<T> *__restrict__ m1_out,
+                                                 P4<T> *__restrict__ m0_out, Grid g, Tiling tl,
                                                  Phys<T> ph, uint32_t wg) {
     LBM_TILE_PROLOGUE(D, wg, (PopFmt<P>::shifted))
     using L = Lat<D>;
@@ -991,8 +996,10 @@ __device__ __forceinline__ void moments_body(const P *__restrict__ f,
         constexpr int i = decltype(ii)::value;
         fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
     });
-    const Rec<T> q = cell_moments<D>(fi, ev, muD, muF, nb, ph);
+    T v0[3];
+    const Rec<T> q = cell_moments<D>(fi, ev, muD, muF, nb, ph, m0_out ? v0 : nullptr);
     store_rec<D>(m1_out, n, q.r, q.w);
+    if (m0_out) store_rec<D>(m0_out, n, q.r, v0);  // base predictor for the Picard iterations
 }
 
 // Velocity correction (v_final) of every cell: reads the cell's own (rho, v^(1)) record from
@@ -1089,6 +1096,65 @@ __device__ __forceinline__ void fused_body(P *__restrict__ f, const P4<T> *__res
     store_rec<D>(m2n, n, own2.r, own2.w);
 }
 
+// One Picard iteration of the second-order velocity evaluation (App. F):
+//   s = v_0 + Delta_nu(rho v^(k) / eps) / (2 rho),  v^(k+1) = 2 s / (c_1 + sqrt(c_1^2 + 4 c_2 |s|)),
+// under-relaxed by omega when omega != 1; reads the (rho, v^(k)) records of the cell and its
+// neighbours and the cell's (rho, v_0) record, writes (rho, v^(k+1)).
+template <int D, typename T, bool SOLIDS>
+__device__ __forceinline__ void picard_body(const P4<T> *__restrict__ vin,
+                                            const P4<T> *__restrict__ m0,
+                                            const T *__restrict__ eps,
+                                            const T *__restrict__ muD,
+                                            const T *__restrict__ muF,
+                                            const uint8_t *__restrict__ mask,
+                                            P4<T> *__restrict__ vout, Grid g, Tiling tl,
+                                            Phys<T> ph, T omega, uint32_t wg) {
+    LBM_TILE_PROLOGUE(D, wg, false)
+    if constexpr (SOLIDS) {
+        if (mask[n]) {
+            *at(vout, n) = pack(T(0), T(0), T(0), T(0));
+            return;
+        }
+    }
+    const Rec<T> own = load_rec<D>(vin, n, ev.at(0, 0, 0));
+    const CellStatic<D, T> cs = cell_static<D>(ev, ph, own.e);
+    Rec<T> rec[3][2];
+    bool fl[3][2];
+    load_stencil<D, T, SOLIDS>(vin, ev, mask, g, nb, rec, fl);
+    T dn[3];
+    delta_nu<D, T, SOLIDS>(vin, eps, mask, g, nb, own, rec, fl, cs.ge, cs.H, cs.vs, dn);
+    const P4<T> q0 = ld(m0, n);
+    const T v0[3] = {q0.y, q0.z, q0.w};
+    T sv[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) sv[a] = v0[a] + dv(dn[a], T(2) * own.r);
+    const T c1 = T(1) + T(0.5) * ld(muD, n);
+    const T c2 = T(0.5) * ld(muF, n);
+    T s = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) s = s + sv[a] * sv[a];
+    const T den = c1 + sq(c1 * c1 + (T(4) * c2) * sq(s));
+    T v[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const T vk = dv(T(2) * sv[a], den);
+        v[a] = omega == T(1) ? vk : (T(1) - omega) * own.w[a] + omega * vk;
+    }
+    store_rec<D>(vout, n, own.r, v);
+}
+
+template <int D, typename T, bool SOLIDS>
+__global__ __launch_bounds__(256) void k_picard(const P4<T> *__restrict__ vin,
+                                                const P4<T> *__restrict__ m0,
+                                                const T *__restrict__ eps,
+                                                const T *__restrict__ muD,
+                                                const T *__restrict__ muF,
+                                                const uint8_t *__restrict__ mask,
+                                                P4<T> *__restrict__ vout, Grid g, Tiling tl,
+                                                Phys<T> ph, T omega) {
+    picard_body<D, T, SOLIDS>(vin, m0, eps, muD, muF, mask, vout, g, tl, ph, omega, blockIdx.x);
+}
+
 // Single-run kernels: workgroup w handles tile w of the run.
 template <int D, typename T, typename P, bool SOLIDS, int PH>
 __global__ __launch_bounds__(256) void k_moments(const P *__restrict__ f,
@@ -1096,9 +1162,11 @@ __global__ __launch_bounds__(256) void k_moments(const P *__restrict__ f,
                                                  const T *__restrict__ muD,
                                                  const T *__restrict__ muF,
                                                  const uint8_t *__restrict__ mask,
-                                                 P4<T> *__restrict__ m1_out, Grid g, Tiling tl,
+                                                 P4<T> *__restrict__ m1_out,
+                                                 P4<T> *__restrict__ m0_out, Grid g, Tiling tl,
                                                  Phys<T> ph) {
-    moments_body<D, T, P, SOLIDS, PH>(f, eps, muD, muF, mask, m1_out, g, tl, ph, blockIdx.x);
+    moments_body<D, T, P, SOLIDS, PH>(f, eps, muD, muF, mask, m1_out, m0_out, g, tl, ph,
+                                      blockIdx.x);
 }
 
 template <int D, typename T, bool SOLIDS>

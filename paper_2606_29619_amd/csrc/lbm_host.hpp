@@ -48,12 +48,13 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
     size_t f, eps, muD, muF, mask, m1[2], m2[2], vsnap, part, res;
     size_t bcell, bcode, bval;  // boundary-node list (wet-node boundaries)
+    size_t m0, mx;              // (rho, v_0) records and a second velocity buffer (Picard)
     size_t total;
 };
 
 // sp: bytes per population value; s: bytes per value of the static fields and moment records.
 inline Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool solids, bool lagged,
-                          size_t nbnodes = 0) {
+                          size_t nbnodes = 0, bool picard = false) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -79,6 +80,8 @@ inline Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool soli
     L.bcell = nbnodes ? take(nbnodes * sizeof(uint32_t)) : 0;
     L.bcode = nbnodes ? take(nbnodes * sizeof(uint32_t)) : 0;
     L.bval = nbnodes ? take(nbnodes * 4 * s) : 0;
+    L.m0 = picard ? take(4 * N * s) : 0;
+    L.mx = picard ? take(4 * N * s) : 0;
     L.total = off;
     return L;
 }
@@ -106,6 +109,8 @@ struct lbm_solver {
     uint32_t nb;        // boundary nodes
     bool bc_outflow, bc_vp;  // outflow nodes, velocity or pressure nodes present
     int bc_scheme, bc_rho_rule;
+    int picard_iters;
+    double picard_omega;
     lbm::Tiling tiles;  // 256-cell tiles, blocked, in XCD-contiguous ranges
 };
 

@@ -54,8 +54,8 @@ __global__ __launch_bounds__(256) void kb_moments(const RunDesc<T, P> *__restric
                                                   const uint32_t *__restrict__ starts, int nrun) {
     const int r = find_run(starts, nrun, blockIdx.x);
     const RunDesc<T, P> &d = runs[r];
-    moments_body<D, T, P, S, PH>(d.f, d.eps, d.muD, d.muF, d.mask, d.m1[0], d.g, d.tl, d.ph,
-                                 blockIdx.x - starts[r]);
+    moments_body<D, T, P, S, PH>(d.f, d.eps, d.muD, d.muF, d.mask, d.m1[0], nullptr, d.g, d.tl,
+                                 d.ph, blockIdx.x - starts[r]);
 }
 
 template <int D, typename T, typename P, bool S>
@@ -401,8 +401,10 @@ LBM_API int lbm_server_submit(lbm_server *s, const lbm_params *p, double tol, in
     if (!p || !id) return fail(LBM_ERR_INVALID_ARG, "null argument");
     if (!(tol > 0) || max_steps < s->check_every)
         return fail(LBM_ERR_INVALID_ARG, "tol must be > 0 and max_steps >= check_every");
-    if (p->bc_type)
-        return fail(LBM_ERR_UNSUPPORTED, "the server runs periodic / bounce-back runs (no bc_type)");
+    if (p->bc_type || p->picard_iters)
+        return fail(LBM_ERR_UNSUPPORTED,
+                    "the server runs periodic / bounce-back runs with the one-shot velocity "
+                    "(no bc_type, picard_iters = 0)");
     size_t bytes = 0;
     rc = lbm_footprint(p, &bytes);
     if (rc) return rc;

@@ -60,6 +60,8 @@ class Workload:
     bc_density: Optional[np.ndarray] = None
     bc_scheme: int = 1          # 0 equilibrium, 1 NEEM, 2 TMS
     bc_rho_rule: int = 0        # 0 mass continuity, 1 bounce-back
+    picard_iters: int = 0       # second-order velocity evaluation: Picard iterations
+    picard_omega: float = 1.0
 
     @property
     def D(self) -> int:

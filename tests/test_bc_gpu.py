@@ -126,3 +126,43 @@ def test_couette_steady_state_on_gpu():
     ref = ((V0 + V0 * np.exp(rm * H)) * np.exp(rp * y) +
            (-V0 * np.exp(rp * H) - V0) * np.exp(rm * y)) / (np.exp(rp * H) - np.exp(rm * H))
     assert np.abs(v - ref).max() / V0 < 1.2e-2
+
+
+# --------------------------------------------------------------------------------------------
+# Second-order velocity evaluation (App. F)
+# --------------------------------------------------------------------------------------------
+def _oracle_picard(w):
+    return oracle.Oracle(oracle.OracleConfig(
+        D=w.D, eps=w.eps, kappa=w.kappa, cf=w.forch, mask=w.mask, RT=w.RT, nu_f=w.nu_f,
+        nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow, eta_eff=w.eta_eff, b=w.b,
+        rho0=w.rho0, rho_init=w.rho_init, v_init=w.v_init, bc_type=w.bc_type,
+        bc_normal=w.bc_normal, bc_vel=w.bc_velocity, bc_rho=w.bc_density,
+        bc_scheme=w.bc_scheme, bc_density=w.bc_rho_rule, picard_iters=w.picard_iters,
+        picard_omega=w.picard_omega))
+
+
+@pytest.mark.parametrize("case", ["2d_forchheimer", "3d_solids_relaxed", "walls"])
+def test_picard_iterations_match_oracle(case):
+    """Picard iterations after the one-shot correction, FP64: a heterogeneous D2Q9 field with
+    Forchheimer drag (3 iterations), D3Q27 with solid blocks and under-relaxation 0.7 (2
+    iterations), and NEEM walls with gravity (2 iterations, boundary velocity kept)."""
+    if case == "2d_forchheimer":
+        w = workloads.random_porosity_2d(nx=45, ny=33, seed=6, ell=3.0, nu=0.04, b=3e-4)
+        w.picard_iters = 3
+    elif case == "3d_solids_relaxed":
+        w = workloads.random_porosity_3d(shape=(7, 9, 40), seed=7, ell=2.5, nu=0.03, b=2e-4)
+        m = np.zeros(w.shape, np.uint8)
+        m[2:4, 3:6, 10:15] = 1
+        w.mask = m
+        w.picard_iters, w.picard_omega = 2, 0.7
+    else:
+        w = workloads.couette_gravity_2d(H=20)
+        w.picard_iters = 2
+    s = capi.Solver.from_workload(w, storage=capi.LBM_F64)
+    o = _oracle_picard(w)
+    for n in (21, 20):
+        s.step(n)
+        o.step(n)
+    errs = _errors(s, o)
+    print(f"picard {case}:", errs, flush=True)
+    assert max(errs.values()) <= FP64_TOL, errs

@@ -290,3 +290,19 @@ def test_server_rejects_boundary_runs():
         assert ei.value.code == capi.LBM_ERR_UNSUPPORTED
     finally:
         capi.lbm_server_destroy(s)
+
+
+def test_picard_validation_and_footprint():
+    p, _k = _params(shape=(4, 5, 6))
+    base = capi.lbm_footprint(p)
+    p.picard_iters, p.picard_omega = 3, 1.0
+    assert capi.lbm_footprint(p) - base >= 2 * 4 * 120 * 4          # (rho, v_0) + scratch
+    for iters, omega, scheme, code in [(65, 1.0, 0, capi.LBM_ERR_INVALID_ARG),
+                                       (2, 0.0, 0, capi.LBM_ERR_INVALID_ARG),
+                                       (2, 1.5, 0, capi.LBM_ERR_INVALID_ARG),
+                                       (2, 1.0, capi.LBM_SCHEME_LAGGED, capi.LBM_ERR_UNSUPPORTED)]:
+        q, _kk = _params(shape=(4, 5, 6))
+        q.picard_iters, q.picard_omega, q.scheme = iters, omega, scheme
+        with pytest.raises(capi.LbmError) as ei:
+            capi.lbm_footprint(q)
+        assert ei.value.code == code, (iters, omega, scheme)
