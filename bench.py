@@ -56,7 +56,7 @@ def method_bytes_per_cell(Q, D, sp, s, lagged=False):
 def source_hash():
     h = hashlib.sha256()
     for rel in ("paper_2606_29619_amd/csrc/lbm_device.hpp", "paper_2606_29619_amd/csrc/lbm_host.hpp",
-                "paper_2606_29619_amd/csrc/lbm.hip"):
+                "paper_2606_29619_amd/csrc/lbm_launch.hpp", "paper_2606_29619_amd/csrc/lbm.hip"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

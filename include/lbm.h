@@ -167,6 +167,19 @@ typedef struct lbm_params {
                                    scheme only; each is one stencil pass over the moment records
                                    (and, with boundaries, their records fixed again) */
     double picard_omega;        /* under-relaxation omega in (0, 1] of the iterations */
+    /* Analytic porosity derivatives (Sec. 3.5: Delta_nu is best evaluated from analytic
+     * derivatives of eps when eps(x) is known in closed form).  Both NULL: central differences
+     * of eps.  Otherwise both are required, FP64, host memory, read only during lbm_create:
+     *   grad_eps [D][N]         d eps / d x_a, a = x, y (, z);
+     *   hess_eps [D(D+1)/2][N]  the Hessian's upper triangle row by row: xx, xy, yy (D2Q9) or
+     *                           xx, xy, xz, yy, yz, zz (D3Q27).
+     * They replace every derivative of eps in the step (the RT grad eps force of v_(0),
+     * Delta_nu, and the wall-normal gradient at pressure and velocity nodes); values on solid
+     * cells are never read.  They cost D + D(D+1)/2 extra values per cell of workspace and of
+     * traffic in the passes that evaluate Delta_nu.  Only one of the two given, or a value
+     * that is not finite on a fluid cell: LBM_ERR_INVALID_ARG. */
+    const double *grad_eps;
+    const double *hess_eps;
 } lbm_params;
 
 /* Global statistics of the current state, accumulated in FP64 on the device. */
@@ -328,7 +341,9 @@ LBM_API int lbm_server_create(void *dev_pool, size_t pool_bytes, int64_t check_e
  * free them on return.  tol > 0 is the steady-state threshold on the relative L2 change of v
  * over one round; max_steps >= check_every caps the run.  *id receives the request id (ids
  * count from 0 in submission order).  Errors: those of lbm_footprint, LBM_ERR_INVALID_ARG,
- * LBM_ERR_WORKSPACE (the run can never fit in the pool).
+ * LBM_ERR_WORKSPACE (the run can never fit in the pool), LBM_ERR_UNSUPPORTED for runs with
+ * wet-node boundaries (bc_type), Picard iterations or analytic porosity derivatives, which
+ * lbm_create serves one run at a time.
  */
 LBM_API int lbm_server_submit(lbm_server *s, const lbm_params *p, double tol, int64_t max_steps,
                               int64_t *id);

@@ -50,6 +50,7 @@ class _Params(ctypes.Structure):
         ("bc_vel", ctypes.POINTER(ctypes.c_double)), ("bc_rho", ctypes.POINTER(ctypes.c_double)),
         ("bc_scheme", ctypes.c_int), ("bc_density", ctypes.c_int),
         ("picard_iters", ctypes.c_int), ("picard_omega", ctypes.c_double),
+        ("grad_eps", ctypes.POINTER(ctypes.c_double)), ("hess_eps", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -154,6 +155,10 @@ class OracleConfig:
     bc_density: int = 0                    # 0 mass continuity, 1 bounce-back
     picard_iters: int = 0                  # App. F: Picard iterations after the one-shot step
     picard_omega: float = 1.0
+    # analytic porosity derivatives (Sec. 3.5): grad eps [D, nz, ny, nx] and the Hessian's upper
+    # triangle row by row [D(D+1)/2, nz, ny, nx]; None: central differences
+    grad_eps: Optional[np.ndarray] = None
+    hess_eps: Optional[np.ndarray] = None
 
 
 class Oracle:
@@ -211,6 +216,8 @@ class Oracle:
         p.bc_rho = _dp(arr(cfg.bc_rho))
         p.bc_scheme, p.bc_density = cfg.bc_scheme, cfg.bc_density
         p.picard_iters, p.picard_omega = cfg.picard_iters, cfg.picard_omega
+        p.grad_eps = _dp(arr(cfg.grad_eps, (cfg.D,) + self.shape))
+        p.hess_eps = _dp(arr(cfg.hess_eps, (cfg.D * (cfg.D + 1) // 2,) + self.shape))
         err = ctypes.create_string_buffer(256)
         h = lib().orc_create(ctypes.byref(p), err, 256)
         if not h:

@@ -62,6 +62,11 @@ typedef struct {
      * correction (0 = one-shot only) and the under-relaxation factor omega in (0, 1]. */
     int picard_iters;
     double picard_omega;
+    /* Analytic porosity derivatives (Sec. 3.5), both NULL for central differences:
+     * grad_eps [D][N], hess_eps [D(D+1)/2][N] holding the Hessian's upper triangle row by row
+     * (xx, xy, yy in 2D; xx, xy, xz, yy, yz, zz in 3D). */
+    const double *grad_eps;
+    const double *hess_eps;
 } orc_params;
 
 typedef struct {
@@ -240,12 +245,28 @@ static double deriv(const orc_solver *S, const double *g, long n, int a)
     return 0.0;
 }
 
-/* Porosity gradient and Hessian by central differences on the (everywhere defined) eps field. */
+/* Porosity gradient and Hessian.  Sec. 3.5 prefers analytic derivatives of eps where eps(x) is
+ * given in closed form: then they are the caller's.  Otherwise central differences on the
+ * (everywhere defined) eps field. */
 static void porosity_derivatives(orc_solver *S)
 {
     int D = S->D, a, b;
     long n, N = S->N;
     const double *e = S->eps;
+    if (S->p.grad_eps) {
+        for (n = 0; n < N; ++n) {
+            int k = 0;
+            for (a = 0; a < D; ++a) S->ge[a * N + n] = S->p.grad_eps[a * N + n];
+            for (a = 0; a < D; ++a)
+                for (b = a; b < D; ++b) {
+                    double h = S->p.hess_eps[(long)k * N + n];
+                    S->H[(a * D + b) * N + n] = h;
+                    S->H[(b * D + a) * N + n] = h;
+                    k = k + 1;
+                }
+        }
+        return;
+    }
     for (n = 0; n < N; ++n) {
         for (a = 0; a < D; ++a) {
             long p = shift(S, n, a, 1), q = shift(S, n, a, -1);
@@ -356,6 +377,10 @@ orc_solver *orc_create(const orc_params *p, char *err, int errlen)
         snprintf(err, (size_t)errlen, "bad physical parameters or missing fields");
         return NULL;
     }
+    if ((p->grad_eps == NULL) != (p->hess_eps == NULL)) {
+        snprintf(err, (size_t)errlen, "grad_eps and hess_eps go together");
+        return NULL;
+    }
     S = (orc_solver *)xcalloc(1, sizeof(orc_solver));
     S->p = *p;
     S->D = D;
@@ -435,6 +460,8 @@ orc_solver *orc_create(const orc_params *p, char *err, int errlen)
             if (p->bc_type[n]) S->bnodes[k++] = n;
     }
     porosity_derivatives(S);
+    S->p.grad_eps = NULL;   /* the caller's arrays are read only here */
+    S->p.hess_eps = NULL;
     init_populations(S);
     return S;
 }

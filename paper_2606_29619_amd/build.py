@@ -1,12 +1,13 @@
-"""Build step of the HIP library: hipcc for gfx950 over the solver and the request-server
-sources (compiled in parallel, then linked), in-tree output."""
+"""Build step of the HIP library: hipcc for gfx950 over the solver (differenced and analytic
+porosity-derivative halves) and the request-server sources, compiled in parallel and then
+linked; in-tree output."""
 import os
 import subprocess
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRCS = [os.path.join(PKG, "csrc", f) for f in ("lbm.hip", "lbm_server.hip")]
+SRCS = [os.path.join(PKG, "csrc", f) for f in ("lbm.hip", "lbm_analytic.hip", "lbm_server.hip")]
 LIB = os.path.join(PKG, "liblbm.so")
 
 HIPCC_FLAGS = [

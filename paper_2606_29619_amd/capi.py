@@ -61,6 +61,7 @@ class lbm_params(ctypes.Structure):
         ("bc_velocity", _dp), ("bc_density", _dp),
         ("bc_scheme", ctypes.c_int), ("bc_rho_rule", ctypes.c_int),
         ("picard_iters", ctypes.c_int), ("picard_omega", ctypes.c_double),
+        ("grad_eps", _dp), ("hess_eps", _dp),
     ]
 
 
@@ -288,8 +289,11 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
                 bc_velocity: Optional[np.ndarray] = None,
                 bc_density: Optional[np.ndarray] = None, bc_scheme: int = LBM_BC_NEEM,
                 bc_rho_rule: int = LBM_BC_RHO_CONTINUITY, picard_iters: int = 0,
-                picard_omega: float = 1.0):
-    """Build an lbm_params from numpy arrays shaped [nz, ny, nx]; returns (params, keepalive)."""
+                picard_omega: float = 1.0, grad_eps: Optional[np.ndarray] = None,
+                hess_eps: Optional[np.ndarray] = None):
+    """Build an lbm_params from numpy arrays shaped [nz, ny, nx]; returns (params, keepalive).
+    grad_eps [D][nz, ny, nx] and hess_eps [D(D+1)/2][nz, ny, nx] (upper triangle row by row)
+    are the optional analytic porosity derivatives."""
     eps = np.ascontiguousarray(eps, dtype=np.float64)
     if eps.ndim == 2:
         eps = eps[None]
@@ -333,6 +337,8 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
     p.bc_density = arr(bc_density, eps.shape)
     p.bc_scheme, p.bc_rho_rule = bc_scheme, bc_rho_rule
     p.picard_iters, p.picard_omega = picard_iters, picard_omega
+    p.grad_eps = arr(grad_eps, (D,) + eps.shape)
+    p.hess_eps = arr(hess_eps, (D * (D + 1) // 2,) + eps.shape)
     return p, keep
 
 
@@ -375,7 +381,9 @@ class Solver:
                               bc_scheme=getattr(w, "bc_scheme", LBM_BC_NEEM),
                               bc_rho_rule=getattr(w, "bc_rho_rule", LBM_BC_RHO_CONTINUITY),
                               picard_iters=getattr(w, "picard_iters", 0),
-                              picard_omega=getattr(w, "picard_omega", 1.0))
+                              picard_omega=getattr(w, "picard_omega", 1.0),
+                              grad_eps=getattr(w, "grad_eps", None),
+                              hess_eps=getattr(w, "hess_eps", None))
         return cls(p, keep, **kw)
 
     def close(self):

@@ -19,242 +19,9 @@
 #include "lbm_bc.hpp"
 #include "lbm_device.hpp"
 #include "lbm_host.hpp"
+#include "lbm_launch.hpp"
 
 namespace lbmh {
-
-// ---- kernel launchers, dispatched on (lattice, arithmetic type T, population storage type P,
-// solids, phase) ------------------------------------------------------------------------------
-template <int D, typename T, typename P, bool S, int PH>
-void launch_moments(const lbm_solver *h, size_t m1_out) {
-    auto ph = phys_of<T>(h);
-    lbm::P4<T> *m0 = h->picard_iters ? ws_ptr<lbm::P4<T>>(h, h->L.m0) : nullptr;
-    hipLaunchKernelGGL((lbm::k_moments<D, T, P, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<const P>(h, h->L.f), ws_ptr<const T>(h, h->L.eps),
-                       ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
-                       ws_ptr<lbm::P4<T>>(h, m1_out), m0, grid_of(h), h->tiles, ph);
-}
-
-template <int D, typename T, bool S>
-void launch_picard(const lbm_solver *h, size_t vin, size_t vout) {
-    auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_picard<D, T, S>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<const lbm::P4<T>>(h, vin), ws_ptr<const lbm::P4<T>>(h, h->L.m0),
-                       ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
-                       ws_ptr<const T>(h, h->L.muF), mask_ptr(h), ws_ptr<lbm::P4<T>>(h, vout),
-                       grid_of(h), h->tiles, ph, (T)h->picard_omega);
-}
-
-template <int D, typename T, bool S>
-void launch_vcorrect(const lbm_solver *h, size_t own_src, size_t m1, size_t m2_out) {
-    auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_vcorrect<D, T, S>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<const lbm::P4<T>>(h, own_src), ws_ptr<const lbm::P4<T>>(h, m1),
-                       ws_ptr<const T>(h, h->L.eps), mask_ptr(h), ws_ptr<lbm::P4<T>>(h, m2_out),
-                       grid_of(h), h->tiles, ph);
-}
-
-template <int D, typename T, typename P, bool S, int PH>
-void launch_collide(const lbm_solver *h, size_t m2) {
-    auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_collide<D, T, P, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
-                       ws_ptr<const T>(h, h->L.eps),
-                       ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
-                       grid_of(h), h->tiles, ph);
-}
-
-template <int D, typename T, typename P, bool S, int PH>
-void launch_fused(const lbm_solver *h, int prev, int next) {
-    auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_fused<D, T, P, S, PH>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m1[prev]),
-                       ws_ptr<const lbm::P4<T>>(h, h->L.m2[prev]),
-                       ws_ptr<lbm::P4<T>>(h, h->L.m1[next]), ws_ptr<lbm::P4<T>>(h, h->L.m2[next]),
-                       ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
-                       ws_ptr<const T>(h, h->L.muF), mask_ptr(h), grid_of(h), h->tiles, ph);
-}
-
-template <int D, typename T, typename P, bool S>
-void launch_init(const lbm_solver *h) {
-    auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_init<D, T, P, S>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m2[0]),
-                       ws_ptr<const T>(h, h->L.eps),
-                       ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
-                       grid_of(h), h->tiles, ph);
-}
-
-template <int D, typename T, typename P, bool S, int PH, typename O>
-void launch_export(const lbm_solver *h, O *out) {
-    hipLaunchKernelGGL((lbm::k_export<D, T, P, S, PH, O>), cell_tiles(h), dim3(256), 0,
-                       h->stream, ws_ptr<const P>(h, h->L.f), mask_ptr(h),
-                       ws_ptr<const T>(h, h->L.eps), out, grid_of(h), h->tiles, phys_of<T>(h));
-}
-
-template <int D, typename T, typename P, bool S, typename I>
-void launch_import(const lbm_solver *h, const I *in) {
-    hipLaunchKernelGGL((lbm::k_import<D, T, P, S, I>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<P>(h, h->L.f), in, mask_ptr(h), ws_ptr<const T>(h, h->L.eps),
-                       grid_of(h), h->tiles, phys_of<T>(h));
-}
-
-// Statistics blocks: one per 256 cells up to kStatsBlocks (grid-stride beyond).
-int stats_blocks(const lbm_solver *h) {
-    return (int)std::min<int64_t>(lbm::kStatsBlocks, (h->N + 255) / 256);
-}
-
-template <int D, typename T, typename P, bool S, int PH>
-void launch_stats(const lbm_solver *h, size_t m2) {
-    hipLaunchKernelGGL((lbm::k_stats<D, T, P, S, PH>), dim3(stats_blocks(h)), dim3(256), 0,
-                       h->stream, ws_ptr<const P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
-                       ws_ptr<T>(h, h->L.vsnap), mask_ptr(h), ws_ptr<const T>(h, h->L.eps),
-                       ws_ptr<double>(h, h->L.part), grid_of(h), phys_of<T>(h));
-}
-
-// ---- wet-node boundary kernels (one thread per boundary node; boundaries imply solids) -----
-template <typename T>
-lbm::BNodes<T> bnodes_of(const lbm_solver *h) {
-    return lbm::BNodes<T>{ws_ptr<const uint32_t>(h, h->L.bcell), ws_ptr<const uint32_t>(h, h->L.bcode),
-                          ws_ptr<const lbm::P4<T>>(h, h->L.bval), h->nb};
-}
-
-struct BcOutflowPass {
-    const lbm_solver *h;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() {
-        if constexpr (S)
-            hipLaunchKernelGGL((lbm::k_bc_outflow<D, T, P, S, PH>), flat_grid(h->nb), dim3(256), 0,
-                               h->stream, ws_ptr<P>(h, h->L.f), mask_ptr(h),
-                               ws_ptr<const T>(h, h->L.eps), bnodes_of<T>(h), grid_of(h),
-                               phys_of<T>(h));
-    }
-};
-struct BcRecordsPass {
-    const lbm_solver *h;
-    size_t m1;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() {
-        if constexpr (S)
-            hipLaunchKernelGGL((lbm::k_bc_records<D, T, P, S, PH>), flat_grid(h->nb), dim3(256), 0,
-                               h->stream, ws_ptr<const P>(h, h->L.f), mask_ptr(h),
-                               ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
-                               ws_ptr<const T>(h, h->L.muF), ws_ptr<lbm::P4<T>>(h, m1),
-                               bnodes_of<T>(h), grid_of(h), phys_of<T>(h),
-                               h->bc_rho_rule == LBM_BC_RHO_BOUNCE_BACK ? 1 : 0);
-    }
-};
-struct BcFixPass {
-    const lbm_solver *h;
-    size_t m1, m2;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() {
-        if constexpr (S)
-            hipLaunchKernelGGL((lbm::k_bc_fix<T>), flat_grid(h->nb), dim3(256), 0, h->stream,
-                               ws_ptr<const lbm::P4<T>>(h, m1), ws_ptr<lbm::P4<T>>(h, m2),
-                               bnodes_of<T>(h));
-    }
-};
-struct BcRebuildPass {
-    const lbm_solver *h;
-    size_t m2;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() {
-        if constexpr (S)
-            hipLaunchKernelGGL((lbm::k_bc_rebuild<D, T, P, S, PH>), flat_grid(h->nb), dim3(256), 0,
-                               h->stream, ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
-                               ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
-                               ws_ptr<const T>(h, h->L.muF), mask_ptr(h), bnodes_of<T>(h),
-                               grid_of(h), phys_of<T>(h), h->bc_scheme);
-    }
-};
-
-// Calls fn.template operator()<D, T, P, S, PH>() for the handle's configuration.
-template <typename F>
-void dispatch(const lbm_solver *h, F &&fn) {
-    const bool s = h->solids;
-    const int ph = h->phase;
-#define LBM_DISPATCH_T(DD, TT, PP)                                   \
-    if (s) {                                                         \
-        if (ph) fn.template operator()<DD, TT, PP, true, 1>();       \
-        else fn.template operator()<DD, TT, PP, true, 0>();          \
-    } else {                                                         \
-        if (ph) fn.template operator()<DD, TT, PP, false, 1>();      \
-        else fn.template operator()<DD, TT, PP, false, 0>();         \
-    }
-#define LBM_DISPATCH_D(DD)                                                        \
-    switch (h->storage) {                                                         \
-    case LBM_F64: { LBM_DISPATCH_T(DD, double, double) } break;                   \
-    case LBM_F32: { LBM_DISPATCH_T(DD, float, float) } break;                     \
-    case LBM_F16_SHIFTED: { LBM_DISPATCH_T(DD, float, _Float16) } break;          \
-    default: { LBM_DISPATCH_T(DD, float, __bf16) } break;                         \
-    }
-    if (h->D == 2) { LBM_DISPATCH_D(2) }
-    else { LBM_DISPATCH_D(3) }
-#undef LBM_DISPATCH_D
-#undef LBM_DISPATCH_T
-}
-
-struct MomentsPass {
-    const lbm_solver *h;
-    size_t m1_out;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() { launch_moments<D, T, P, S, PH>(h, m1_out); }
-};
-struct VcorrectPass {
-    const lbm_solver *h;
-    size_t own_src, m1, m2_out;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() { launch_vcorrect<D, T, S>(h, own_src, m1, m2_out); }
-};
-struct CollidePass {
-    const lbm_solver *h;
-    size_t m2;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() { launch_collide<D, T, P, S, PH>(h, m2); }
-};
-struct PicardPass {
-    const lbm_solver *h;
-    size_t vin, vout;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() { launch_picard<D, T, S>(h, vin, vout); }
-};
-struct FusedPass {
-    const lbm_solver *h;
-    int prev, next;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() { launch_fused<D, T, P, S, PH>(h, prev, next); }
-};
-struct InitPass {
-    const lbm_solver *h;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() { launch_init<D, T, P, S>(h); }
-};
-struct StatsPass {
-    const lbm_solver *h;
-    size_t m2;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() { launch_stats<D, T, P, S, PH>(h, m2); }
-};
-struct ExportPass {
-    const lbm_solver *h;
-    void *out;
-    int dtype;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() {
-        if (dtype == LBM_DTYPE_F64) launch_export<D, T, P, S, PH, double>(h, (double *)out);
-        else launch_export<D, T, P, S, PH, float>(h, (float *)out);
-    }
-};
-struct ImportPass {
-    const lbm_solver *h;
-    const void *in;
-    int dtype;
-    template <int D, typename T, typename P, bool S, int PH>
-    void operator()() {
-        if (dtype == LBM_DTYPE_F64) launch_import<D, T, P, S, double>(h, (const double *)in);
-        else launch_import<D, T, P, S, float>(h, (const float *)in);
-    }
-};
 
 // Velocity of the two-pass step after the one-shot correction into m2: the boundary records,
 // then the Picard iterations (App. F), each followed by the boundary records again.  Returns
@@ -345,6 +112,8 @@ int validate_shape(const lbm_params *p, int *D, int *Q, size_t *sp, size_t *s, i
         return fail(LBM_ERR_INVALID_ARG, "picard_omega must be in (0, 1]");
     if (p->picard_iters && p->scheme != LBM_SCHEME_TWO_PASS)
         return fail(LBM_ERR_UNSUPPORTED, "Picard iterations need LBM_SCHEME_TWO_PASS");
+    if ((p->grad_eps == nullptr) != (p->hess_eps == nullptr))
+        return fail(LBM_ERR_INVALID_ARG, "grad_eps and hess_eps go together (both or neither)");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LBM_ERR_INVALID_ARG, "dimensions must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
     if (*D == 2 && p->nz != 1) return fail(LBM_ERR_INVALID_ARG, "D2Q9 needs nz = 1 (got %d)", p->nz);
@@ -461,7 +230,8 @@ LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes) {
     rc = boundary_nodes(p, D, N, &nb, &bo, &bv);
     if (rc) return rc;
     *workspace_bytes = make_layout(Q, D, (size_t)N, sp, s, p->mask != nullptr,
-                                   p->scheme == LBM_SCHEME_LAGGED, nb, p->picard_iters > 0).total;
+                                   p->scheme == LBM_SCHEME_LAGGED, nb, p->picard_iters > 0,
+                                   p->grad_eps != nullptr).total;
     return LBM_OK;
 }
 
@@ -502,6 +272,14 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
             for (int a = 0; a < D; ++a)
                 if (!is_finite(p->v_init[(int64_t)a * N + n]))
                     return fail(LBM_ERR_INVALID_ARG, "v_init must be finite");
+        if (p->grad_eps) {
+            for (int a = 0; a < D; ++a)
+                if (!is_finite(p->grad_eps[(int64_t)a * N + n]))
+                    return fail(LBM_ERR_INVALID_ARG, "grad_eps must be finite on fluid cells");
+            for (int j = 0; j < D * (D + 1) / 2; ++j)
+                if (!is_finite(p->hess_eps[(int64_t)j * N + n]))
+                    return fail(LBM_ERR_INVALID_ARG, "hess_eps must be finite on fluid cells");
+        }
     }
     if (!any_fluid) return fail(LBM_ERR_INVALID_ARG, "no fluid cell");
     const bool solids = p->mask != nullptr;
@@ -510,7 +288,7 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     rc = boundary_nodes(p, D, N, &nb, &bc_outflow, &bc_vp);
     if (rc) return rc;
     const Layout L = make_layout(Q, D, (size_t)N, sp, s, solids, p->scheme == LBM_SCHEME_LAGGED, nb,
-                                 p->picard_iters > 0);
+                                 p->picard_iters > 0, p->grad_eps != nullptr);
     if (!dev_workspace) return fail(LBM_ERR_INVALID_ARG, "dev_workspace is NULL");
     if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
         return fail(LBM_ERR_WORKSPACE, "dev_workspace must be 256-byte aligned");
@@ -550,6 +328,7 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->bc_rho_rule = p->bc_rho_rule;
     h->picard_iters = p->picard_iters;
     h->picard_omega = p->picard_omega;
+    h->analytic = p->grad_eps != nullptr;
     for (int a = 0; a < 3; ++a) h->b[a] = a < D ? p->b[a] : 0.0;
 
     auto cleanup = [&](int code) {
@@ -614,6 +393,26 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
             (e = hipMemcpyAsync(h->ws + L.bcode, bcode.data(), nb * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
             (e = hipMemcpyAsync(h->ws + L.bval, bval.data(), bval.size(), hipMemcpyHostToDevice, h->stream)) != hipSuccess)
             return cleanup(fail(LBM_ERR_HIP, "upload of boundary nodes failed: %s", hipGetErrorString(e)));
+    }
+    // analytic porosity derivatives, converted to the value type on the host (solid cells: 0)
+    std::vector<char> dbuf;
+    if (h->analytic) {
+        const int K = D + D * (D + 1) / 2;
+        dbuf.resize((size_t)K * N * s);
+        for (int j = 0; j < K; ++j) {
+            const double *src = j < D ? p->grad_eps + (int64_t)j * N : p->hess_eps + (int64_t)(j - D) * N;
+            for (int64_t n = 0; n < N; ++n) {
+                const double v = (p->mask && p->mask[n]) ? 0.0 : src[n];
+                char *dst = dbuf.data() + ((size_t)j * N + n) * s;
+                if (s == 8) std::memcpy(dst, &v, 8);
+                else {
+                    const float x = (float)v;
+                    std::memcpy(dst, &x, 4);
+                }
+            }
+        }
+        if ((e = hipMemcpyAsync(h->ws + L.deps, dbuf.data(), dbuf.size(), hipMemcpyHostToDevice, h->stream)) != hipSuccess)
+            return cleanup(fail(LBM_ERR_HIP, "upload of porosity derivatives failed: %s", hipGetErrorString(e)));
     }
     const uint8_t *mk = mask_ptr(h);
     const bool lag = p->scheme == LBM_SCHEME_LAGGED;

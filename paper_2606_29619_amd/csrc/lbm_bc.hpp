@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_bc_outflow(P *__restrict__ f,
 //     accel_approx_boundary without its viscous term), or the bounce-back density;
 //   pressure node: v_perp (1 + mu_D / 2) + (mu_F / 2) |v_perp| v_perp = R,
 //     R = (S0 + 2 S+) / rho_b - eps_b + (eps_b b_perp + RT d(eps)/dn) / 2, closed form as v_(1).
-template <int D, typename T, typename P, bool SOLIDS, int PH>
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
 __global__ __launch_bounds__(256) void k_bc_records(const P *__restrict__ f,
                                                     const uint8_t *__restrict__ mask,
                                                     const T *__restrict__ eps,
@@ -145,7 +145,10 @@ __global__ __launch_bounds__(256) void k_bc_records(const P *__restrict__ f,
     const T sgn = (code >> 8) & 1u ? T(1) : T(-1);
     const T e = ev.at(0, 0, 0);
     const int ox = ax == 0, oy = ax == 1, oz = ax == 2;
-    const T gperp = sgn * ((ev.at(ox, oy, oz) - ev.at(-ox, -oy, -oz)) * T(0.5));
+    T gax;
+    if constexpr (AD) gax = ld(plane(ph.deps, ax, ph.dN), n);
+    else gax = (ev.at(ox, oy, oz) - ev.at(-ox, -oy, -oz)) * T(0.5);
+    const T gperp = sgn * gax;
     const T bperp = sgn * ph.b[ax];
     const P4<T> pv = bn.val[k];
     T vb[3] = {pv.x, pv.y, pv.z};
@@ -200,7 +203,7 @@ __device__ __forceinline__ void eq_at(T e, T rho, const T w[3], T RT, ProductFor
 }
 
 // Acceleration of cell nb from the (rho, v) records.
-template <int D, typename T, bool SOLIDS>
+template <int D, typename T, bool SOLIDS, bool AD>
 __device__ __forceinline__ void node_accel(const P4<T> *__restrict__ m2,
                                            const T *__restrict__ eps, const T *__restrict__ muD,
                                            const T *__restrict__ muF,
@@ -209,7 +212,7 @@ __device__ __forceinline__ void node_accel(const P4<T> *__restrict__ m2,
                                            const EpsGlobal<D, T> &ev, Rec<T> &own, Visc<T> &vs,
                                            T acc[3]) {
     own = load_rec<D>(m2, nb.self(), ev.at(0, 0, 0));
-    const CellStatic<D, T> cs = cell_static<D>(ev, ph, own.e);
+    const CellStatic<D, T> cs = cell_static<D, AD>(ev, ph, nb.self(), own.e);
     vs = cs.vs;
     Rec<T> rec[3][2];
     bool fl[3][2];
@@ -224,7 +227,7 @@ __device__ __forceinline__ void node_accel(const P4<T> *__restrict__ m2,
 //   scheme 1, eqs. (NEEM_bc_f_bar), (zeta_beta_NEEM):
 //     f_i = zeta f_i(x_f) + (3/2)[f^tgt_i - zeta f^eq_i(x_f)] + (1/2)[zeta f^*_i(x_f) - f^*_i];
 //   scheme 2, TMS (Sec. 3.4.4, steps 1-3).
-template <int D, typename T, typename P, bool SOLIDS, int PH>
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
 __global__ __launch_bounds__(256) void k_bc_rebuild(P *__restrict__ f,
                                                     const P4<T> *__restrict__ m2,
                                                     const T *__restrict__ eps,
@@ -249,7 +252,7 @@ __global__ __launch_bounds__(256) void k_bc_rebuild(P *__restrict__ f,
     Rec<T> own;
     Visc<T> vs;
     T acc[3];
-    node_accel<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, ev, own, vs, acc);
+    node_accel<D, T, SOLIDS, AD>(m2, eps, muD, muF, mask, g, ph, nb, ev, own, vs, acc);
     T vstar[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int a = 0; a < D; ++a) vstar[a] = own.w[a] + acc[a];
@@ -269,7 +272,7 @@ __global__ __launch_bounds__(256) void k_bc_rebuild(P *__restrict__ f,
         Rec<T> ownf;
         Visc<T> vsf;
         T accf[3];
-        node_accel<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nf, evf, ownf, vsf, accf);
+        node_accel<D, T, SOLIDS, AD>(m2, eps, muD, muF, mask, g, ph, nf, evf, ownf, vsf, accf);
         T vfs[3] = {T(0), T(0), T(0)};
 #pragma unroll
         for (int a = 0; a < D; ++a) vfs[a] = ownf.w[a] + accf[a];

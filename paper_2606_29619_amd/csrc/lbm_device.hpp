@@ -88,7 +88,16 @@ struct Phys {
     int nu_pow;    // -1, 0, 1
     int eta_on;    // Phi^eta switched on
     int shift_porous;  // 16-bit shift base rho0 eps(src) (1) or rho0 (0)
+    const T *deps;     // analytic porosity derivatives: planes of dN values, grad eps (D planes)
+                       // then the Hessian's upper triangle row by row; null: central differences
+    uint32_t dN;       // plane stride of deps (cells)
 };
+
+// Plane of the Hessian entry (a, b), a <= b, among the analytic derivative planes.
+template <int D>
+constexpr int hess_plane(int a, int b) {
+    return D + a * D - a * (a - 1) / 2 + (b - a);
+}
 
 // ---- arithmetic policy -------------------------------------------------------------------
 __device__ __forceinline__ double dv(double a, double b) { return a / b; }
@@ -455,10 +464,38 @@ __device__ __forceinline__ Visc<T> viscosity(const Phys<T> &ph, T e) {
     return r;
 }
 
-// Porosity gradient and Hessian by central differences (eps is defined on every cell); the
-// mixed derivatives come from the four diagonal neighbours, computed once for a < b.
-template <int D, typename T, typename E>
-__device__ __forceinline__ void porosity_derivatives(const E &ev, T e0, T ge[3], T H[3][3]) {
+// Component A of grad eps at cell n: the analytic input (AD) or the central difference.
+// The choice is a template parameter: a run-time branch here costs the differenced kernels
+// their register allocation (arrays of the stencil work spill to scratch).
+template <int A, bool AD, typename T, typename E>
+__device__ __forceinline__ T eps_gradient(const E &ev, const Phys<T> &ph, uint32_t n) {
+    if constexpr (AD) {
+        return ld(plane(ph.deps, A, ph.dN), n);
+    } else {
+        constexpr int px = A == 0, py = A == 1, pz = A == 2;
+        return (ev.at(px, py, pz) - ev.at(-px, -py, -pz)) * T(0.5);
+    }
+}
+
+// Porosity gradient and Hessian of cell n: the analytic inputs (AD), else central differences
+// (eps is defined on every cell), the mixed derivatives from the four diagonal neighbours,
+// computed once for a < b.
+template <int D, bool AD, typename T, typename E>
+__device__ __forceinline__ void porosity_derivatives(const E &ev, const Phys<T> &ph, uint32_t n,
+                                                     T e0, T ge[3], T H[3][3]) {
+    if constexpr (AD) {
+        unroll<0, D>([&](auto ia) {
+            constexpr int a = decltype(ia)::value;
+            ge[a] = ld(plane(ph.deps, a, ph.dN), n);
+            unroll<a, D>([&](auto ib) {
+                constexpr int b = decltype(ib)::value;
+                const T h = ld(plane(ph.deps, hess_plane<D>(a, b), ph.dN), n);
+                H[a][b] = h;
+                H[b][a] = h;
+            });
+        });
+        return;
+    }
     unroll<0, D>([&](auto ia) {
         constexpr int a = decltype(ia)::value;
         constexpr int px = a == 0, py = a == 1, pz = a == 2;
@@ -773,10 +810,11 @@ struct CellStatic {
     Visc<T> vs;
 };
 
-template <int D, typename T, typename E>
-__device__ __forceinline__ CellStatic<D, T> cell_static(const E &ev, const Phys<T> &ph, T e0) {
+template <int D, bool AD, typename T, typename E>
+__device__ __forceinline__ CellStatic<D, T> cell_static(const E &ev, const Phys<T> &ph,
+                                                        uint32_t n, T e0) {
     CellStatic<D, T> c;
-    porosity_derivatives<D>(ev, e0, c.ge, c.H);
+    porosity_derivatives<D, AD>(ev, ph, n, e0, c.ge, c.H);
     c.vs = viscosity(ph, e0);
     return c;
 }
@@ -901,7 +939,7 @@ __device__ __forceinline__ auto make_eps_view(const T *eps, const Nbr<D> *nb, co
 // Density (transformed_density_moment), transformed momentum (transformed_momentum_moment),
 // v^(0) (v_(0)) and the closed-form drag solve v^(1) (v_(1), velocity_coefficients) of a cell
 // from its populations fi: returns the record (rho, eps, v^(1)).
-template <int D, typename T, typename E>
+template <int D, bool AD, typename T, typename E>
 __device__ __forceinline__ Rec<T> cell_moments(const T fi[], const E &ev,
                                                const T *__restrict__ muD,
                                                const T *__restrict__ muF, const Nbr<D> &nb,
@@ -923,8 +961,7 @@ __device__ __forceinline__ Rec<T> cell_moments(const T fi[], const E &ev,
     T v0[3];
     unroll<0, D>([&](auto ia) {
         constexpr int a = decltype(ia)::value;
-        constexpr int px = a == 0, py = a == 1, pz = a == 2;
-        const T ge = (ev.at(px, py, pz) - ev.at(-px, -py, -pz)) * T(0.5);
+        const T ge = eps_gradient<a, AD>(ev, ph, n);
         v0[a] = dv(Pi[a], rho) + T(0.5) * (e * ph.b[a] + ph.RT * ge);
     });
     const T c1 = T(1) + T(0.5) * ld(muD, n);
@@ -974,7 +1011,7 @@ __device__ __forceinline__ void collide_stream(P *__restrict__ f,
 }
 
 // Pass one of the two-pass scheme: the record (rho, v^(1)) of every cell.
-template <int D, typename T, typename P, bool SOLIDS, int PH>
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
 __device__ __forceinline__ void moments_body(const P *__restrict__ f,
                                                  const T *__restrict__ eps,
                                                  const T *__restrict__ muD,
@@ -997,7 +1034,7 @@ __device__ __forceinline__ void moments_body(const P *__restrict__ f,
         fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
     });
     T v0[3];
-    const Rec<T> q = cell_moments<D>(fi, ev, muD, muF, nb, ph, m0_out ? v0 : nullptr);
+    const Rec<T> q = cell_moments<D, AD>(fi, ev, muD, muF, nb, ph, m0_out ? v0 : nullptr);
     store_rec<D>(m1_out, n, q.r, q.w);
     if (m0_out) store_rec<D>(m0_out, n, q.r, v0);  // base predictor for the Picard iterations
 }
@@ -1005,7 +1042,7 @@ __device__ __forceinline__ void moments_body(const P *__restrict__ f,
 // Velocity correction (v_final) of every cell: reads the cell's own (rho, v^(1)) record from
 // `own_src` and the neighbour records from `m1` (the same buffer in the two-pass scheme; the
 // previous step's records when the lagged scheme reports moments), writes (rho, v).
-template <int D, typename T, bool SOLIDS>
+template <int D, typename T, bool SOLIDS, bool AD>
 __device__ __forceinline__ void vcorrect_body(const P4<T> *__restrict__ own_src,
                                                   const P4<T> *__restrict__ m1,
                                                   const T *__restrict__ eps,
@@ -1020,14 +1057,14 @@ __device__ __forceinline__ void vcorrect_body(const P4<T> *__restrict__ own_src,
         }
     }
     const Rec<T> own = load_rec<D>(own_src, n, ev.at(0, 0, 0));
-    const CellStatic<D, T> cs = cell_static<D>(ev, ph, own.e);
+    const CellStatic<D, T> cs = cell_static<D, AD>(ev, ph, n, own.e);
     T v[3];
     corrected_velocity<D, T, SOLIDS>(m1, ev, eps, mask, g, nb, own, cs, v);
     store_rec<D>(m2_out, n, own.r, v);
 }
 
 // Pass two of the two-pass scheme: forcing from the (rho, v) records, collision, streaming.
-template <int D, typename T, typename P, bool SOLIDS, int PH>
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
 __device__ __forceinline__ void collide_body(P *__restrict__ f,
                                                  const P4<T> *__restrict__ m2,
                                                  const T *__restrict__ eps,
@@ -1041,7 +1078,7 @@ __device__ __forceinline__ void collide_body(P *__restrict__ f,
         if (mask[n]) return;
     }
     const Rec<T> own = load_rec<D>(m2, n, ev.at(0, 0, 0));
-    const CellStatic<D, T> cs = cell_static<D>(ev, ph, own.e);
+    const CellStatic<D, T> cs = cell_static<D, AD>(ev, ph, n, own.e);
     ProductForm<D, T> peq, pst;
     cell_equilibria<D, T, SOLIDS>(m2, ev, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
     // The populations are loaded only now, after the forcing arguments: fewer registers are
@@ -1061,7 +1098,7 @@ __device__ __forceinline__ void collide_body(P *__restrict__ f,
 // Phi^eta are the previous step's records (m1p: rho, v^(1); m2p: rho, v).  The cell's new
 // records go to m1n / m2n for the next step.  A steady state of this scheme is a steady state
 // of the two-pass scheme.
-template <int D, typename T, typename P, bool SOLIDS, int PH>
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
 __device__ __forceinline__ void fused_body(P *__restrict__ f, const P4<T> *__restrict__ m1p,
                                                const P4<T> *__restrict__ m2p,
                                                P4<T> *__restrict__ m1n, P4<T> *__restrict__ m2n,
@@ -1084,8 +1121,8 @@ __device__ __forceinline__ void fused_body(P *__restrict__ f, const P4<T> *__res
         constexpr int i = decltype(ii)::value;
         fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
     });
-    const Rec<T> own1 = cell_moments<D>(fi, ev, muD, muF, nb, ph);
-    const CellStatic<D, T> cs = cell_static<D>(ev, ph, own1.e);
+    const Rec<T> own1 = cell_moments<D, AD>(fi, ev, muD, muF, nb, ph);
+    const CellStatic<D, T> cs = cell_static<D, AD>(ev, ph, n, own1.e);
     Rec<T> own2 = own1;
     corrected_velocity<D, T, SOLIDS>(m1p, ev, eps, mask, g, nb, own1, cs, own2.w);
     ProductForm<D, T> peq, pst;
@@ -1100,7 +1137,7 @@ __device__ __forceinline__ void fused_body(P *__restrict__ f, const P4<T> *__res
 //   s = v_0 + Delta_nu(rho v^(k) / eps) / (2 rho),  v^(k+1) = 2 s / (c_1 + sqrt(c_1^2 + 4 c_2 |s|)),
 // under-relaxed by omega when omega != 1; reads the (rho, v^(k)) records of the cell and its
 // neighbours and the cell's (rho, v_0) record, writes (rho, v^(k+1)).
-template <int D, typename T, bool SOLIDS>
+template <int D, typename T, bool SOLIDS, bool AD>
 __device__ __forceinline__ void picard_body(const P4<T> *__restrict__ vin,
                                             const P4<T> *__restrict__ m0,
                                             const T *__restrict__ eps,
@@ -1117,7 +1154,7 @@ __device__ __forceinline__ void picard_body(const P4<T> *__restrict__ vin,
         }
     }
     const Rec<T> own = load_rec<D>(vin, n, ev.at(0, 0, 0));
-    const CellStatic<D, T> cs = cell_static<D>(ev, ph, own.e);
+    const CellStatic<D, T> cs = cell_static<D, AD>(ev, ph, n, own.e);
     Rec<T> rec[3][2];
     bool fl[3][2];
     load_stencil<D, T, SOLIDS>(vin, ev, mask, g, nb, rec, fl);
@@ -1143,7 +1180,7 @@ __device__ __forceinline__ void picard_body(const P4<T> *__restrict__ vin,
     store_rec<D>(vout, n, own.r, v);
 }
 
-template <int D, typename T, bool SOLIDS>
+template <int D, typename T, bool SOLIDS, bool AD>
 __global__ __launch_bounds__(256) void k_picard(const P4<T> *__restrict__ vin,
                                                 const P4<T> *__restrict__ m0,
                                                 const T *__restrict__ eps,
@@ -1152,11 +1189,11 @@ __global__ __launch_bounds__(256) void k_picard(const P4<T> *__restrict__ vin,
                                                 const uint8_t *__restrict__ mask,
                                                 P4<T> *__restrict__ vout, Grid g, Tiling tl,
                                                 Phys<T> ph, T omega) {
-    picard_body<D, T, SOLIDS>(vin, m0, eps, muD, muF, mask, vout, g, tl, ph, omega, blockIdx.x);
+    picard_body<D, T, SOLIDS, AD>(vin, m0, eps, muD, muF, mask, vout, g, tl, ph, omega, blockIdx.x);
 }
 
 // Single-run kernels: workgroup w handles tile w of the run.
-template <int D, typename T, typename P, bool SOLIDS, int PH>
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
 __global__ __launch_bounds__(256) void k_moments(const P *__restrict__ f,
                                                  const T *__restrict__ eps,
                                                  const T *__restrict__ muD,
@@ -1165,21 +1202,21 @@ __global__ __launch_bounds__(256) void k_moments(const P *__restrict__ f,
                                                  P4<T> *__restrict__ m1_out,
                                                  P4<T> *__restrict__ m0_out, Grid g, Tiling tl,
                                                  Phys<T> ph) {
-    moments_body<D, T, P, SOLIDS, PH>(f, eps, muD, muF, mask, m1_out, m0_out, g, tl, ph,
+    moments_body<D, T, P, SOLIDS, PH, AD>(f, eps, muD, muF, mask, m1_out, m0_out, g, tl, ph,
                                       blockIdx.x);
 }
 
-template <int D, typename T, bool SOLIDS>
+template <int D, typename T, bool SOLIDS, bool AD>
 __global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ own_src,
                                                   const P4<T> *__restrict__ m1,
                                                   const T *__restrict__ eps,
                                                   const uint8_t *__restrict__ mask,
                                                   P4<T> *__restrict__ m2_out, Grid g, Tiling tl,
                                                   Phys<T> ph) {
-    vcorrect_body<D, T, SOLIDS>(own_src, m1, eps, mask, m2_out, g, tl, ph, blockIdx.x);
+    vcorrect_body<D, T, SOLIDS, AD>(own_src, m1, eps, mask, m2_out, g, tl, ph, blockIdx.x);
 }
 
-template <int D, typename T, typename P, bool SOLIDS, int PH>
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
 __global__ __launch_bounds__(256) void k_collide(P *__restrict__ f,
                                                  const P4<T> *__restrict__ m2,
                                                  const T *__restrict__ eps,
@@ -1187,10 +1224,10 @@ __global__ __launch_bounds__(256) void k_collide(P *__restrict__ f,
                                                  const T *__restrict__ muF,
                                                  const uint8_t *__restrict__ mask, Grid g,
                                                  Tiling tl, Phys<T> ph) {
-    collide_body<D, T, P, SOLIDS, PH>(f, m2, eps, muD, muF, mask, g, tl, ph, blockIdx.x);
+    collide_body<D, T, P, SOLIDS, PH, AD>(f, m2, eps, muD, muF, mask, g, tl, ph, blockIdx.x);
 }
 
-template <int D, typename T, typename P, bool SOLIDS, int PH>
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
 __global__ __launch_bounds__(256) void k_fused(P *__restrict__ f, const P4<T> *__restrict__ m1p,
                                                const P4<T> *__restrict__ m2p,
                                                P4<T> *__restrict__ m1n, P4<T> *__restrict__ m2n,
@@ -1199,13 +1236,13 @@ __global__ __launch_bounds__(256) void k_fused(P *__restrict__ f, const P4<T> *_
                                                const T *__restrict__ muF,
                                                const uint8_t *__restrict__ mask, Grid g,
                                                Tiling tl, Phys<T> ph) {
-    fused_body<D, T, P, SOLIDS, PH>(f, m1p, m2p, m1n, m2n, eps, muD, muF, mask, g, tl, ph, blockIdx.x);
+    fused_body<D, T, P, SOLIDS, PH, AD>(f, m1p, m2p, m1n, m2n, eps, muD, muF, mask, g, tl, ph, blockIdx.x);
 }
 
 // Initial populations, eq. (eq_bc_f_bar) with lambda = dt = 1, from the moment fields (rho, v):
 // f-bar_i = (1 + 1/2) f^eq_i - (1/2) f^*_i, written in natural layout.  A 16-bit slot is
 // encoded with the shift of its source cell, as a phase-0 read decodes it.
-template <int D, typename T, typename P, bool SOLIDS>
+template <int D, typename T, typename P, bool SOLIDS, bool AD>
 __global__ __launch_bounds__(256) void k_init(P *__restrict__ f,
                                               const P4<T> *__restrict__ m2,
                                               const T *__restrict__ eps,
@@ -1225,7 +1262,7 @@ __global__ __launch_bounds__(256) void k_init(P *__restrict__ f,
         }
     }
     const Rec<T> own = load_rec<D>(m2, n, ev.at(0, 0, 0));
-    const CellStatic<D, T> cs = cell_static<D>(ev, ph, own.e);
+    const CellStatic<D, T> cs = cell_static<D, AD>(ev, ph, n, own.e);
     ProductForm<D, T> peq, pst;
     cell_equilibria<D, T, SOLIDS>(m2, ev, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
     unroll<0, L::Q>([&](auto ii) {

@@ -49,12 +49,13 @@ struct Layout {
     size_t f, eps, muD, muF, mask, m1[2], m2[2], vsnap, part, res;
     size_t bcell, bcode, bval;  // boundary-node list (wet-node boundaries)
     size_t m0, mx;              // (rho, v_0) records and a second velocity buffer (Picard)
+    size_t deps;                // analytic porosity derivatives, D + D(D+1)/2 planes
     size_t total;
 };
 
 // sp: bytes per population value; s: bytes per value of the static fields and moment records.
 inline Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool solids, bool lagged,
-                          size_t nbnodes = 0, bool picard = false) {
+                          size_t nbnodes = 0, bool picard = false, bool analytic = false) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -82,6 +83,7 @@ inline Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool soli
     L.bval = nbnodes ? take(nbnodes * 4 * s) : 0;
     L.m0 = picard ? take(4 * N * s) : 0;
     L.mx = picard ? take(4 * N * s) : 0;
+    L.deps = analytic ? take((size_t)(D + D * (D + 1) / 2) * N * s) : 0;
     L.total = off;
     return L;
 }
@@ -111,6 +113,7 @@ struct lbm_solver {
     int bc_scheme, bc_rho_rule;
     int picard_iters;
     double picard_omega;
+    bool analytic;      // analytic porosity derivatives in L.deps
     lbm::Tiling tiles;  // 256-cell tiles, blocked, in XCD-contiguous ranges
 };
 
@@ -129,6 +132,8 @@ lbm::Phys<T> phys_of(const lbm_solver *h) {
     ph.nu_pow = h->nu_eff_pow;
     ph.rho0 = (T)h->rho0;
     ph.shift_porous = h->shift == LBM_SHIFT_POROUS ? 1 : 0;
+    ph.deps = h->analytic ? reinterpret_cast<const T *>(h->ws + h->L.deps) : nullptr;
+    ph.dN = (uint32_t)h->N;
     return ph;
 }
 

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void kb_moments(const RunDesc<T, P> *__restric
                                                   const uint32_t *__restrict__ starts, int nrun) {
     const int r = find_run(starts, nrun, blockIdx.x);
     const RunDesc<T, P> &d = runs[r];
-    moments_body<D, T, P, S, PH>(d.f, d.eps, d.muD, d.muF, d.mask, d.m1[0], nullptr, d.g, d.tl,
+    moments_body<D, T, P, S, PH, false>(d.f, d.eps, d.muD, d.muF, d.mask, d.m1[0], nullptr, d.g, d.tl,
                                  d.ph, blockIdx.x - starts[r]);
 }
 
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void kb_vcorrect(const RunDesc<T, P> *__restri
                                                    const uint32_t *__restrict__ starts, int nrun) {
     const int r = find_run(starts, nrun, blockIdx.x);
     const RunDesc<T, P> &d = runs[r];
-    vcorrect_body<D, T, S>(d.m1[0], d.m1[0], d.eps, d.mask, d.m2[0], d.g, d.tl, d.ph,
+    vcorrect_body<D, T, S, false>(d.m1[0], d.m1[0], d.eps, d.mask, d.m2[0], d.g, d.tl, d.ph,
                            blockIdx.x - starts[r]);
 }
 
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void kb_collide(const RunDesc<T, P> *__restric
                                                   const uint32_t *__restrict__ starts, int nrun) {
     const int r = find_run(starts, nrun, blockIdx.x);
     const RunDesc<T, P> &d = runs[r];
-    collide_body<D, T, P, S, PH>(d.f, d.m2[0], d.eps, d.muD, d.muF, d.mask, d.g, d.tl, d.ph,
+    collide_body<D, T, P, S, PH, false>(d.f, d.m2[0], d.eps, d.muD, d.muF, d.mask, d.g, d.tl, d.ph,
                                  blockIdx.x - starts[r]);
 }
 
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void kb_fused(const RunDesc<T, P> *__restrict_
     const int r = find_run(starts, nrun, blockIdx.x);
     const RunDesc<T, P> &d = runs[r];
     const int prev = d.cur ^ parity;
-    fused_body<D, T, P, S, PH>(d.f, d.m1[prev], d.m2[prev], d.m1[prev ^ 1], d.m2[prev ^ 1],
+    fused_body<D, T, P, S, PH, false>(d.f, d.m1[prev], d.m2[prev], d.m1[prev ^ 1], d.m2[prev ^ 1],
                                d.eps, d.muD, d.muF, d.mask, d.g, d.tl, d.ph,
                                blockIdx.x - starts[r]);
 }
@@ -401,10 +401,11 @@ LBM_API int lbm_server_submit(lbm_server *s, const lbm_params *p, double tol, in
     if (!p || !id) return fail(LBM_ERR_INVALID_ARG, "null argument");
     if (!(tol > 0) || max_steps < s->check_every)
         return fail(LBM_ERR_INVALID_ARG, "tol must be > 0 and max_steps >= check_every");
-    if (p->bc_type || p->picard_iters)
+    if (p->bc_type || p->picard_iters || p->grad_eps || p->hess_eps)
         return fail(LBM_ERR_UNSUPPORTED,
-                    "the server runs periodic / bounce-back runs with the one-shot velocity "
-                    "(no bc_type, picard_iters = 0)");
+                    "the server runs periodic / bounce-back runs with the one-shot velocity and "
+                    "differenced porosity derivatives (no bc_type, picard_iters = 0, no "
+                    "grad_eps / hess_eps)");
     size_t bytes = 0;
     rc = lbm_footprint(p, &bytes);
     if (rc) return rc;

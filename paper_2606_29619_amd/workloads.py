@@ -62,6 +62,10 @@ class Workload:
     bc_rho_rule: int = 0        # 0 mass continuity, 1 bounce-back
     picard_iters: int = 0       # second-order velocity evaluation: Picard iterations
     picard_omega: float = 1.0
+    # analytic porosity derivatives: grad eps [D, ...] and the Hessian's upper triangle row by
+    # row [D(D+1)/2, ...] (xx, xy, yy or xx, xy, xz, yy, yz, zz); None: central differences
+    grad_eps: Optional[np.ndarray] = None
+    hess_eps: Optional[np.ndarray] = None
 
     @property
     def D(self) -> int:
@@ -207,12 +211,121 @@ def smoothstep_cinf(psi: np.ndarray) -> np.ndarray:
     return out
 
 
+def smoothstep_cinf_derivatives(psi: np.ndarray):
+    """First and second derivatives of S(psi).  Inside (0, 1), S = 1 / (1 + exp(-u)) with
+    u = 1/(1 - psi) - 1/psi, so S' = S (1 - S) u' and S'' = S (1 - S) [(1 - 2 S) u'^2 + u''],
+    u' = 1/psi^2 + 1/(1 - psi)^2, u'' = 2/(1 - psi)^3 - 2/psi^3; both vanish outside."""
+    psi = np.asarray(psi, dtype=np.float64)
+    d1 = np.zeros_like(psi)
+    d2 = np.zeros_like(psi)
+    inner = (psi > 0.0) & (psi < 1.0)
+    p = psi[inner]
+    S = smoothstep_cinf(p)
+    u1 = 1.0 / p ** 2 + 1.0 / (1.0 - p) ** 2
+    u2 = 2.0 / (1.0 - p) ** 3 - 2.0 / p ** 3
+    d1[inner] = S * (1.0 - S) * u1
+    d2[inner] = S * (1.0 - S) * ((1.0 - 2.0 * S) * u1 * u1 + u2)
+    return d1, d2
+
+
 def heterogeneous_channel_setup1(H: int, eps_bot=1.0, eps_top=0.5, phi_bot=0.1, phi_top=0.1):
     """Wall-normal two-plateau porosity with a smoothstep transition, sampled at the fluid rows
     of a channel with halfway walls at y = 0 and y = H (row j sits at y = j - 1/2)."""
     y = np.arange(1, H + 1) - 0.5
     psi = ((y / H) - phi_bot) / (1.0 - phi_top - phi_bot)
     return y, eps_bot + (eps_top - eps_bot) * smoothstep_cinf(psi)
+
+
+def heterogeneous_channel_setup1_derivatives(H: int, eps_bot=1.0, eps_top=0.5, phi_bot=0.1,
+                                             phi_top=0.1):
+    """Analytic d eps / dy and d^2 eps / dy^2 of the Setup I porosity at the fluid rows."""
+    y = np.arange(1, H + 1) - 0.5
+    span = 1.0 - phi_top - phi_bot
+    psi = ((y / H) - phi_bot) / span
+    d1, d2 = smoothstep_cinf_derivatives(psi)
+    dpsi = 1.0 / (H * span)
+    return (eps_top - eps_bot) * d1 * dpsi, (eps_top - eps_bot) * d2 * dpsi * dpsi
+
+
+def _upper_pairs(D):
+    return [(a, b) for a in range(D) for b in range(a, D)]
+
+
+def quadratic_box(D=2, n=(28, 22, 18), nu=0.05, b=(2e-4, -1e-4, 5e-5), kappa=0.5) -> Workload:
+    """Closed box (one solid layer on every face) with the quadratic porosity
+    eps = 0.65 + sum_a g_a u_a + sum_{a<=b} h_ab u_a u_b, u_a = (x_a - c_a) / n_a centred on the
+    box, and its exact derivatives.  Central differences of a quadratic are exact, so a run with
+    these analytic derivatives and one with differenced ones must agree to rounding."""
+    g = (0.12, -0.08, 0.05)
+    h = {(0, 0): 0.10, (0, 1): 0.07, (0, 2): -0.04, (1, 1): -0.09, (1, 2): 0.06, (2, 2): 0.05}
+    dims = tuple(n[:D])
+    shape = (1, dims[1], dims[0]) if D == 2 else (dims[2], dims[1], dims[0])
+    grids = np.meshgrid(*[np.arange(k, dtype=np.float64) for k in shape], indexing="ij")
+    xs = [grids[2], grids[1]] + ([grids[0]] if D == 3 else [])     # x, y (, z)
+    u = [(xs[a] - (dims[a] - 1) / 2.0) / dims[a] for a in range(D)]
+    eps = np.full(shape, 0.65)
+    for a in range(D):
+        eps = eps + g[a] * u[a]
+    for (a, c) in _upper_pairs(D):
+        eps = eps + h[(a, c)] * u[a] * u[c]
+    grad = np.zeros((D,) + shape)
+    for a in range(D):
+        da = np.full(shape, g[a])
+        for (p, q) in _upper_pairs(D):
+            if p == a and q == a:
+                da = da + 2.0 * h[(p, q)] * u[a]
+            elif p == a:
+                da = da + h[(p, q)] * u[q]
+            elif q == a:
+                da = da + h[(p, q)] * u[p]
+        grad[a] = da / dims[a]
+    hess = np.zeros((len(_upper_pairs(D)),) + shape)
+    for k, (a, c) in enumerate(_upper_pairs(D)):
+        hess[k] = (2.0 if a == c else 1.0) * h[(a, c)] / (dims[a] * dims[c])
+    mask = np.zeros(shape, np.uint8)
+    mask[:, 0, :] = mask[:, -1, :] = 1
+    mask[:, :, 0] = mask[:, :, -1] = 1
+    if D == 3:
+        mask[0] = mask[-1] = 1
+    return Workload(name=f"quadratic-porosity box D{D}", lattice=9 if D == 2 else 27, eps=eps,
+                    kappa=np.full(shape, kappa), forch=np.full(shape, 0.55 / math.sqrt(kappa)),
+                    mask=mask, nu_f=nu, nu_eff_ref=nu, nu_eff_pow=0, b=tuple(b[:3]),
+                    grad_eps=grad, hess_eps=hess)
+
+
+def sine_porosity(D=3, shape=(12, 16, 20), amp=0.15, nu=0.03, b=(2e-4, 0.0, 0.0),
+                  nu_eff_pow=-1) -> Workload:
+    """Periodic box with eps = 0.7 + amp sin(k_x x + 0.3) cos(k_y y) (sin(k_z z + 0.5) in 3D),
+    k_a = 2 pi / n_a, Kozeny-Carman permeability (d = 2), and its exact derivatives."""
+    shape = tuple(shape) if D == 3 else (1,) + tuple(shape[-2:])
+    grids = np.meshgrid(*[np.arange(k, dtype=np.float64) for k in shape], indexing="ij")
+    xs = [grids[2], grids[1]] + ([grids[0]] if D == 3 else [])
+    ns = [shape[2], shape[1]] + ([shape[0]] if D == 3 else [])
+    k = [2.0 * math.pi / m for m in ns]
+    ph = [0.3, 0.0, 0.5]
+    # factor functions and their derivatives: sin, cos, sin
+    fs = [np.sin, np.cos, np.sin]
+    d1 = [lambda t: np.cos(t), lambda t: -np.sin(t), lambda t: np.cos(t)]
+    d2 = [lambda t: -np.sin(t), lambda t: -np.cos(t), lambda t: -np.sin(t)]
+    t = [k[a] * xs[a] + ph[a] for a in range(D)]
+    F = [fs[a](t[a]) for a in range(D)]
+    F1 = [k[a] * d1[a](t[a]) for a in range(D)]
+    F2 = [k[a] * k[a] * d2[a](t[a]) for a in range(D)]
+
+    def prod(sel):
+        out = np.full(shape, amp)
+        for a in range(D):
+            out = out * sel[a]
+        return out
+
+    eps = 0.7 + prod(F)
+    grad = np.stack([prod([F1[c] if c == a else F[c] for c in range(D)]) for a in range(D)])
+    hess = np.stack([prod([(F2[c] if a == q else F1[c]) if c in (a, q) else F[c]
+                           for c in range(D)]) for (a, q) in _upper_pairs(D)])
+    K = kozeny_carman(eps, 2.0)
+    return Workload(name=f"sine-porosity D{D}", lattice=9 if D == 2 else 27, eps=eps, kappa=K,
+                    forch=forchheimer(K), mask=None, nu_f=nu, nu_eff_ref=nu,
+                    nu_eff_pow=nu_eff_pow, b=tuple(b), grad_eps=grad, hess_eps=hess)
 
 
 def request_stream(n_requests=512, seed=0):

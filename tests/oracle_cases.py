@@ -10,9 +10,10 @@ from paper_2606_29619_amd import workloads
 
 
 def channel(D, H, eps_rows, kappa_rows, cf_rows=None, nu=0.1, nu_f=None, b=1e-6, pow_=0,
-            visc_corr=1, ext_corr=1, nx=1, nz=1, lagged=0):
+            visc_corr=1, ext_corr=1, nx=1, nz=1, lagged=0, deps_rows=None, d2eps_rows=None):
     """Channel periodic in x (and z), solid rows y = 0 and y = H + 1, so the halfway walls sit at
-    distance H apart and fluid row j lies at y = j - 1/2 from the lower wall."""
+    distance H apart and fluid row j lies at y = j - 1/2 from the lower wall.  deps_rows and
+    d2eps_rows: analytic d eps/dy and d^2 eps/dy^2 of the fluid rows (else differences)."""
     ny = H + 2
     shape = (nz if D == 3 else 1, ny, nx)
     eps = np.ones(shape)
@@ -27,10 +28,16 @@ def channel(D, H, eps_rows, kappa_rows, cf_rows=None, nu=0.1, nu_f=None, b=1e-6,
     mask = np.zeros(shape, dtype=np.uint8)
     mask[:, 0, :] = 1
     mask[:, -1, :] = 1
+    grad = hess = None
+    if deps_rows is not None:
+        grad = np.zeros((D,) + shape)
+        hess = np.zeros((D * (D + 1) // 2,) + shape)
+        grad[1][:, 1:-1, :] = np.asarray(deps_rows).reshape(1, H, 1)
+        hess[D][:, 1:-1, :] = np.asarray(d2eps_rows).reshape(1, H, 1)   # the yy entry
     cfg = oracle.OracleConfig(D=D, eps=eps, kappa=kappa, cf=cf, mask=mask,
                               nu_f=nu if nu_f is None else nu_f, nu_eff_ref=nu,
                               nu_eff_pow=pow_, b=(b, 0.0, 0.0), visc_corr=visc_corr,
-                              ext_corr=ext_corr, lagged=lagged)
+                              ext_corr=ext_corr, lagged=lagged, grad_eps=grad, hess_eps=hess)
     return oracle.Oracle(cfg)
 
 

@@ -306,3 +306,39 @@ def test_picard_validation_and_footprint():
         with pytest.raises(capi.LbmError) as ei:
             capi.lbm_footprint(q)
         assert ei.value.code == code, (iters, omega, scheme)
+
+
+def test_analytic_derivative_validation_and_footprint():
+    """grad_eps and hess_eps go together, add D + D(D+1)/2 value planes to the workspace, must
+    be finite on fluid cells (solid cells are never read), and the server declines them."""
+    shape = (4, 5, 6)
+    N = 120
+    p, _k = _params(shape=shape)
+    base = capi.lbm_footprint(p)
+    g, h = np.zeros((3,) + shape), np.zeros((6,) + shape)
+    q, _kq = _params(shape=shape, grad_eps=g, hess_eps=h)
+    assert capi.lbm_footprint(q) - base >= 9 * N * 4
+    r, _kr = _params(shape=shape, grad_eps=g)
+    with pytest.raises(capi.LbmError) as ei:
+        capi.lbm_footprint(r)
+    assert ei.value.code == capi.LBM_ERR_INVALID_ARG
+    mask = np.zeros(shape, np.uint8)
+    mask[0, 0, 0] = 1
+    for which, idx, expect in [("grad", (1, 2, 3, 4), "grad_eps"),
+                               ("hess", (5, 1, 1, 1), "hess_eps"),
+                               ("grad", (2, 0, 0, 0), "dev_workspace")]:   # a solid cell
+        gg, hh = g.copy(), h.copy()
+        (gg if which == "grad" else hh)[idx] = math.nan
+        s, _ks = _params(shape=shape, mask=mask, grad_eps=gg, hess_eps=hh)
+        need = capi.lbm_footprint(s)
+        with pytest.raises(capi.LbmError) as ei:
+            capi.lbm_create(s, 0, need, 0)         # null workspace: fails after the field checks
+        assert ei.value.code == capi.LBM_ERR_INVALID_ARG
+        assert expect in capi.lbm_last_error(), capi.lbm_last_error()
+    srv = capi.lbm_server_create(_FAKE_POOL, 1 << 30, 100, 0, 0)
+    try:
+        with pytest.raises(capi.LbmError) as ei:
+            capi.lbm_server_submit(srv, q, 1e-7, 1000)
+        assert ei.value.code == capi.LBM_ERR_UNSUPPORTED
+    finally:
+        capi.lbm_server_destroy(srv)

@@ -1,0 +1,149 @@
+"""GPU parity of the analytic porosity-derivative inputs (Sec. 3.5: Delta_nu from analytic
+derivatives of eps when eps(x) is known in closed form) against the FP64 oracle fed the same
+derivatives: the RT grad eps force of v_(0), Delta_nu (porosity_correction_expanded) and the
+wall-normal gradient of pressure nodes all read them.  FP64 must match to 1e-12 normwise per
+field, as the bulk parity tests; FP32 and FP16 storage take the tolerances of their bulk cases.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_29619_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+capi = pytest.importorskip("paper_2606_29619_amd.capi")
+
+FP64_TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    capi.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def _oracle(w, lagged=0):
+    return oracle.Oracle(oracle.OracleConfig(
+        D=w.D, eps=w.eps, kappa=w.kappa, cf=w.forch, mask=w.mask, RT=w.RT, nu_f=w.nu_f,
+        nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow, eta_eff=w.eta_eff, b=w.b,
+        rho0=w.rho0, rho_init=w.rho_init, v_init=w.v_init, bc_type=w.bc_type,
+        bc_normal=w.bc_normal, bc_vel=w.bc_velocity, bc_rho=w.bc_density,
+        bc_scheme=w.bc_scheme, bc_density=w.bc_rho_rule, picard_iters=w.picard_iters,
+        picard_omega=w.picard_omega, lagged=lagged, grad_eps=w.grad_eps, hess_eps=w.hess_eps))
+
+
+def _rel(a, b):
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+
+
+def _errors(s, o):
+    f_gpu = s.populations(torch.float64).cpu().numpy()
+    rho_gpu, v_gpu = (t.cpu().numpy() for t in s.moments(torch.float64))
+    rho_ref, v_ref, _ = o.moments()
+    errs = {"f": _rel(f_gpu, o.populations()), "rho": _rel(rho_gpu, rho_ref)}
+    for a in range(v_ref.shape[0]):
+        errs[f"v{a}"] = _rel(v_gpu[a], v_ref[a])
+    return errs
+
+
+def _pair(w, chunks, storage=capi.LBM_F64, lagged=False, shift=capi.LBM_SHIFT_WEIGHTS):
+    scheme = capi.LBM_SCHEME_LAGGED if lagged else capi.LBM_SCHEME_TWO_PASS
+    s = capi.Solver.from_workload(w, storage=storage, scheme=scheme, shift=shift)
+    o = _oracle(w, lagged=int(lagged))
+    for n in chunks:
+        s.step(n)
+        o.step(n)
+    torch.cuda.synchronize()
+    return s, o
+
+
+def _channel_with_sine_porosity(D):
+    """Pressure-driven channel (pressure inlet and outlet nodes, solid side walls) whose
+    porosity is a smooth product of sines with its analytic derivatives; the porosity varies
+    along the channel at the pressure nodes too, so their wall-normal gradient is read."""
+    L, H, W = (40, 12, 6) if D == 2 else (24, 8, 6)
+    w = workloads.pressure_channel(D=D, L=L, H=H, W=W, drho=2e-3)
+    sw = workloads.sine_porosity(D, shape=w.shape, amp=0.1)
+    w.eps, w.grad_eps, w.hess_eps = sw.eps, sw.grad_eps, sw.hess_eps
+    w.kappa = np.full(w.shape, 0.5)
+    w.forch = 0.55 / np.sqrt(w.kappa)
+    return w
+
+
+@pytest.mark.parametrize("case", ["quadratic_d2", "quadratic_d3", "sine_d3_pow_eta",
+                                  "sine_d2_lagged", "pressure_d2", "pressure_d3",
+                                  "picard_sine_d2"])
+def test_analytic_derivatives_match_oracle(case):
+    """FP64, 41 + 40 steps (both AA phases at the checks): closed quadratic-porosity boxes in
+    2D and 3D, a periodic sine field with nu_eff = nu/eps and Phi^eta on, the lagged scheme,
+    pressure channels with a sine field (the pressure nodes' wall-normal gradient), and the
+    Picard iterations."""
+    lagged = False
+    if case.startswith("quadratic"):
+        w = workloads.quadratic_box(2 if case.endswith("d2") else 3)
+    elif case == "sine_d3_pow_eta":
+        w = workloads.sine_porosity(3, shape=(9, 14, 70))
+        w.eta_eff = 0.05
+    elif case == "sine_d2_lagged":
+        w = workloads.sine_porosity(2, shape=(1, 30, 45), nu_eff_pow=0)
+        lagged = True
+    elif case.startswith("pressure"):
+        w = _channel_with_sine_porosity(2 if case.endswith("d2") else 3)
+    else:
+        w = workloads.sine_porosity(2, shape=(1, 33, 45), b=(3e-4, 1e-4, 0.0))
+        w.picard_iters = 3
+    s, o = _pair(w, (41, 40), lagged=lagged)
+    errs = _errors(s, o)
+    print(f"analytic {case}:", errs, flush=True)
+    assert max(errs.values()) <= FP64_TOL, errs
+
+
+@pytest.mark.parametrize("storage,lagged", [("f32", False), ("f32", True), ("f16", True)])
+def test_analytic_derivatives_reduced_precision(storage, lagged):
+    """FP32 storage (both schemes) and FP16 storage with the porous shift (lagged scheme, the
+    kernel that stages eps in LDS and reads the derivative planes) against the FP64 oracle on a
+    32^3 sine field, 100 steps.  The flow here is a small residual of the RT grad eps force and
+    the pressure gradient, so its relative rounding error depends on the field; the analytic
+    run must do no worse than the differenced run of the same field against its own oracle,
+    and the populations stay within the bulk FP32 bounds."""
+    w = workloads.sine_porosity(3, shape=(32, 32, 32), nu=0.01, b=(1e-6, 0.0, 0.0),
+                                nu_eff_pow=0)
+    st = capi.LBM_F32 if storage == "f32" else capi.LBM_F16_SHIFTED
+    s, o = _pair(w, (100,), storage=st, lagged=lagged, shift=capi.LBM_SHIFT_POROUS)
+    errs = _errors(s, o)
+    vmax = [float(np.abs(o.moments()[1][a]).max()) for a in range(3)]
+    w.grad_eps = w.hess_eps = None
+    s2, o2 = _pair(w, (100,), storage=st, lagged=lagged, shift=capi.LBM_SHIFT_POROUS)
+    errs_fd = _errors(s2, o2)
+    print(f"analytic {storage} lagged={lagged}:", errs, "max|v|", vmax, flush=True)
+    print(f"differenced {storage} lagged={lagged}:", errs_fd, flush=True)
+    f_bound = 3e-5 if storage == "f32" else 5e-5
+    assert errs["f"] < f_bound and errs["rho"] < 5e-5, errs
+    for k in ("v0", "v1", "v2"):
+        assert errs[k] < 2 * errs_fd[k] + 1e-4, (k, errs, errs_fd)
+
+
+def test_analytic_and_differenced_runs_agree_on_quadratic_porosity():
+    """On the GPU itself: central differences of a quadratic porosity are exact, so the runs
+    with and without the analytic inputs agree to rounding (FP64, 60 steps)."""
+    w = workloads.quadratic_box(3)
+    a = capi.Solver.from_workload(w, storage=capi.LBM_F64)
+    g, h = w.grad_eps, w.hess_eps
+    w.grad_eps = w.hess_eps = None
+    b = capi.Solver.from_workload(w, storage=capi.LBM_F64)
+    w.grad_eps, w.hess_eps = g, h
+    a.step(60)
+    b.step(60)
+    _, va = a.moments(torch.float64)
+    _, vb = b.moments(torch.float64)
+    fa = a.populations(torch.float64)
+    fb = b.populations(torch.float64)
+    assert float((va - vb).abs().max()) < 1e-14
+    assert float((fa - fb).abs().max()) < 1e-14
+    assert float(vb.abs().max()) > 1e-6

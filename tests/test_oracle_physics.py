@@ -260,6 +260,70 @@ def test_heterogeneous_channel_matches_bvp(visc_corr):
     assert np.ptp(rho) / rho.mean() < 5e-3     # measured 2.3e-3, falling as 1/H^2
 
 
+def _setup1_error(H, analytic, scale=1.0):
+    """Setup I (Sec. 5.2.2, Da = 1e-2, V0 = 0.01): max deviation of the steady profile from the
+    target problem (Poiseuille_v_BVP), relative to its maximum, and the profile."""
+    nu = 0.1
+    y, eps_rows = workloads.heterogeneous_channel_setup1(H)
+    kappa = 1e-2 * H * H
+    b = 8 * nu * 0.01 / H ** 2
+    d1 = d2 = None
+    if analytic:
+        d1, d2 = workloads.heterogeneous_channel_setup1_derivatives(H)
+        d1, d2 = scale * d1, scale * d2
+    o = oc.channel(2, H, eps_rows, np.full(H, kappa), nu=nu, b=b, deps_rows=d1, d2eps_rows=d2)
+    oc.run_to_steady(o, tol=1e-11, chunk=500)
+    _, v = oc.profile(o)
+    eps_f = lambda yy: _eps_cont(yy, H)
+    target = _solve_channel_bvp(H, eps_f, lambda yy: eps_f(yy) * nu / kappa,
+                                lambda yy: 0.0 * yy, b, nu)(y)
+    return np.abs(v - target).max() / target.max(), v
+
+
+def test_analytic_porosity_derivatives_setup1():
+    """Sec. 3.5 evaluates Delta_nu preferably from analytic derivatives of eps: with the exact
+    eps' and eps'' of the C-inf smoothstep (instead of central differences) the Setup I profile
+    still solves the target problem (Poiseuille_v_BVP) and converges at second order (measured
+    8.1e-3 -> 2.4e-3 -> 6.6e-4 for H = 24 -> 48 -> 96, the differenced run within 0.5 % of
+    that); the inputs are really used (the two profiles differ by 1.9e-4 at H = 48, falling as
+    1/H^2 like the differencing error), and derivatives off by half spoil the solution (5.1e-2)."""
+    e24, _ = _setup1_error(24, True)
+    e48, v_an = _setup1_error(48, True)
+    _, v_fd = _setup1_error(48, False)
+    assert e48 < 3e-3 and e24 / e48 > 3.0, (e24, e48)
+    diff = np.abs(v_an - v_fd).max() / v_fd.max()
+    assert 5e-5 < diff < e48, diff
+    e_bad, _ = _setup1_error(48, True, scale=1.5)
+    assert e_bad > 5 * e48, (e_bad, e48)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_analytic_derivatives_equal_differences_on_quadratic_porosity(D):
+    """Central differences of a quadratic are exact, so on a closed box with a quadratic
+    porosity (all six Hessian entries distinct) a run fed the analytic grad eps and Hessian
+    equals the differenced run to rounding (60 steps): every component lands in its place."""
+    w = workloads.quadratic_box(D)
+    base = dict(D=D, eps=w.eps, kappa=w.kappa, cf=w.forch, mask=w.mask, nu_f=w.nu_f,
+                nu_eff_ref=w.nu_eff_ref, b=w.b)
+    oa = oracle.Oracle(oracle.OracleConfig(**base, grad_eps=w.grad_eps, hess_eps=w.hess_eps))
+    of = oracle.Oracle(oracle.OracleConfig(**base))
+    ga, Ha = oa.porosity_derivatives()
+    gf, Hf = of.porosity_derivatives()
+    fl = ~w.mask.astype(bool)
+    # differences of O(1) porosities: rounding of 1e-16 against derivatives of 1e-4 .. 1e-2
+    assert np.abs(ga[:, fl] - gf[:, fl]).max() < 1e-14
+    assert np.abs(Ha[:, :, fl] - Hf[:, :, fl]).max() < 1e-14
+    oa.step(60)
+    of.step(60)
+    fa, ff = oa.populations(), of.populations()
+    _, va, _ = oa.moments()
+    _, vf, _ = of.moments()
+    # measured 2.5e-16 (v) and 5e-16 (f); two Hessian entries swapped give 1e-7 .. 6e-7
+    assert np.abs(va - vf).max() < 1e-14
+    assert np.abs(fa - ff).max() < 1e-14
+    assert np.abs(vf).max() > 1e-6              # the porosity gradients drive a flow
+
+
 def test_lagged_scheme_shares_the_two_pass_steady_state():
     """The lagged single-pass scheme (neighbour values of the Delta_nu, Phi^ext and Phi^eta
     stencils from the previous step) has the two-pass scheme's fixed points: once the state
