@@ -26,31 +26,33 @@ HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E, published
 METRIC = "MLUPS & % HBM roofline (D3Q27); served MLUPS + p50/p99 time-to-steady"
 
 
-def kernel_bytes_per_cell(Q, D, sp, s):
+def kernel_bytes_per_cell(Q, D, sp, s, m=0):
     """Algorithmic HBM bytes per cell of each kernel (values each kernel must move once), with
-    sp bytes per population and s per static-field or moment value:
-    moments: read Q pops + eps, mu_D, mu_F; write rho and v^(1) (D+1);
-    velocity correction: read rho, v^(1), eps; write v (D);
-    collide-stream: read Q pops, rho, v, eps, mu_D, mu_F; write Q pops."""
+    sp bytes per population, s per static-field or moment value and m per solid-mask byte
+    (1 when the run has solid cells, else 0):
+    moments: read Q pops + eps, mu_D, mu_F (+ mask); write rho and v^(1) (D+1);
+    velocity correction: read rho, v^(1), eps (+ mask); write v (D);
+    collide-stream: read Q pops, rho, v, eps, mu_D, mu_F (+ mask); write Q pops."""
     return {
-        "moments": Q * sp + (3 + (D + 1)) * s,
-        "vcorrect": ((D + 1) + 1 + D) * s,
-        "collide": 2 * Q * sp + ((D + 1) + 3) * s,
+        "moments": Q * sp + (3 + (D + 1)) * s + m,
+        "vcorrect": ((D + 1) + 1 + D) * s + m,
+        "collide": 2 * Q * sp + ((D + 1) + 3) * s + m,
     }
 
 
-def lagged_bytes_per_cell(Q, D, sp, s):
-    """Single pass of the lagged scheme: read Q pops, 3 static fields and the previous step's
-    rho, v^(1), v; write Q pops and the new rho, v^(1), v."""
-    return 2 * Q * sp + (3 + 2 * (2 * D + 1)) * s
+def lagged_bytes_per_cell(Q, D, sp, s, m=0):
+    """Single pass of the lagged scheme: read Q pops, 3 static fields (+ mask) and the previous
+    step's rho, v^(1), v; write Q pops and the new rho, v^(1), v."""
+    return 2 * Q * sp + (3 + 2 * (2 * D + 1)) * s + m
 
 
-def method_bytes_per_cell(Q, D, sp, s, lagged=False):
-    """Per-step minimum of the method.  Two-pass: pass one reads Q pops + 3 static fields and
-    writes rho, v^(1); pass two reads Q pops, rho, v, 3 static fields and writes Q pops."""
+def method_bytes_per_cell(Q, D, sp, s, lagged=False, m=0):
+    """Per-step minimum of the method.  Two-pass: pass one reads Q pops + 3 static fields
+    (+ mask) and writes rho, v^(1); pass two reads Q pops, rho, v, 3 static fields (+ mask) and
+    writes Q pops."""
     if lagged:
-        return lagged_bytes_per_cell(Q, D, sp, s)
-    return 3 * Q * sp + (3 + (D + 1) + (D + 1) + 3) * s
+        return lagged_bytes_per_cell(Q, D, sp, s, m)
+    return 3 * Q * sp + (3 + (D + 1) + (D + 1) + 3) * s + 2 * m
 
 
 def source_hash():
@@ -62,10 +64,11 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel, N, src_hash):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, when it was taken on
-    the current kernel source; otherwise None."""
-    path = os.path.join(ROOT, "profiles", "pmc_d3q27_f32_256.json")
+def traffic_from_profiles(kernel, tag, src_hash):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary of the 256^3 box with this
+    storage (tag: "f32", "f16_porous", ...), when it was taken on the current kernel source;
+    otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_d3q27_{tag}_256.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -76,14 +79,21 @@ def traffic_from_profiles(kernel, N, src_hash):
     return (k["fetch_kib"] * pmc["fetch_scale"] + k["write_kib"] * pmc["write_scale"]) * 1024.0
 
 
-def cpu_baseline(budget_s=15.0):
-    """The FP64 oracle, as it stands, on the 64^3 instance of the same recipe (seed 0):
-    one process, one thread; steps until about budget_s of stepping have elapsed."""
+def cpu_baseline(budget_s=15.0, workload="box"):
+    """The FP64 oracle, as it stands, on a bounded instance of the same recipe: the 64^3 box
+    (seed 0), or the sphere duct at 1/8 scale (96 x 48 x 48, radius 12); one process, one
+    thread; steps until about budget_s of stepping have elapsed."""
     import oracle
     from paper_2606_29619_amd import workloads
-    w = workloads.random_porosity_3d(n=64, seed=0, ell=16.0)
+    if workload == "box":
+        w = workloads.random_porosity_3d(n=64, seed=0, ell=16.0)
+        what = "D3Q27 64^3 instance of the same random-porosity recipe (seed 0)"
+    else:
+        w = workloads.sphere_duct_3d(96, 48, 48, radius=12.0, bump_m=8)
+        what = "the sphere-duct recipe at 1/8 scale (96 x 48 x 48, radius 12, bump m = 8)"
     o = oracle.Oracle(oracle.OracleConfig(D=3, eps=w.eps, kappa=w.kappa, cf=w.forch,
-                                          nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref, b=w.b))
+                                          mask=w.mask, nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref,
+                                          b=w.b))
     t0 = time.perf_counter()
     o.step(1)
     one = time.perf_counter() - t0
@@ -94,8 +104,8 @@ def cpu_baseline(budget_s=15.0):
     cells = w.cells
     return {"value": round(cells * k / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
             "kind": "oracle",
-            "sample": f"FP64 oracle, D3Q27 64^3 instance of the same random-porosity recipe "
-                      f"(seed 0), {k} timed steps after 1 warm-up step, {dt:.1f} s"}
+            "sample": f"FP64 oracle, {what}, {k} timed steps after 1 warm-up step, "
+                      f"{dt:.1f} s"}
 
 
 def serving_sample(n_requests, max_steps):
@@ -131,7 +141,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=256, help="cells per side")
+    ap.add_argument("--workload", choices=["box", "sphere"], default="box",
+                    help="box: random-porosity periodic box (headline); sphere: 768x384x384 "
+                         "duct with walls on the y and z faces and a smooth porous sphere")
+    ap.add_argument("--n", type=int, default=256, help="cells per side of the box")
     ap.add_argument("--storage", choices=["f32", "f64", "f16", "bf16"], default="f32",
                     help="population storage; f16/bf16 are the shifted 16-bit forms (FP32 math)")
     ap.add_argument("--shift", choices=["weights", "porous"], default="porous",
@@ -162,7 +175,17 @@ def main():
 
     torch.cuda.set_device(0)
     n = args.n
-    w = workloads.random_porosity_3d(n=n, seed=0, ell=16.0, steps=args.steps)
+    if args.workload == "box":
+        w = workloads.random_porosity_3d(n=n, seed=0, ell=16.0, steps=args.steps)
+        wdesc = (f"random-porosity D3Q27 {n}^3 periodic box, seed 0, correlation length 16, "
+                 f"phi in (0.3,1), Kozeny-Carman K (d=2), C_F=0.55/sqrt(K), nu=0.01, b=1e-6 x")
+    else:
+        w = workloads.sphere_duct_3d(bump_m=8, steps=args.steps)
+        wdesc = ("D3Q27 768x384x384 duct, solid walls on the y and z faces, porous sphere of "
+                 "radius 96 at (192, 192, 192): eps = 1 - 0.5 B_8(r^2/R^2), 1/K = B_8/5e-3, "
+                 "C_F=0.55/sqrt(K), nu=0.052, b = 1e-4/768 x (pressure drop 1e-4 as a body "
+                 "force); MLUPS count every cell, solid walls included")
+    msk = 1 if w.mask is not None else 0
     storage = {"f32": capi.LBM_F32, "f64": capi.LBM_F64, "f16": capi.LBM_F16_SHIFTED,
                "bf16": capi.LBM_BF16_SHIFTED}[args.storage]
     s_bytes = 8 if args.storage == "f64" else 4
@@ -193,18 +216,20 @@ def main():
 
     Q, D = 27, 3
     if lagged:
-        kb = {"fused": lagged_bytes_per_cell(Q, D, sp_bytes, s_bytes)}
+        kb = {"fused": lagged_bytes_per_cell(Q, D, sp_bytes, s_bytes, msk)}
         avg_ms = {"fused": kms[2] / args.steps}
     else:
-        kb = kernel_bytes_per_cell(Q, D, sp_bytes, s_bytes)
+        kb = kernel_bytes_per_cell(Q, D, sp_bytes, s_bytes, msk)
         avg_ms = {"moments": kms[0] / args.steps, "vcorrect": kms[1] / args.steps,
                   "collide": kms[2] / args.steps}
     dom = max(avg_ms, key=avg_ms.get)
     algo = kb[dom] * N
     achieved = algo / (avg_ms[dom] * 1e-3) / 1e9
     src = source_hash()
-    traffic = traffic_from_profiles(dom, N, src)
-    step_bytes = method_bytes_per_cell(Q, D, sp_bytes, s_bytes, lagged)
+    tag = args.storage if sp_bytes != 2 else f"{args.storage}_{args.shift}"
+    traffic = (traffic_from_profiles(dom, tag, src)
+               if args.workload == "box" and n == 256 else None)
+    step_bytes = method_bytes_per_cell(Q, D, sp_bytes, s_bytes, lagged, msk)
     kernels = {k: {"avg_ms": round(avg_ms[k], 4), "bytes_per_cell": kb[k],
                    "achieved_GBps": round(kb[k] * N / (avg_ms[k] * 1e-3) / 1e9, 1)}
                for k in avg_ms}
@@ -221,9 +246,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"random-porosity D3Q27 {n}^3 periodic box, seed 0, "
-                               f"correlation length 16, phi in (0.3,1), Kozeny-Carman K (d=2), "
-                               f"C_F=0.55/sqrt(K), nu=0.01, b=1e-6 x", "lattice": "D3Q27",
+        "config": {"workload": wdesc, "lattice": "D3Q27",
                    "cells": N, "scheme": args.scheme,
                    "storage": args.storage if sp_bytes != 2 else
                    f"{args.storage} shifted ({args.shift})"},
@@ -253,7 +276,7 @@ def main():
     if not args.no_serving:
         line["serving"] = serving_sample(args.serve_requests, args.serve_max_steps)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"] = cpu_baseline(workload=args.workload)
     print(json.dumps(line), flush=True)
 
 

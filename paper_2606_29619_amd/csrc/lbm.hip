@@ -229,9 +229,10 @@ LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes) {
     bool bo, bv;
     rc = boundary_nodes(p, D, N, &nb, &bo, &bv);
     if (rc) return rc;
+    const size_t ntiles = 8 * (size_t)make_tiling(p->nx, p->ny, p->nz).per;
     *workspace_bytes = make_layout(Q, D, (size_t)N, sp, s, p->mask != nullptr,
-                                   p->scheme == LBM_SCHEME_LAGGED, nb, p->picard_iters > 0,
-                                   p->grad_eps != nullptr).total;
+                                   p->scheme == LBM_SCHEME_LAGGED, ntiles, nb,
+                                   p->picard_iters > 0, p->grad_eps != nullptr).total;
     return LBM_OK;
 }
 
@@ -287,8 +288,10 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     bool bc_outflow = false, bc_vp = false;
     rc = boundary_nodes(p, D, N, &nb, &bc_outflow, &bc_vp);
     if (rc) return rc;
-    const Layout L = make_layout(Q, D, (size_t)N, sp, s, solids, p->scheme == LBM_SCHEME_LAGGED, nb,
-                                 p->picard_iters > 0, p->grad_eps != nullptr);
+    const lbm::Tiling tiles = make_tiling(p->nx, p->ny, p->nz);
+    const Layout L = make_layout(Q, D, (size_t)N, sp, s, solids, p->scheme == LBM_SCHEME_LAGGED,
+                                 8 * (size_t)tiles.per, nb, p->picard_iters > 0,
+                                 p->grad_eps != nullptr);
     if (!dev_workspace) return fail(LBM_ERR_INVALID_ARG, "dev_workspace is NULL");
     if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
         return fail(LBM_ERR_WORKSPACE, "dev_workspace must be 256-byte aligned");
@@ -308,7 +311,7 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     h->ws = reinterpret_cast<char *>(dev_workspace);
     h->L = L;
-    h->tiles = make_tiling(p->nx, p->ny, p->nz);
+    h->tiles = tiles;
     h->step = 0;
     h->phase = 0;
     h->scheme = p->scheme;
@@ -346,6 +349,13 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
         return cleanup(fail(LBM_ERR_HIP, "upload of input fields failed: %s", hipGetErrorString(e)));
     if (solids && (e = hipMemcpyAsync(h->ws + L.mask, p->mask, (size_t)N, hipMemcpyHostToDevice, h->stream)) != hipSuccess)
         return cleanup(fail(LBM_ERR_HIP, "upload of mask failed: %s", hipGetErrorString(e)));
+    if (solids) {
+        uint8_t *ts = reinterpret_cast<uint8_t *>(h->ws + L.tsolid);
+        if (D == 2) hipLaunchKernelGGL(lbm::k_tile_solid<2>, cell_tiles(h), dim3(256), 0, h->stream, mask_ptr(h), grid_of(h), h->tiles, ts);
+        else hipLaunchKernelGGL(lbm::k_tile_solid<3>, cell_tiles(h), dim3(256), 0, h->stream, mask_ptr(h), grid_of(h), h->tiles, ts);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return cleanup(fail(LBM_ERR_HIP, "tile-flag kernel failed: %s", hipGetErrorString(e)));
+    }
     if (h->storage == LBM_F64)
         hipLaunchKernelGGL(lbm::k_static<double>, flat_grid(N), dim3(256), 0, h->stream, st, st + N, st + 2 * N,
                            ws_ptr<double>(h, L.eps), ws_ptr<double>(h, L.muD), ws_ptr<double>(h, L.muF), N, p->nu_f);

@@ -1193,17 +1193,34 @@ __global__ __launch_bounds__(256) void k_picard(const P4<T> *__restrict__ vin,
 }
 
 // Single-run kernels: workgroup w handles tile w of the run.
+//
+// Runs with solid cells: the solid-aware code (mask checks on every stencil and streaming
+// access) is needed only by tiles that have a solid cell within one cell (in any direction) of
+// one of their cells; every other tile takes the solid-free code, which evaluates the same
+// expressions.  tsolid[w] (k_tile_solid) tells which; null means every tile is solid-aware.
+__device__ __forceinline__ bool tile_free(const uint8_t *__restrict__ tsolid) {
+    return tsolid && !tsolid[blockIdx.x];
+}
+
 template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
 __global__ __launch_bounds__(256) void k_moments(const P *__restrict__ f,
                                                  const T *__restrict__ eps,
                                                  const T *__restrict__ muD,
                                                  const T *__restrict__ muF,
                                                  const uint8_t *__restrict__ mask,
+                                                 const uint8_t *__restrict__ tsolid,
                                                  P4<T> *__restrict__ m1_out,
                                                  P4<T> *__restrict__ m0_out, Grid g, Tiling tl,
                                                  Phys<T> ph) {
+    if constexpr (SOLIDS) {
+        if (tile_free(tsolid)) {
+            moments_body<D, T, P, false, PH, AD>(f, eps, muD, muF, mask, m1_out, m0_out, g, tl,
+                                                 ph, blockIdx.x);
+            return;
+        }
+    }
     moments_body<D, T, P, SOLIDS, PH, AD>(f, eps, muD, muF, mask, m1_out, m0_out, g, tl, ph,
-                                      blockIdx.x);
+                                          blockIdx.x);
 }
 
 template <int D, typename T, bool SOLIDS, bool AD>
@@ -1211,8 +1228,15 @@ __global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ own_
                                                   const P4<T> *__restrict__ m1,
                                                   const T *__restrict__ eps,
                                                   const uint8_t *__restrict__ mask,
+                                                  const uint8_t *__restrict__ tsolid,
                                                   P4<T> *__restrict__ m2_out, Grid g, Tiling tl,
                                                   Phys<T> ph) {
+    if constexpr (SOLIDS) {
+        if (tile_free(tsolid)) {
+            vcorrect_body<D, T, false, AD>(own_src, m1, eps, mask, m2_out, g, tl, ph, blockIdx.x);
+            return;
+        }
+    }
     vcorrect_body<D, T, SOLIDS, AD>(own_src, m1, eps, mask, m2_out, g, tl, ph, blockIdx.x);
 }
 
@@ -1222,8 +1246,16 @@ __global__ __launch_bounds__(256) void k_collide(P *__restrict__ f,
                                                  const T *__restrict__ eps,
                                                  const T *__restrict__ muD,
                                                  const T *__restrict__ muF,
-                                                 const uint8_t *__restrict__ mask, Grid g,
+                                                 const uint8_t *__restrict__ mask,
+                                                 const uint8_t *__restrict__ tsolid, Grid g,
                                                  Tiling tl, Phys<T> ph) {
+    if constexpr (SOLIDS) {
+        if (tile_free(tsolid)) {
+            collide_body<D, T, P, false, PH, AD>(f, m2, eps, muD, muF, mask, g, tl, ph,
+                                                 blockIdx.x);
+            return;
+        }
+    }
     collide_body<D, T, P, SOLIDS, PH, AD>(f, m2, eps, muD, muF, mask, g, tl, ph, blockIdx.x);
 }
 
@@ -1234,9 +1266,40 @@ __global__ __launch_bounds__(256) void k_fused(P *__restrict__ f, const P4<T> *_
                                                const T *__restrict__ eps,
                                                const T *__restrict__ muD,
                                                const T *__restrict__ muF,
-                                               const uint8_t *__restrict__ mask, Grid g,
+                                               const uint8_t *__restrict__ mask,
+                                               const uint8_t *__restrict__ tsolid, Grid g,
                                                Tiling tl, Phys<T> ph) {
-    fused_body<D, T, P, SOLIDS, PH, AD>(f, m1p, m2p, m1n, m2n, eps, muD, muF, mask, g, tl, ph, blockIdx.x);
+    if constexpr (SOLIDS) {
+        if (tile_free(tsolid)) {
+            fused_body<D, T, P, false, PH, AD>(f, m1p, m2p, m1n, m2n, eps, muD, muF, mask, g, tl,
+                                               ph, blockIdx.x);
+            return;
+        }
+    }
+    fused_body<D, T, P, SOLIDS, PH, AD>(f, m1p, m2p, m1n, m2n, eps, muD, muF, mask, g, tl, ph,
+                                        blockIdx.x);
+}
+
+// tsolid[w] = 1 when a cell of tile w, or a cell within one cell of one of them (faces, edges
+// and corners, through the periodic wrap), is solid.  Same grid and tile order as the passes;
+// workgroups past the last tile write nothing (the passes return before reading theirs).
+template <int D>
+__global__ __launch_bounds__(256) void k_tile_solid(const uint8_t *__restrict__ mask, Grid g,
+                                                    Tiling tl, uint8_t *__restrict__ tsolid) {
+    int x, y, z, x0, y0;
+    const int act = tile_cell(g, tl, blockIdx.x, x, y, z, x0, y0);
+    if (act < 0) return;  // uniform over the workgroup
+    int any = 0;
+    if (act) {
+        Nbr<D> nb;
+        nb.init(g, x, y, z);
+        unroll<0, Lat<D>::Q>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            any |= mask[nb.at(Lat<D>::c[i][0], Lat<D>::c[i][1], Lat<D>::c[i][2])];
+        });
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) tsolid[blockIdx.x] = any ? 1 : 0;
 }
 
 // Initial populations, eq. (eq_bc_f_bar) with lambda = dt = 1, from the moment fields (rho, v):

@@ -50,12 +50,15 @@ struct Layout {
     size_t bcell, bcode, bval;  // boundary-node list (wet-node boundaries)
     size_t m0, mx;              // (rho, v_0) records and a second velocity buffer (Picard)
     size_t deps;                // analytic porosity derivatives, D + D(D+1)/2 planes
+    size_t tsolid;              // per-tile flag: a solid cell within one cell of the tile
     size_t total;
 };
 
 // sp: bytes per population value; s: bytes per value of the static fields and moment records.
+// ntiles: workgroups of the tiled passes (solid runs keep one flag byte per tile).
 inline Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool solids, bool lagged,
-                          size_t nbnodes = 0, bool picard = false, bool analytic = false) {
+                          size_t ntiles, size_t nbnodes = 0, bool picard = false,
+                          bool analytic = false) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -84,6 +87,7 @@ inline Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool soli
     L.m0 = picard ? take(4 * N * s) : 0;
     L.mx = picard ? take(4 * N * s) : 0;
     L.deps = analytic ? take((size_t)(D + D * (D + 1) / 2) * N * s) : 0;
+    L.tsolid = solids ? take(ntiles) : 0;
     L.total = off;
     return L;
 }
@@ -173,6 +177,10 @@ T *ws_ptr(const lbm_solver *h, size_t off) {
 
 inline const uint8_t *mask_ptr(const lbm_solver *h) {
     return h->solids ? reinterpret_cast<const uint8_t *>(h->ws + h->L.mask) : nullptr;
+}
+
+inline const uint8_t *tsolid_ptr(const lbm_solver *h) {
+    return h->solids ? reinterpret_cast<const uint8_t *>(h->ws + h->L.tsolid) : nullptr;
 }
 
 // Enqueue the statistics of the current state into h->L.res (8 doubles, the lbm_stats slots)

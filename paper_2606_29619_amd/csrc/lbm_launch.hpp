@@ -22,7 +22,7 @@ void launch_moments(const lbm_solver *h, size_t m1_out) {
     hipLaunchKernelGGL((lbm::k_moments<D, T, P, S, PH, AD>), cell_tiles(h), dim3(256), 0, h->stream,
                        ws_ptr<const P>(h, h->L.f), ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
-                       ws_ptr<lbm::P4<T>>(h, m1_out), m0, grid_of(h), h->tiles, ph);
+                       tsolid_ptr(h), ws_ptr<lbm::P4<T>>(h, m1_out), m0, grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, bool S, bool AD>
@@ -40,8 +40,8 @@ void launch_vcorrect(const lbm_solver *h, size_t own_src, size_t m1, size_t m2_o
     auto ph = phys_of<T>(h);
     hipLaunchKernelGGL((lbm::k_vcorrect<D, T, S, AD>), cell_tiles(h), dim3(256), 0, h->stream,
                        ws_ptr<const lbm::P4<T>>(h, own_src), ws_ptr<const lbm::P4<T>>(h, m1),
-                       ws_ptr<const T>(h, h->L.eps), mask_ptr(h), ws_ptr<lbm::P4<T>>(h, m2_out),
-                       grid_of(h), h->tiles, ph);
+                       ws_ptr<const T>(h, h->L.eps), mask_ptr(h), tsolid_ptr(h),
+                       ws_ptr<lbm::P4<T>>(h, m2_out), grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, typename P, bool S, int PH, bool AD>
@@ -51,7 +51,7 @@ void launch_collide(const lbm_solver *h, size_t m2) {
                        ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
                        ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
-                       grid_of(h), h->tiles, ph);
+                       tsolid_ptr(h), grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, typename P, bool S, int PH, bool AD>
@@ -62,7 +62,8 @@ void launch_fused(const lbm_solver *h, int prev, int next) {
                        ws_ptr<const lbm::P4<T>>(h, h->L.m2[prev]),
                        ws_ptr<lbm::P4<T>>(h, h->L.m1[next]), ws_ptr<lbm::P4<T>>(h, h->L.m2[next]),
                        ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
-                       ws_ptr<const T>(h, h->L.muF), mask_ptr(h), grid_of(h), h->tiles, ph);
+                       ws_ptr<const T>(h, h->L.muF), mask_ptr(h), tsolid_ptr(h), grid_of(h),
+                       h->tiles, ph);
 }
 
 template <int D, typename T, typename P, bool S, bool AD>

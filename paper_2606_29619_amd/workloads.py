@@ -171,25 +171,51 @@ def channel_step_2d(nx=128, ny=64, x_step=64, phi_porous=0.4, K=1e-3, nu=1.0 / 6
                     meta={"smooth_width": smooth_width})
 
 
+def bump(s: np.ndarray, m: int = 1) -> np.ndarray:
+    """Localized bump B_m(s) = exp(1 - 1/(1 - s^m)) for s < 1, 0 for s >= 1 (eq. b_cinf)."""
+    s = np.asarray(s, dtype=np.float64)
+    out = np.zeros_like(s)
+    inner = s < 1.0
+    out[inner] = np.exp(1.0 - 1.0 / (1.0 - s[inner] ** m))
+    return out
+
+
 def sphere_duct_3d(nx=768, ny=384, nz=384, radius=96.0, center=None, phi=0.5, K=5e-3,
-                   nu=0.052, dp=1e-4, rho0=1.0, RT=1.0 / 3.0, steps=20000) -> Workload:
+                   nu=0.052, dp=1e-4, rho0=1.0, RT=1.0 / 3.0, steps=20000,
+                   bump_m=None) -> Workload:
     """Duct with solid walls on the y and z faces and a porous sphere; the pressure drop dp is
-    carried by an equivalent body force b_x = dp / (rho0 L_x) with p = rho RT."""
+    carried by an equivalent body force b_x = dp / (rho0 L_x) with p = rho RT.  bump_m None:
+    a sharp sphere (porosity phi and permeability K inside, free fluid outside).  bump_m = m:
+    the smooth inclusion of eq. (Porous_Cylinder_Profile) in 3D, eps = 1 - (1 - phi) B_m(s),
+    s = r^2 / R^2, with 1/kappa = B_m(s) / K and C_F = 0.55 / sqrt(kappa) following the same
+    bump (free fluid for s >= 1)."""
     center = center or (nx / 4.0, ny / 2.0, nz / 2.0)
-    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5,
-                          indexing="ij")
-    inside = ((x - center[0]) ** 2 + (y - center[1]) ** 2 + (z - center[2]) ** 2) < radius ** 2
-    eps = np.where(inside, phi, 1.0)
-    kappa = np.where(inside, K, np.inf)
+    eps = np.empty((nz, ny, nx))
+    kappa = np.empty((nz, ny, nx))
+    x = np.arange(nx) + 0.5 - center[0]
+    y = np.arange(ny) + 0.5 - center[1]
+    for k in range(nz):                      # plane by plane: the full grid is 113 M cells
+        zz = k + 0.5 - center[2]
+        r2 = (x[None, :] ** 2 + y[:, None] ** 2 + zz * zz) / (radius * radius)
+        if bump_m is None:
+            inside = r2 < 1.0
+            eps[k] = np.where(inside, phi, 1.0)
+            kappa[k] = np.where(inside, K, np.inf)
+        else:
+            B = bump(r2, bump_m)
+            eps[k] = 1.0 - (1.0 - phi) * B
+            with np.errstate(divide="ignore"):
+                kappa[k] = np.where(B > 0.0, K / np.where(B > 0.0, B, 1.0), np.inf)
     mask = np.zeros(eps.shape, dtype=np.uint8)
     mask[:, 0, :] = 1
     mask[:, -1, :] = 1
     mask[0, :, :] = 1
     mask[-1, :, :] = 1
-    return Workload(name=f"porous sphere in duct D3Q27 {nx}x{ny}x{nz}", lattice=27, eps=eps,
-                    kappa=kappa, forch=forchheimer(kappa), mask=mask, nu_f=nu, nu_eff_ref=nu,
-                    nu_eff_pow=0, b=(dp / (rho0 * nx), 0.0, 0.0), rho0=rho0, RT=RT,
-                    steps=steps)
+    kind = "sharp" if bump_m is None else f"bump m={bump_m}"
+    return Workload(name=f"porous sphere ({kind}) in duct D3Q27 {nx}x{ny}x{nz}", lattice=27,
+                    eps=eps, kappa=kappa, forch=forchheimer(kappa), mask=mask, nu_f=nu,
+                    nu_eff_ref=nu, nu_eff_pow=0, b=(dp / (rho0 * nx), 0.0, 0.0), rho0=rho0,
+                    RT=RT, steps=steps)
 
 
 def uniform_box(D=2, n=8, eps=0.5, K=0.1, cf=0.0, nu=0.05, b=(1e-4, 0.0, 0.0)) -> Workload:
@@ -234,6 +260,43 @@ def heterogeneous_channel_setup1(H: int, eps_bot=1.0, eps_top=0.5, phi_bot=0.1, 
     y = np.arange(1, H + 1) - 0.5
     psi = ((y / H) - phi_bot) / (1.0 - phi_top - phi_bot)
     return y, eps_bot + (eps_top - eps_bot) * smoothstep_cinf(psi)
+
+
+def heterogeneous_channel_setup2(H: int, eps_ctr=0.7, eps_wall=0.3, phi_ctr=0.4, phi_wall=0.1):
+    """Centerline-symmetric porosity (eq. Hetero_Channel_Setup_II_Profile): eps_ctr for
+    |y/H - 1/2| <= phi_ctr/2, eps_wall for |y/H - 1/2| >= 1/2 - phi_wall, the smoothstep in
+    between; sampled at the fluid rows (row j at y = j - 1/2)."""
+    y = np.arange(1, H + 1) - 0.5
+    psi = (np.abs(y / H - 0.5) - phi_ctr / 2.0) / (0.5 - phi_wall - phi_ctr / 2.0)
+    return y, eps_ctr + (eps_wall - eps_ctr) * smoothstep_cinf(psi)
+
+
+def ergun(eps: np.ndarray, dp: float):
+    """Ergun permeability kappa = dp^2 eps^3 / (150 (1 - eps)^2) (eq. kappa_Ergun) and the
+    Forchheimer coefficient C_F = F_eps / sqrt(kappa) with F_eps = 1.75 / sqrt(150 eps^3)
+    (eq. F_eps_Ergun)."""
+    eps = np.asarray(eps, dtype=np.float64)
+    kappa = dp * dp * eps ** 3 / (150.0 * (1.0 - eps) ** 2)
+    return kappa, 1.75 / np.sqrt(150.0 * eps ** 3) / np.sqrt(kappa)
+
+
+def channel_2d(H: int, eps_rows, kappa_rows, cf_rows=None, nu=0.1, b=1e-6, nx=1) -> Workload:
+    """D2Q9 channel periodic in x, solid rows y = 0 and y = H + 1 (halfway walls H apart,
+    fluid row j at y = j - 1/2); the wall rows continue the porosity of their neighbours."""
+    shape = (1, H + 2, nx)
+    eps = np.ones(shape)
+    kappa = np.full(shape, np.inf)
+    cf = np.zeros(shape)
+    eps[:, 1:-1, :] = np.asarray(eps_rows, dtype=np.float64).reshape(1, H, 1)
+    eps[:, 0, :] = eps[:, 1, :]
+    eps[:, -1, :] = eps[:, -2, :]
+    kappa[:, 1:-1, :] = np.asarray(kappa_rows, dtype=np.float64).reshape(1, H, 1)
+    if cf_rows is not None:
+        cf[:, 1:-1, :] = np.asarray(cf_rows, dtype=np.float64).reshape(1, H, 1)
+    mask = np.zeros(shape, np.uint8)
+    mask[:, 0, :] = mask[:, -1, :] = 1
+    return Workload(name=f"channel D2Q9 H={H}", lattice=9, eps=eps, kappa=kappa, forch=cf,
+                    mask=mask, nu_f=nu, nu_eff_ref=nu, nu_eff_pow=0, b=(b, 0.0, 0.0))
 
 
 def heterogeneous_channel_setup1_derivatives(H: int, eps_bot=1.0, eps_top=0.5, phi_bot=0.1,

@@ -63,6 +63,12 @@ def wave_setup(setup, L=48, JT=1.0, Ma0=0.1, Jnu=1.0, Jeta=None, ext=1, eps=0.5,
     """Linear plane-wave setups (I)-(IV) of Sec. 4.2 with the viscous-drag-balance drag
     parameters (VDB_params); the drag is scaled with the wave's own |k|^2.  Returns the oracle
     and the analytic decay rate."""
+    cfg, rate = wave_config(setup, L, JT, Ma0, Jnu, Jeta, ext, eps, nu_f)
+    return oracle.Oracle(cfg), rate
+
+
+def wave_config(setup, L=48, JT=1.0, Ma0=0.1, Jnu=1.0, Jeta=None, ext=1, eps=0.5, nu_f=0.01):
+    """The OracleConfig of a wave setup and its analytic decay rate."""
     RT = JT / 3.0
     k = 2 * math.pi / L
     kk = 2 * k * k if setup == "III" else k * k
@@ -94,7 +100,7 @@ def wave_setup(setup, L=48, JT=1.0, Ma0=0.1, Jnu=1.0, Jeta=None, ext=1, eps=0.5,
     pref = 2 * math.pi ** 2 * nu_f / L ** 2
     rate = {"I": 2 * pref * (Jnu + 1 + Ma0), "II": pref * (Jnu + Jeta_eff + 1 + 2 * Ma0),
             "III": 4 * pref * (Jnu + 1 + Ma0), "IV": pref * (Jnu + Jeta_eff + 1 + Ma0)}[setup]
-    return oracle.Oracle(cfg), rate
+    return cfg, rate
 
 
 def measure_decay(o, setup, steps, L):

@@ -260,6 +260,35 @@ def test_heterogeneous_channel_matches_bvp(visc_corr):
     assert np.ptp(rho) / rho.mean() < 5e-3     # measured 2.3e-3, falling as 1/H^2
 
 
+def _setup2_reference(H, nu, b, eps_ctr=0.7, eps_wall=0.3, phi_ctr=0.4, phi_wall=0.1):
+    """eq. Poiseuille_v_BVP for the Setup II porosity with Ergun permeability (d_p = H/10)."""
+    def eps_f(yy):
+        psi = (np.abs(yy / H - 0.5) - phi_ctr / 2) / (0.5 - phi_wall - phi_ctr / 2)
+        return eps_ctr + (eps_wall - eps_ctr) * workloads.smoothstep_cinf(psi)
+    muD_f = lambda yy: eps_f(yy) * nu / workloads.ergun(eps_f(yy), H / 10)[0]
+    muF_f = lambda yy: eps_f(yy) * workloads.ergun(eps_f(yy), H / 10)[1]
+    return _solve_channel_bvp(H, eps_f, muD_f, muF_f, b, nu)
+
+
+def test_setup2_channel_matches_bvp():
+    """Sec. 5.2.2, Setup II: centerline-symmetric porosity (eq. Hetero_Channel_Setup_II_Profile)
+    with eps_ctr + eps_wall = 1, Ergun permeability and Forchheimer coefficient (eqs. kappa_Ergun,
+    F_eps_Ergun, d_p = H/10); the steady profile solves eq. Poiseuille_v_BVP at second order
+    (measured 8.6e-3 -> 2.4e-3 for H = 32 -> 64 at Hg = b H^3 / nu^2 = 40)."""
+    errs = []
+    for H in (32, 64):
+        nu = 0.1
+        b = 40.0 * nu * nu / H ** 3
+        y, e = workloads.heterogeneous_channel_setup2(H)
+        k, cf = workloads.ergun(e, H / 10)
+        o = oc.channel(2, H, e, k, cf, nu=nu, b=b)
+        oc.run_to_steady(o, tol=1e-11, chunk=500)
+        _, v = oc.profile(o)
+        ref = _setup2_reference(H, nu, b)(y)
+        errs.append(np.abs(v - ref).max() / ref.max())
+    assert errs[1] < 3e-3 and errs[0] / errs[1] > 3.0, errs
+
+
 def _setup1_error(H, analytic, scale=1.0):
     """Setup I (Sec. 5.2.2, Da = 1e-2, V0 = 0.01): max deviation of the steady profile from the
     target problem (Poiseuille_v_BVP), relative to its maximum, and the profile."""

@@ -213,6 +213,37 @@ def test_lagged_scheme_matches_oracle(case):
     assert _rel(v_lag.cpu().numpy(), v_two.cpu().numpy()) > 1e-9
 
 
+@pytest.mark.parametrize("D,lagged,storage", [(3, False, "f64"), (3, True, "f64"),
+                                               (2, False, "f64"), (3, False, "f16")])
+def test_solid_free_tiles_match_oracle(D, lagged, storage):
+    """A large domain whose few solid cells sit in one corner region and one thin wall: most
+    workgroup tiles have no solid cell within one cell and take the solid-free code, the others
+    the solid-aware code, in one launch.  FP64 must still match the oracle to 1e-12 (both AA
+    phases at the checks); FP16 storage (porous shift) stays within its bulk bounds."""
+    if D == 3:
+        shape = (6, 24, 300)
+        w = workloads.random_porosity_3d(shape=shape, seed=4, ell=3.0, nu=0.03, b=2e-4)
+        m = np.zeros(shape, np.uint8)
+        m[1:3, 5:8, 200:230] = 1             # a block inside the domain
+        m[:, 0, :] = 1                       # one wall row (its neighbours y = 1, y = ny - 1)
+    else:
+        shape = (1, 40, 400)
+        w = workloads.random_porosity_2d(nx=400, ny=40, seed=4, ell=4.0, nu=0.04, b=2e-4)
+        m = np.zeros(shape, np.uint8)
+        m[0, 18:21, 100:103] = 1
+    w.mask = m
+    st = capi.LBM_F64 if storage == "f64" else capi.LBM_F16_SHIFTED
+    s, o = _run_pair(w, 41, storage=st, lagged=lagged, shift=capi.LBM_SHIFT_POROUS)
+    s.step(40)
+    o.step(40)
+    errs = _field_errors(s, o)
+    _print(f"solid-free tiles D{D} lagged={lagged} {storage}:", errs)
+    if storage == "f64":
+        assert max(errs.values()) <= FP64_TOL, errs
+    else:
+        assert errs["f"] < 1e-4 and errs["rho"] < 1e-4, errs
+
+
 def test_lagged_restart_takes_a_two_pass_step():
     """After lbm_set_populations the lagged history restarts: the next step is a two-pass step,
     as in the oracle, and the run continues lagged from there."""
