@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_bc_records(const P *__restrict__ f,
         for (int a = 0; a < D; ++a) s = s + vb[a] * vb[a];
         const T vm = sq(s);
         if (bounce_back_density) {
-            rho = dv(sum, e);
+            rho = div_rn(sum, e);
         } else {
             const T aperp = ((e * bperp - ld(muD, n) * vperp) - (ld(muF, n) * vm) * vperp) +
                             ph.RT * gperp;

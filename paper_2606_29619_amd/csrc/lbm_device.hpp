@@ -102,6 +102,11 @@ constexpr int hess_plane(int a, int b) {
 // ---- arithmetic policy -------------------------------------------------------------------
 __device__ __forceinline__ double dv(double a, double b) { return a / b; }
 __device__ __forceinline__ float dv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// Correctly rounded quotient, for rho = S / eps: eps rho then scales the equilibria, whose sum
+// is the cell's mass after collision, and rcp's rounding is not symmetric (FP32 runs lost
+// mass steadily with it).
+__device__ __forceinline__ double div_rn(double a, double b) { return a / b; }
+__device__ __forceinline__ float div_rn(float a, float b) { return a / b; }
 __device__ __forceinline__ double sq(double x) { return sqrt(x); }
 __device__ __forceinline__ float sq(float x) { return __builtin_amdgcn_sqrtf(x); }
 
@@ -957,7 +962,7 @@ __device__ __forceinline__ Rec<T> cell_moments(const T fi[], const E &ev,
         });
     });
     const T e = ev.at(0, 0, 0);
-    const T rho = dv(S, e);
+    const T rho = div_rn(S, e);
     T v0[3];
     unroll<0, D>([&](auto ia) {
         constexpr int a = decltype(ia)::value;
