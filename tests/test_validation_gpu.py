@@ -33,10 +33,10 @@ def _gpu():
 
 
 class _GpuRun:
-    """The oracle's step / moments interface over a GPU solver (FP64 storage)."""
+    """The oracle's step / moments / stats interface over a GPU solver."""
 
-    def __init__(self, params, keep):
-        self.s = capi.Solver(params, keep)
+    def __init__(self, solver):
+        self.s = solver
 
     def step(self, n):
         self.s.step(n)
@@ -55,7 +55,7 @@ def _wave_run(cfg):
                                RT=cfg.RT, nu_f=cfg.nu_f, nu_eff_ref=cfg.nu_eff_ref,
                                nu_eff_pow=cfg.nu_eff_pow, eta_eff=cfg.eta_eff, b=cfg.b,
                                rho0=cfg.rho0, rho_init=cfg.rho_init, v_init=cfg.v_init)
-    return _GpuRun(p, keep)
+    return _GpuRun(capi.Solver(p, keep))
 
 
 @pytest.mark.parametrize("case", [
@@ -78,9 +78,7 @@ def test_decay_rates_on_gpu(case):
 
 
 def _steady_channel(w):
-    s = capi.Solver.from_workload(w, storage=capi.LBM_F64)
-    run = _GpuRun.__new__(_GpuRun)
-    run.s = s
+    run = _GpuRun(capi.Solver.from_workload(w, storage=capi.LBM_F64))
     steps = oc.run_to_steady(run, tol=1e-11, chunk=1000, max_steps=400000)
     _, v, _ = run.moments()
     return steps, v[0, 0, 1:-1, 0]
@@ -118,3 +116,4 @@ def test_setup2_channel_on_gpu():
     err = np.abs(v - ref).max() / ref.max()
     print(f"setup II Hg=1e6: {steps} steps, error {err:.3e}", flush=True)
     assert err < 2e-3, err
+
