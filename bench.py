@@ -108,6 +108,25 @@ def cpu_baseline(budget_s=15.0, workload="box"):
                       f"{dt:.1f} s"}
 
 
+def copy_bandwidth(nbytes=2 << 30, reps=10):
+    """Practical HBM ceiling: a plain device-to-device copy of nbytes (read + write bytes per
+    second), the best of reps, timed with events on the current stream."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * nbytes / best / 1e9, 1)
+
+
 def serving_sample(n_requests, max_steps):
     """The first n_requests of the serving stream (seed 0), FP32 and FP16-shifted storage:
     a closed batch measures the server's capacity (requests/s), then the same requests arrive
@@ -264,6 +283,9 @@ def main():
     solver.close()
     del solver
     torch.cuda.empty_cache()
+    copy = copy_bandwidth()
+    line["roofline"]["copy_GBps"] = copy
+    line["roofline"]["frac_of_copy"] = round(achieved / copy, 4)
     if args.copy_probe_mib:
         nb = args.copy_probe_mib * 2 ** 20
         a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
