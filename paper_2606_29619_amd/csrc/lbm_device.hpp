@@ -835,11 +835,23 @@ __device__ __forceinline__ void corrected_velocity(const P4<T> *__restrict__ m1,
                                                    const Grid &g, const Nbr<D> &nb,
                                                    const Rec<T> &own, const CellStatic<D, T> &cs,
                                                    T v[3]) {
-    Rec<T> rec[3][2];
-    bool fl[3][2];
-    load_stencil<D, T, SOLIDS>(m1, ev, mask, g, nb, rec, fl);
-    T dn[3];
-    delta_nu<D, T, SOLIDS>(m1, eps, mask, g, nb, own, rec, fl, cs.ge, cs.H, cs.vs, dn);
+    // Where eps is locally uniform (zero gradient and Hessian: free fluid, or the plateau of a
+    // porous region) every term of Delta_nu carries a factor of them and vanishes, and the
+    // stencil need not be read: v = v^(1) + 0.
+    bool flat = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        flat = flat && cs.ge[a] == T(0);
+#pragma unroll
+        for (int b = 0; b < D; ++b) flat = flat && cs.H[a][b] == T(0);
+    }
+    T dn[3] = {T(0), T(0), T(0)};
+    if (!flat) {
+        Rec<T> rec[3][2];
+        bool fl[3][2];
+        load_stencil<D, T, SOLIDS>(m1, ev, mask, g, nb, rec, fl);
+        delta_nu<D, T, SOLIDS>(m1, eps, mask, g, nb, own, rec, fl, cs.ge, cs.H, cs.vs, dn);
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) v[a] = T(0);
 #pragma unroll
