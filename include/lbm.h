@@ -138,7 +138,10 @@ typedef struct lbm_params {
     int scheme;           /* LBM_SCHEME_TWO_PASS or LBM_SCHEME_LAGGED */
     int shift;            /* LBM_SHIFT_WEIGHTS or LBM_SHIFT_POROUS (16-bit storage only) */
     int nx, ny, nz;       /* >= 1; nz must be 1 for D2Q9 */
-    double RT;            /* lattice temperature RT > 0 (1/3 is the lattice reference) */
+    double RT;            /* lattice temperature RT > 0 (1/3 is the lattice reference); FP32
+                             arithmetic uses 1 - fl(1 - fl(RT)), whose complement is exact
+                             (for 1/3: 1.2e-7 relative above it), so that the equilibria of a
+                             cell at rest sum to its mass */
     double nu_f;          /* fluid viscosity in the Darcy coefficient mu_D = eps nu_f / kappa
                              (eq. mu_D_Ergun_perm) */
     double nu_eff_ref;    /* effective shear viscosity nu_eff(eps) = nu_eff_ref * eps^nu_eff_pow > 0;

@@ -132,9 +132,9 @@ namespace lbmh {
 template <typename T>
 T lattice_temperature(double RT) {
     if constexpr (std::is_same_v<T, float>) {
-        volatile float rt = (float)RT;
-        volatile float c = 1.0f - rt;
-        return 1.0f - c;
+        const float rt = (float)RT;
+        const float c = 1.0f - rt;  // rounded: 1 - rt needs one bit more than a float for 1/3
+        return 1.0f - c;            // exact (Sterbenz), and 1 - (1 - c) == c
     } else {
         return (T)RT;
     }
