@@ -109,8 +109,9 @@ def cpu_baseline(budget_s=15.0, workload="box"):
 
 
 def copy_bandwidth(nbytes=2 << 30, reps=10):
-    """Practical HBM ceiling: a plain device-to-device copy of nbytes (read + write bytes per
-    second), the best of reps, timed with events on the current stream."""
+    """Practical HBM ceiling: a streaming copy of nbytes through torch's vectorised elementwise
+    kernel (b = a + 0; read + write bytes per second; it moves about 20 % more than
+    Tensor.copy_'s blit kernel), the best of reps, timed with events on the current stream."""
     import torch
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
@@ -118,7 +119,7 @@ def copy_bandwidth(nbytes=2 << 30, reps=10):
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        b.copy_(a)
+        torch.add(a, 0.0, out=b)
         e1.record()
         e1.synchronize()
         best = min(best, e0.elapsed_time(e1) * 1e-3)
