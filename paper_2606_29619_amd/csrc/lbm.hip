@@ -93,6 +93,12 @@ int check_handle(const lbm_solver *h) {
     return LBM_OK;
 }
 
+// Packed-row tiles serve the storages whose kernels read porosity from global memory (the
+// 16-bit kernels stage it in LDS over rectangular tiles).
+bool packed_rows_ok(const lbm_params *p) {
+    return p->storage == LBM_F32 || p->storage == LBM_F64;
+}
+
 int validate_shape(const lbm_params *p, int *D, int *Q, size_t *sp, size_t *s, int64_t *N) {
     if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
     if (p->lattice == LBM_D2Q9) { *D = 2; *Q = 9; }
@@ -229,7 +235,7 @@ LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes) {
     bool bo, bv;
     rc = boundary_nodes(p, D, N, &nb, &bo, &bv);
     if (rc) return rc;
-    const size_t ntiles = 8 * (size_t)make_tiling(p->nx, p->ny, p->nz).per;
+    const size_t ntiles = 8 * (size_t)make_tiling(p->nx, p->ny, p->nz, packed_rows_ok(p)).per;
     *workspace_bytes = make_layout(Q, D, (size_t)N, sp, s, p->mask != nullptr,
                                    p->scheme == LBM_SCHEME_LAGGED, ntiles, nb,
                                    p->picard_iters > 0, p->grad_eps != nullptr).total;
@@ -288,7 +294,7 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     bool bc_outflow = false, bc_vp = false;
     rc = boundary_nodes(p, D, N, &nb, &bc_outflow, &bc_vp);
     if (rc) return rc;
-    const lbm::Tiling tiles = make_tiling(p->nx, p->ny, p->nz);
+    const lbm::Tiling tiles = make_tiling(p->nx, p->ny, p->nz, packed_rows_ok(p));
     const Layout L = make_layout(Q, D, (size_t)N, sp, s, solids, p->scheme == LBM_SCHEME_LAGGED,
                                  8 * (size_t)tiles.per, nb, p->picard_iters > 0,
                                  p->grad_eps != nullptr);

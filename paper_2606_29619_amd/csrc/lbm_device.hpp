@@ -879,7 +879,8 @@ __device__ __forceinline__ void cell_equilibria(const P4<T> *__restrict__ m2, co
 // ------------------------------------------------------------------------------------------
 // Kernels, one thread per cell.  A workgroup of 256 threads owns a tx x ty x 1 tile
 // (tx * ty = 256, tx = 256 for rows of 192 cells or more, so that the x-shifted accesses of the
-// swapped AA phase stay inside one workgroup).  Tiles are ordered so that stencil neighbours
+// swapped AA phase stay inside one workgroup), or, with packed rows, 256 consecutive cells of a
+// plane (see Tiling::packed).  Tiles are ordered so that stencil neighbours
 // are processed close in time on the same XCD: the (tile-row, plane) grid is cut into blocks of
 // by x bz tile rows, each block is traversed x-fastest then y then z, the blocks y-fastest then
 // z, and the eight XCDs take contiguous ranges of that order (workgroup w runs on XCD w mod 8).
@@ -893,6 +894,12 @@ struct Tiling {
     int by, bz;       // block of tile rows
     int nby, nbz;     // blocks along y and z
     uint32_t per;     // tiles per XCD (padded order)
+    // Packed rows (x extent not a multiple of 64, no LDS staging): a tile is 256 consecutive
+    // cells of one z-plane in x-fastest order, wrapping from row to row, so that no wave is
+    // left partly idle at the end of every row; "tile rows" are then these chunks.
+    int packed;
+    uint32_t pn;      // cells per plane, nx * ny
+    uint64_t mnx;     // ceil(2^64 / nx): p / nx = umulhi64(p, mnx) for p < 2^32, nx >= 2
 };
 
 // Cell of this thread in tile w: returns -1 when the whole tile lies outside the order (the
@@ -909,6 +916,17 @@ __device__ __forceinline__ int tile_cell(const Grid &g, const Tiling &tl, uint32
     const uint32_t blk = r / rows_per_block, in = r % rows_per_block;
     const uint32_t ty = (blk % (uint32_t)tl.nby) * (uint32_t)tl.by + in % (uint32_t)tl.by;
     const uint32_t tz = (blk / (uint32_t)tl.nby) * (uint32_t)tl.bz + in / (uint32_t)tl.by;
+    if (tl.packed) {
+        if (ty >= (uint32_t)tl.nty || tz >= (uint32_t)g.nz) return -1;  // partial block
+        const uint32_t p = ty * 256u + threadIdx.x;
+        x0 = y0 = 0;
+        z = (int)tz;
+        if (p >= tl.pn) return 0;
+        const uint32_t q = g.nx > 1 ? (uint32_t)__umul64hi((uint64_t)p, tl.mnx) : p;
+        y = (int)q;
+        x = (int)(p - q * (uint32_t)g.nx);
+        return 1;
+    }
     x0 = (int)(tx * (uint32_t)tl.tx);
     y0 = (int)(ty * (uint32_t)tl.ty);
     z = (int)tz;

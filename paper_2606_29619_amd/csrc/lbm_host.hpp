@@ -163,13 +163,30 @@ inline lbm::Grid grid_of(const lbm_solver *h) { return lbm::Grid{h->nx, h->ny, h
 
 inline dim3 flat_grid(int64_t total) { return dim3((unsigned)((total + 255) / 256)); }
 
-inline lbm::Tiling make_tiling(int nx, int ny, int nz) {
-    lbm::Tiling t;
-    t.tx = nx >= 192 ? 256 : (nx >= 96 ? 128 : 64);
-    t.ltx = t.tx == 256 ? 8 : (t.tx == 128 ? 7 : 6);
-    t.ty = 256 / t.tx;
-    t.ntx = (nx + t.tx - 1) / t.tx;
-    t.nty = (ny + t.ty - 1) / t.ty;
+// Tiles of the cell passes.  Rectangular tiles (256 x 1, 128 x 2 or 64 x 4 cells) when the x
+// extent is a multiple of 64 or the kernels stage porosity in LDS (16-bit storage, which needs
+// rectangular halos); packed rows otherwise, so that rows of, say, 70 cells do not leave most
+// of a second wave idle.
+inline lbm::Tiling make_tiling(int nx, int ny, int nz, bool packed_ok = false) {
+    lbm::Tiling t{};
+    if (const char *e = std::getenv("LBM_TILE_PACKED"))  // "0": rectangular tiles only (A/B runs)
+        packed_ok = packed_ok && std::atoi(e) != 0;
+    if (packed_ok && nx % 64 != 0) {
+        t.packed = 1;
+        t.tx = 256;
+        t.ltx = 8;
+        t.ty = 1;
+        t.ntx = 1;
+        t.pn = (uint32_t)nx * (uint32_t)ny;
+        t.nty = (int)((t.pn + 255u) / 256u);
+        t.mnx = nx >= 2 ? ~uint64_t(0) / (uint64_t)nx + 1 : 0;
+    } else {
+        t.tx = nx >= 192 ? 256 : (nx >= 96 ? 128 : 64);
+        t.ltx = t.tx == 256 ? 8 : (t.tx == 128 ? 7 : 6);
+        t.ty = 256 / t.tx;
+        t.ntx = (nx + t.tx - 1) / t.tx;
+        t.nty = (ny + t.ty - 1) / t.ty;
+    }
     t.ntz = nz;
     int by = 64, bz = 4;  // tile rows per block along y and z (measured best on 256^3)
     if (const char *e = std::getenv("LBM_TILE_BLOCK")) {  // "BYxBZ", for tuning sweeps
