@@ -14,7 +14,7 @@
 namespace lbmh {
 
 // ---- kernel launchers, dispatched on (lattice, arithmetic type T, population storage type P,
-// solids, phase) ------------------------------------------------------------------------------
+// solids, phase, derivative source) -------------------------------------------------------------
 template <int D, typename T, typename P, bool S, int PH, bool AD>
 void launch_moments(const lbm_solver *h, size_t m1_out) {
     auto ph = phys_of<T>(h);
