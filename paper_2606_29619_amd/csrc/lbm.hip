@@ -370,6 +370,18 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
                            ws_ptr<float>(h, L.eps), ws_ptr<float>(h, L.muD), ws_ptr<float>(h, L.muF), N, p->nu_f);
     if ((e = hipGetLastError()) != hipSuccess)
         return cleanup(fail(LBM_ERR_HIP, "static-field kernel failed: %s", hipGetErrorString(e)));
+    if (!h->analytic) {  // after the static-field kernel has written eps (same stream)
+        uint8_t *tf = reinterpret_cast<uint8_t *>(h->ws + L.tflat);
+        if (h->storage == LBM_F64) {
+            if (D == 2) hipLaunchKernelGGL((lbm::k_tile_flat<2, double>), cell_tiles(h), dim3(256), 0, h->stream, ws_ptr<const double>(h, L.eps), grid_of(h), h->tiles, tf);
+            else hipLaunchKernelGGL((lbm::k_tile_flat<3, double>), cell_tiles(h), dim3(256), 0, h->stream, ws_ptr<const double>(h, L.eps), grid_of(h), h->tiles, tf);
+        } else {
+            if (D == 2) hipLaunchKernelGGL((lbm::k_tile_flat<2, float>), cell_tiles(h), dim3(256), 0, h->stream, ws_ptr<const float>(h, L.eps), grid_of(h), h->tiles, tf);
+            else hipLaunchKernelGGL((lbm::k_tile_flat<3, float>), cell_tiles(h), dim3(256), 0, h->stream, ws_ptr<const float>(h, L.eps), grid_of(h), h->tiles, tf);
+        }
+        if ((e = hipGetLastError()) != hipSuccess)
+            return cleanup(fail(LBM_ERR_HIP, "flat-tile kernel failed: %s", hipGetErrorString(e)));
+    }
     const double *rho_st = nullptr, *v_st = nullptr;
     if (p->rho_init) {
         if ((e = hipMemcpyAsync(st, p->rho_init, NB, hipMemcpyHostToDevice, h->stream)) != hipSuccess)

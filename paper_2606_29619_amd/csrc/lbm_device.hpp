@@ -1294,14 +1294,35 @@ __global__ __launch_bounds__(256) void k_moments(const P *__restrict__ f,
                                           blockIdx.x);
 }
 
+// Velocity correction of a tile whose every cell has a uniform porosity neighbourhood: Delta_nu
+// vanishes, v = v^(1) + 0 (the value of the full evaluation), from the cell's own record only.
+// A solid cell's record is zero (the moment pass writes it so), and so is its copy: no mask
+// read is needed.
+template <int D, typename T>
+__device__ __forceinline__ void vcorrect_flat_body(const P4<T> *__restrict__ own_src,
+                                                   P4<T> *__restrict__ m2_out, Grid g,
+                                                   Tiling tl, uint32_t wg) {
+    int x, y, z, x0_, y0_;
+    if (tile_cell(g, tl, wg, x, y, z, x0_, y0_) != 1) return;
+    const uint32_t n = (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+    const P4<T> q = ld(own_src, n);
+    *at(m2_out, n) = pack(q.x, q.y + T(0), q.z + T(0), D == 3 ? q.w + T(0) : T(0));
+}
+
 template <int D, typename T, bool SOLIDS, bool AD>
 __global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ own_src,
                                                   const P4<T> *__restrict__ m1,
                                                   const T *__restrict__ eps,
                                                   const uint8_t *__restrict__ mask,
                                                   const uint8_t *__restrict__ tsolid,
+                                                  const uint8_t *__restrict__ tflat,
                                                   P4<T> *__restrict__ m2_out, Grid g, Tiling tl,
                                                   Phys<T> ph) {
+    // tflat[w] = 0: no cell of tile w has a porosity gradient or Hessian (k_tile_flat)
+    if (tflat && !tflat[blockIdx.x]) {
+        vcorrect_flat_body<D, T>(own_src, m2_out, g, tl, blockIdx.x);
+        return;
+    }
     if constexpr (SOLIDS) {
         if (tile_free(tsolid)) {
             vcorrect_body<D, T, false, AD>(own_src, m1, eps, mask, m2_out, g, tl, ph, blockIdx.x);
@@ -1371,6 +1392,29 @@ __global__ __launch_bounds__(256) void k_tile_solid(const uint8_t *__restrict__ 
     }
     any = __syncthreads_or(any);
     if (threadIdx.x == 0) tsolid[blockIdx.x] = any ? 1 : 0;
+}
+
+// tflat[w] = 1 when some cell of tile w has a porosity neighbourhood (the 3 x 3 (x 3) cells
+// around it, through the periodic wrap) that is not uniform, i.e. when differenced porosity
+// derivatives can be nonzero there; 0 lets the velocity correction skip the whole tile.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_tile_flat(const T *__restrict__ eps, Grid g, Tiling tl,
+                                                   uint8_t *__restrict__ tflat) {
+    int x, y, z, x0, y0;
+    const int act = tile_cell(g, tl, blockIdx.x, x, y, z, x0, y0);
+    if (act < 0) return;  // uniform over the workgroup
+    int bumpy = 0;
+    if (act) {
+        Nbr<D> nb;
+        nb.init(g, x, y, z);
+        const T e0 = ld(eps, nb.self());
+        unroll<0, Lat<D>::Q>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            bumpy |= ld(eps, nb.at(Lat<D>::c[i][0], Lat<D>::c[i][1], Lat<D>::c[i][2])) != e0;
+        });
+    }
+    bumpy = __syncthreads_or(bumpy);
+    if (threadIdx.x == 0) tflat[blockIdx.x] = bumpy ? 1 : 0;
 }
 
 // Initial populations, eq. (eq_bc_f_bar) with lambda = dt = 1, from the moment fields (rho, v):

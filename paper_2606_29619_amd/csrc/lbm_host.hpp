@@ -52,6 +52,7 @@ struct Layout {
     size_t m0, mx;              // (rho, v_0) records and a second velocity buffer (Picard)
     size_t deps;                // analytic porosity derivatives, D + D(D+1)/2 planes
     size_t tsolid;              // per-tile flag: a solid cell within one cell of the tile
+    size_t tflat;               // per-tile flag: a porosity gradient somewhere in the tile
     size_t total;
 };
 
@@ -89,6 +90,7 @@ inline Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool soli
     L.mx = picard ? take(4 * N * s) : 0;
     L.deps = analytic ? take((size_t)(D + D * (D + 1) / 2) * N * s) : 0;
     L.tsolid = solids ? take(ntiles) : 0;
+    L.tflat = analytic ? 0 : take(ntiles);
     L.total = off;
     return L;
 }
@@ -215,6 +217,11 @@ inline const uint8_t *mask_ptr(const lbm_solver *h) {
 
 inline const uint8_t *tsolid_ptr(const lbm_solver *h) {
     return h->solids ? reinterpret_cast<const uint8_t *>(h->ws + h->L.tsolid) : nullptr;
+}
+
+// Flat-tile flags exist for differenced porosity derivatives only (analytic runs: null).
+inline const uint8_t *tflat_ptr(const lbm_solver *h) {
+    return h->analytic ? nullptr : reinterpret_cast<const uint8_t *>(h->ws + h->L.tflat);
 }
 
 // Enqueue the statistics of the current state into h->L.res (8 doubles, the lbm_stats slots)

@@ -40,7 +40,7 @@ void launch_vcorrect(const lbm_solver *h, size_t own_src, size_t m1, size_t m2_o
     auto ph = phys_of<T>(h);
     hipLaunchKernelGGL((lbm::k_vcorrect<D, T, S, AD>), cell_tiles(h), dim3(256), 0, h->stream,
                        ws_ptr<const lbm::P4<T>>(h, own_src), ws_ptr<const lbm::P4<T>>(h, m1),
-                       ws_ptr<const T>(h, h->L.eps), mask_ptr(h), tsolid_ptr(h),
+                       ws_ptr<const T>(h, h->L.eps), mask_ptr(h), tsolid_ptr(h), tflat_ptr(h),
                        ws_ptr<lbm::P4<T>>(h, m2_out), grid_of(h), h->tiles, ph);
 }
 

@@ -317,7 +317,8 @@ def test_analytic_derivative_validation_and_footprint():
     base = capi.lbm_footprint(p)
     g, h = np.zeros((3,) + shape), np.zeros((6,) + shape)
     q, _kq = _params(shape=shape, grad_eps=g, hess_eps=h)
-    assert capi.lbm_footprint(q) - base >= 9 * N * 4
+    # nine planes of N values more; the analytic run drops the flat-tile flags (256 B here)
+    assert capi.lbm_footprint(q) - base >= 9 * N * 4 - 256
     r, _kr = _params(shape=shape, grad_eps=g)
     with pytest.raises(capi.LbmError) as ei:
         capi.lbm_footprint(r)
