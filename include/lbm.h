@@ -40,7 +40,7 @@ extern "C" {
 /* Return codes. */
 #define LBM_OK 0
 #define LBM_ERR_INVALID_ARG -1   /* a parameter, field value or pointer is out of its domain */
-#define LBM_ERR_UNSUPPORTED -2   /* a valid combination this build does not implement */
+#define LBM_ERR_UNSUPPORTED -2   /* a valid combination this library does not implement */
 #define LBM_ERR_WORKSPACE -3     /* the device workspace is too small or misaligned */
 #define LBM_ERR_HIP -4           /* a HIP runtime call or kernel launch failed */
 #define LBM_ERR_NONFINITE -5     /* the state holds NaN or Inf (reported by lbm_residual) */

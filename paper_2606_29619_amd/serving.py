@@ -7,7 +7,7 @@ field (correlation length 16) with phi_min uniform in [0.2, 0.6], Kozeny-Carman 
 nu uniform in [0.005, 0.05], body force 1e-6 along x, periodic box, run until the relative L2
 change of v over 100 steps falls below 1e-7 (or a step cap, reported as censored).
 
-The driver only submits at the arrival times and reads results back; admission, batching and
+This module only submits at the arrival times and reads results back; admission, batching and
 retirement are the library's.
 
     python -m paper_2606_29619_amd.serving --requests 512 --storage f32 --max-steps 200000

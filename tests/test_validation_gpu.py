@@ -32,7 +32,7 @@ def _gpu():
     torch.cuda.synchronize()
 
 
-class _GpuRun:
+class _DeviceRun:
     """The oracle's step / moments / stats interface over a GPU solver."""
 
     def __init__(self, solver):
@@ -55,7 +55,7 @@ def _wave_run(cfg):
                                RT=cfg.RT, nu_f=cfg.nu_f, nu_eff_ref=cfg.nu_eff_ref,
                                nu_eff_pow=cfg.nu_eff_pow, eta_eff=cfg.eta_eff, b=cfg.b,
                                rho0=cfg.rho0, rho_init=cfg.rho_init, v_init=cfg.v_init)
-    return _GpuRun(capi.Solver(p, keep))
+    return _DeviceRun(capi.Solver(p, keep))
 
 
 @pytest.mark.parametrize("case", [
@@ -78,7 +78,7 @@ def test_decay_rates_on_gpu(case):
 
 
 def _steady_channel(w):
-    run = _GpuRun(capi.Solver.from_workload(w, storage=capi.LBM_F64))
+    run = _DeviceRun(capi.Solver.from_workload(w, storage=capi.LBM_F64))
     steps = oc.run_to_steady(run, tol=1e-11, chunk=1000, max_steps=400000)
     _, v, _ = run.moments()
     return steps, v[0, 0, 1:-1, 0]
