@@ -204,6 +204,25 @@ struct Nbr {
         return xs[cx + 1] + row[cy + 1][cz + 1];
     }
     __device__ __forceinline__ uint32_t self() const { return at(0, 0, 0); }
+    // A copy whose row and column indices the compiler cannot prove equal to these.  In the
+    // swapped phase the population slots are the stencil neighbours whose porosity and records
+    // were read first; addresses built from the copy are recomputed (one add each) next to the
+    // population loads and stores instead of being held in registers from those stencil loads
+    // (FP32 lagged pass 170 -> 121 registers, 16-bit collision 124 -> 112).  The empty asm
+    // statements emit no instruction.
+    __device__ __forceinline__ Nbr opaque() const {
+        Nbr r = *this;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            asm volatile("" : "+v"(r.xs[j]));
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (D == 2 && k != 1) continue;
+                asm volatile("" : "+v"(r.row[j][k]));
+            }
+        }
+        return r;
+    }
     // Neighbour along axis a at offset k (|k| <= 2).
     __device__ __forceinline__ uint32_t axis(const Grid &g, int a, int k) const {
         if (k == 1 || k == -1) {
@@ -1145,20 +1164,26 @@ __device__ __forceinline__ void collide_body(P *__restrict__ f,
     const T two_beta = T(2) * cs.vs.beta;
     const T omb = T(1) - cs.vs.beta;
     const float base = own_base<P>(ev.at(0, 0, 0), ph);
+    // Swapped phase: population addresses recomputed from an opaque copy of the neighbourhood
+    // (16-bit storage 0.76 -> 0.68 ms on the 256^3 box, FP64 2 % faster).  FP32 storage keeps
+    // the addresses of the stencil loads: 7 instead of 4 waves per SIMD left its collision as
+    // fast as before, and the recomputation cost 1 %.
+    constexpr bool kOpaque = PH == 1 && sizeof(P) != 4;
+    const Nbr<D> nbp = kOpaque ? nb.opaque() : nb;
     unroll<0, PairGroups<D>::n>([&](auto gg) {
         constexpr int k = decltype(gg)::value;
         constexpr int g0 = PairGroups<D>::begin(k), g1 = PairGroups<D>::begin(k + 1);
         T fi[g1 - g0];
         unroll<g0, g1>([&](auto ii) {
             constexpr int i = decltype(ii)::value;
-            fi[i - g0] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
+            fi[i - g0] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nbp);
         });
         unroll<g0, g1>([&](auto ii) {
             constexpr int i = decltype(ii)::value;
             const T feq = peq.template at<i>();
             const T fst = pst.template at<i>();
             const T fpc = (fi[i - g0] + two_beta * (feq - fi[i - g0])) + omb * (fst - feq);
-            store_pop<D, SOLIDS, PH, i>(f, mask, g, nb, fpc, base);
+            store_pop<D, SOLIDS, PH, i>(f, mask, g, nbp, fpc, base);
         });
         __builtin_amdgcn_sched_barrier(0);
     });
@@ -1198,7 +1223,7 @@ __device__ __forceinline__ void fused_body(P *__restrict__ f, const P4<T> *__res
     corrected_velocity<D, T, SOLIDS>(m1p, ev, eps, mask, g, nb, own1, cs, own2.w);
     ProductForm<D, T> peq, pst;
     cell_equilibria<D, T, SOLIDS>(m2p, ev, eps, muD, muF, mask, g, ph, nb, own2, cs, peq, pst);
-    collide_stream<D, T, P, SOLIDS, PH>(f, mask, g, nb, fi, cs.vs.beta,
+    collide_stream<D, T, P, SOLIDS, PH>(f, mask, g, PH == 1 ? nb.opaque() : nb, fi, cs.vs.beta,
                                         own_base<P>(ev.at(0, 0, 0), ph), peq, pst);
     store_rec<D>(m1n, n, own1.r, own1.w);
     store_rec<D>(m2n, n, own2.r, own2.w);
@@ -1332,15 +1357,28 @@ __global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ own_
     vcorrect_body<D, T, SOLIDS, AD>(own_src, m1, eps, mask, m2_out, g, tl, ph, blockIdx.x);
 }
 
+// Waves per SIMD requested for the kernels of runs with solids.  Such a kernel holds the
+// solid-free and the solid-aware code, and the latter, run only by tiles next to a solid, needs
+// more registers; left alone it would set the occupancy of every tile.  Where it pays, the
+// occupancy of the solid-free code is requested and the solid-aware code spills a few values
+// instead (D3Q27 sphere duct, 768 x 384 x 384: 16-bit collision 5.24 -> 4.62 ms, 16-bit lagged
+// pass 9.47 -> 8.29 ms, FP64 swapped-phase collision 12.13 -> 11.89 ms; the same for FP32 cost
+// 2 %, so FP32 requests nothing).  1 requests nothing.
+template <int D, typename T, typename P, bool SOLIDS, int PH>
+struct SolidAwareWaves {
+    static constexpr bool on = SOLIDS && D == 3;
+    static constexpr bool half = sizeof(P) == 2, fp64 = sizeof(T) == 8;
+    static constexpr int collide = !on ? 1 : half ? (PH == 1 ? 5 : 6) : (fp64 && PH == 1 ? 3 : 1);
+    static constexpr int fused = on && half && PH == 0 ? 3 : 1;
+};
+
 template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
-__global__ __launch_bounds__(256) void k_collide(P *__restrict__ f,
-                                                 const P4<T> *__restrict__ m2,
-                                                 const T *__restrict__ eps,
-                                                 const T *__restrict__ muD,
-                                                 const T *__restrict__ muF,
-                                                 const uint8_t *__restrict__ mask,
-                                                 const uint8_t *__restrict__ tsolid, Grid g,
-                                                 Tiling tl, Phys<T> ph) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(SolidAwareWaves<D, T, P, SOLIDS, PH>::collide)))
+void k_collide(P *__restrict__ f, const P4<T> *__restrict__ m2, const T *__restrict__ eps,
+               const T *__restrict__ muD, const T *__restrict__ muF,
+               const uint8_t *__restrict__ mask, const uint8_t *__restrict__ tsolid, Grid g,
+               Tiling tl, Phys<T> ph) {
     if constexpr (SOLIDS) {
         if (tile_free(tsolid)) {
             collide_body<D, T, P, false, PH, AD>(f, m2, eps, muD, muF, mask, g, tl, ph,
@@ -1352,15 +1390,13 @@ __global__ __launch_bounds__(256) void k_collide(P *__restrict__ f,
 }
 
 template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
-__global__ __launch_bounds__(256) void k_fused(P *__restrict__ f, const P4<T> *__restrict__ m1p,
-                                               const P4<T> *__restrict__ m2p,
-                                               P4<T> *__restrict__ m1n, P4<T> *__restrict__ m2n,
-                                               const T *__restrict__ eps,
-                                               const T *__restrict__ muD,
-                                               const T *__restrict__ muF,
-                                               const uint8_t *__restrict__ mask,
-                                               const uint8_t *__restrict__ tsolid, Grid g,
-                                               Tiling tl, Phys<T> ph) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(SolidAwareWaves<D, T, P, SOLIDS, PH>::fused)))
+void k_fused(P *__restrict__ f, const P4<T> *__restrict__ m1p, const P4<T> *__restrict__ m2p,
+             P4<T> *__restrict__ m1n, P4<T> *__restrict__ m2n, const T *__restrict__ eps,
+             const T *__restrict__ muD, const T *__restrict__ muF,
+             const uint8_t *__restrict__ mask, const uint8_t *__restrict__ tsolid, Grid g,
+             Tiling tl, Phys<T> ph) {
     if constexpr (SOLIDS) {
         if (tile_free(tsolid)) {
             fused_body<D, T, P, false, PH, AD>(f, m1p, m2p, m1n, m2n, eps, muD, muF, mask, g, tl,
