@@ -1174,10 +1174,27 @@ __device__ __forceinline__ void collide_body(P *__restrict__ f,
         constexpr int k = decltype(gg)::value;
         constexpr int g0 = PairGroups<D>::begin(k), g1 = PairGroups<D>::begin(k + 1);
         T fi[g1 - g0];
-        unroll<g0, g1>([&](auto ii) {
-            constexpr int i = decltype(ii)::value;
-            fi[i - g0] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nbp);
-        });
+        if constexpr (PopFmt<P>::shifted) {
+            // Every load of the group is issued before the first decode.  With the decode next
+            // to its load the scheduler kept one BF16 load in flight at a time (256^3 box:
+            // BF16 collision 0.835 -> 0.601 ms, FP16 0.630 -> 0.601 ms; same results).
+            P raw[g1 - g0];
+            unroll<g0, g1>([&](auto ii) {
+                constexpr int i = decltype(ii)::value;
+                raw[i - g0] = load_raw<D, SOLIDS, PH, i>(f, mask, g, nbp);
+            });
+            __builtin_amdgcn_sched_barrier(0);
+            unroll<g0, g1>([&](auto ii) {
+                constexpr int i = decltype(ii)::value;
+                fi[i - g0] = decode<D, i, T>(raw[i - g0],
+                                             load_sigma<D, SOLIDS, i, P>(mask, ev, ph, nbp));
+            });
+        } else {
+            unroll<g0, g1>([&](auto ii) {
+                constexpr int i = decltype(ii)::value;
+                fi[i - g0] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nbp);
+            });
+        }
         unroll<g0, g1>([&](auto ii) {
             constexpr int i = decltype(ii)::value;
             const T feq = peq.template at<i>();
