@@ -266,24 +266,44 @@ template <int D, typename T>
 __device__ __forceinline__ void stage_eps(const T *__restrict__ eps, const Grid &g, int tx,
                                           int ty, int x0, int y0, int z0, T *lds) {
     const int row = tx + 2, rows = ty + 2;
-    const int t = (int)threadIdx.x;
-    // columns of this thread, c >= -1: one correction wraps them on all but the narrowest grids
-    // (a tile of 64 on nx < 32 reaches past 2 nx), which take the remainder
-    const int nx = g.nx;
-    auto wrapx = [nx](int c) {
-        return (uint32_t)(c < 0 ? c + nx : (c < nx ? c : (c < 2 * nx ? c - nx : c % nx)));
-    };
-    const uint32_t gx0 = wrapx(x0 + t - 1), gx1 = wrapx(x0 + t + 255);
     constexpr int planes = D == 3 ? 3 : 1;
-    for (int pz = 0; pz < planes; ++pz) {
-        const int zz = D == 3 ? wrapk(z0, pz - 1, g.nz) : z0;
-        for (int py = 0; py < rows; ++py) {
-            const int yy = wrapk(y0, py - 1, g.ny);
-            const uint32_t base = (uint32_t)g.nx * ((uint32_t)yy + (uint32_t)g.ny * (uint32_t)zz);
-            T *dst = lds + (pz * rows + py) * row;
-            if (t < row) dst[t] = ld(eps, base + gx0);
-            if (t + 256 < row) dst[t + 256] = ld(eps, base + gx1);
+    const int total = planes * rows * row;
+    const int nx = g.nx, ny = g.ny;
+    // periodic coordinate c >= -1: at most one correction except on grids narrower than the
+    // tile
+    auto wrap = [](int c, int n) {
+        if (c < 0) c += n;
+        while (c >= n) c -= n;
+        return c;
+    };
+    // Element e of the halo (row-major: plane, row, column) goes to lds[e].  Every load of the
+    // thread is issued before the first LDS write, so they are in flight together (a loop over
+    // halo rows waited for each load in turn: 256^3 box, FP16 moment pass 0.439 -> 0.305 ms,
+    // FP16 lagged pass 1.144 -> 0.882 ms).
+    constexpr int kIt = (EpsTile<D, T>::kSize + 255) / 256;
+    const float inv_row = 1.0f / (float)row;
+    T v[kIt];
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+        const int e = (int)threadIdx.x + 256 * k;
+        v[k] = T(0);
+        if (e < total) {
+            int p = (int)((float)e * inv_row);  // row of the halo, corrected to floor(e / row)
+            if (p * row > e) --p;
+            else if ((p + 1) * row <= e) ++p;
+            const int px = e - p * row;
+            const int pz = D == 3 ? (p >= 2 * rows ? 2 : (p >= rows ? 1 : 0)) : 0;
+            const int py = p - pz * rows;
+            const int zz = D == 3 ? wrap(z0 + pz - 1, g.nz) : z0;
+            const int yy = wrap(y0 + py - 1, ny);
+            const uint32_t base = (uint32_t)nx * ((uint32_t)yy + (uint32_t)ny * (uint32_t)zz);
+            v[k] = ld(eps, base + (uint32_t)wrap(x0 + px - 1, nx));
         }
+    }
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+        const int e = (int)threadIdx.x + 256 * k;
+        if (e < total) lds[e] = v[k];
     }
 }
 
