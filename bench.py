@@ -8,8 +8,10 @@ permeability with d = 2 cells, Forchheimer coefficient 0.55/sqrt(K), nu = 0.01, 
 update of every cell: moment pass, velocity correction, forcing-collide-stream pass.
 
 Prints one JSON line: MLUPS (whole job), the roofline of the dominant kernel measured with HIP
-events on the library's stream over the timed region, and the FP64 CPU oracle timed on a
-bounded sample of the same recipe.
+events on the library's stream over the timed region, secondary rows timed the same way (the
+shifted FP16/BF16 forms, the lagged single-pass scheme, FP64, and the 768x384x384 porous-sphere
+duct), a bounded sample of the serving stream, and the FP64 CPU oracle timed on a bounded
+sample of the same recipe with all host threads and with one.
 """
 import argparse
 import hashlib
@@ -79,10 +81,11 @@ def traffic_from_profiles(kernel, tag, src_hash):
     return (k["fetch_kib"] * pmc["fetch_scale"] + k["write_kib"] * pmc["write_scale"]) * 1024.0
 
 
-def cpu_baseline(budget_s=15.0, workload="box"):
+def cpu_baseline(budget_s=10.0, workload="box"):
     """The FP64 oracle, as it stands, on a bounded instance of the same recipe: the 64^3 box
-    (seed 0), or the sphere duct at 1/8 scale (96 x 48 x 48, radius 12); one process, one
-    thread; steps until about budget_s of stepping have elapsed."""
+    (seed 0), or the sphere duct at 1/8 scale (96 x 48 x 48, radius 12); timed with every
+    thread the host gives the process (OpenMP default: OMP_NUM_THREADS, else the core count)
+    and again with one thread, each for about budget_s of stepping."""
     import oracle
     from paper_2606_29619_amd import workloads
     if workload == "box":
@@ -91,21 +94,33 @@ def cpu_baseline(budget_s=15.0, workload="box"):
     else:
         w = workloads.sphere_duct_3d(96, 48, 48, radius=12.0, bump_m=8)
         what = "the sphere-duct recipe at 1/8 scale (96 x 48 x 48, radius 12, bump m = 8)"
-    o = oracle.Oracle(oracle.OracleConfig(D=3, eps=w.eps, kappa=w.kappa, cf=w.forch,
-                                          mask=w.mask, nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref,
-                                          b=w.b))
-    t0 = time.perf_counter()
-    o.step(1)
-    one = time.perf_counter() - t0
-    k = max(1, int(budget_s / max(one, 1e-3)) - 1)
-    t0 = time.perf_counter()
-    o.step(k)
-    dt = time.perf_counter() - t0
-    cells = w.cells
-    return {"value": round(cells * k / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
-            "sample": f"FP64 oracle, {what}, {k} timed steps after 1 warm-up step, "
-                      f"{dt:.1f} s"}
+
+    def timed(threads):
+        prev = oracle.set_threads(threads)
+        used = oracle.set_threads(0) if threads == 0 else threads
+        try:
+            o = oracle.Oracle(oracle.OracleConfig(D=3, eps=w.eps, kappa=w.kappa, cf=w.forch,
+                                                  mask=w.mask, nu_f=w.nu_f,
+                                                  nu_eff_ref=w.nu_eff_ref, b=w.b))
+            t0 = time.perf_counter()
+            o.step(1)
+            one = time.perf_counter() - t0
+            k = max(1, int(budget_s / max(one, 1e-3)) - 1)
+            t0 = time.perf_counter()
+            o.step(k)
+            dt = time.perf_counter() - t0
+        finally:
+            oracle.set_threads(prev)
+        return w.cells * k / dt / 1e6, used, k, dt
+
+    all_mlups, threads, k_all, dt_all = timed(0)
+    one_mlups, _, k_one, dt_one = timed(1)
+    return {"value": round(all_mlups, 4), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle", "nproc": os.cpu_count(),
+            "value_1_core": round(one_mlups, 4),
+            "sample": f"FP64 oracle, {what}: {k_all} timed steps on {threads} threads "
+                      f"({dt_all:.1f} s) and {k_one} on one thread ({dt_one:.1f} s), each after "
+                      f"1 warm-up step"}
 
 
 def copy_bandwidth(nbytes=2 << 30, reps=10):
@@ -156,6 +171,100 @@ def serving_sample(n_requests, max_steps):
     return out
 
 
+def make_workload(kind, n, steps):
+    """The benchmark's inputs and a one-line description of them."""
+    from paper_2606_29619_amd import workloads
+    if kind == "box":
+        w = workloads.random_porosity_3d(n=n, seed=0, ell=16.0, steps=steps)
+        desc = (f"random-porosity D3Q27 {n}^3 periodic box, seed 0, correlation length 16, "
+                f"phi in (0.3,1), Kozeny-Carman K (d=2), C_F=0.55/sqrt(K), nu=0.01, b=1e-6 x")
+    else:
+        w = workloads.sphere_duct_3d(bump_m=8, steps=steps)
+        desc = ("D3Q27 768x384x384 duct, solid walls on the y and z faces, porous sphere of "
+                "radius 96 at (192, 192, 192): eps = 1 - 0.5 B_8(r^2/R^2), 1/K = B_8/5e-3, "
+                "C_F=0.55/sqrt(K), nu=0.052, b = 1e-4/768 x (pressure drop 1e-4 as a body "
+                "force); MLUPS count every cell, solid walls included")
+    return w, desc
+
+
+def measure(w, desc, storage, shift, scheme, steps, warmup, src, kind="box", n=256):
+    """Create a solver for workload w, take `warmup` untimed steps, then time `steps` steps
+    (wall clock around the whole region, HIP events around every kernel class on the library's
+    stream).  Returns the result fields of one benchmark row."""
+    import torch
+    from paper_2606_29619_amd import capi
+    st = {"f32": capi.LBM_F32, "f64": capi.LBM_F64, "f16": capi.LBM_F16_SHIFTED,
+          "bf16": capi.LBM_BF16_SHIFTED}[storage]
+    s_bytes = 8 if storage == "f64" else 4
+    sp_bytes = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[storage]
+    msk = 1 if w.mask is not None else 0
+    lagged = scheme == "lagged"
+    solver = capi.Solver.from_workload(
+        w, storage=st,
+        shift=capi.LBM_SHIFT_POROUS if shift == "porous" else capi.LBM_SHIFT_WEIGHTS,
+        scheme=capi.LBM_SCHEME_LAGGED if lagged else capi.LBM_SCHEME_TWO_PASS)
+    N = w.cells
+    label = f"{kind} {storage} {scheme}"
+    print(f"[bench] {label}: created, workspace {solver.nbytes / 2**30:.2f} GiB",
+          file=sys.stderr, flush=True)
+    solver.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = solver.step_timed(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stt = solver.residual()
+    mlups = N * steps / wall / 1e6
+    print(f"[bench] {label}: {steps} steps in {wall:.3f} s ({mlups:.0f} MLUPS); mass "
+          f"{stt.mass:.9e} vmax {stt.vmax:.3e}", file=sys.stderr, flush=True)
+    assert stt.nonfinite == 0
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+    Q, D = 27, 3
+    if lagged:
+        kb = {"fused": lagged_bytes_per_cell(Q, D, sp_bytes, s_bytes, msk)}
+        avg_ms = {"fused": kms[2] / steps}
+    else:
+        kb = kernel_bytes_per_cell(Q, D, sp_bytes, s_bytes, msk)
+        avg_ms = {"moments": kms[0] / steps, "vcorrect": kms[1] / steps,
+                  "collide": kms[2] / steps}
+    dom = max(avg_ms, key=avg_ms.get)
+    algo = kb[dom] * N
+    achieved = algo / (avg_ms[dom] * 1e-3) / 1e9
+    tag = storage if sp_bytes != 2 else f"{storage}_{shift}"
+    if lagged:
+        tag += "_lagged"
+    traffic = (traffic_from_profiles(dom, tag, src)
+               if kind == "box" and n == 256 else None)
+    step_bytes = method_bytes_per_cell(Q, D, sp_bytes, s_bytes, lagged, msk)
+    return {
+        "value": round(mlups, 1),
+        "ms_per_step": round(wall / steps * 1e3, 4),
+        "dtype": "f64" if storage == "f64" else "f32",
+        "config": {"workload": desc, "lattice": "D3Q27", "cells": N, "scheme": scheme,
+                   "storage": storage if sp_bytes != 2 else f"{storage} shifted ({shift})"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": None if traffic is None else round(traffic, 0),
+                     "algorithmic_bytes_per_launch": algo},
+        "step_hbm": {"method_bytes_per_cell": step_bytes,
+                     "effective_GBps": round(mlups * 1e6 * step_bytes / 1e9, 1),
+                     "frac_of_peak": round(mlups * 1e6 * step_bytes / 1e9 / HBM_PEAK_GBPS, 4)},
+        "kernels": {k: {"avg_ms": round(avg_ms[k], 4), "bytes_per_cell": kb[k],
+                        "achieved_GBps": round(kb[k] * N / (avg_ms[k] * 1e-3) / 1e9, 1)}
+                    for k in avg_ms},
+    }
+
+
+# Rows timed after the headline, each under its own configuration: the other stored forms and
+# schemes of the random-porosity box, and the sphere duct at scale.
+SECONDARY = [("box", "f16", "porous", "two-pass"), ("box", "bf16", "porous", "two-pass"),
+             ("box", "f32", "porous", "lagged"), ("box", "f16", "porous", "lagged"),
+             ("box", "f64", "porous", "two-pass"), ("sphere", "f32", "porous", "two-pass")]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +284,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the bounded serving-stream sample")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary rows (other stored forms, schemes, the duct)")
+    ap.add_argument("--secondary-steps", type=int, default=None,
+                    help="timed steps of each secondary row (default: --steps, at most 200)")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-max-steps", type=int, default=5000)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -189,104 +302,36 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2606_29619_amd import capi, workloads
 
     torch.cuda.set_device(0)
-    n = args.n
-    if args.workload == "box":
-        w = workloads.random_porosity_3d(n=n, seed=0, ell=16.0, steps=args.steps)
-        wdesc = (f"random-porosity D3Q27 {n}^3 periodic box, seed 0, correlation length 16, "
-                 f"phi in (0.3,1), Kozeny-Carman K (d=2), C_F=0.55/sqrt(K), nu=0.01, b=1e-6 x")
-    else:
-        w = workloads.sphere_duct_3d(bump_m=8, steps=args.steps)
-        wdesc = ("D3Q27 768x384x384 duct, solid walls on the y and z faces, porous sphere of "
-                 "radius 96 at (192, 192, 192): eps = 1 - 0.5 B_8(r^2/R^2), 1/K = B_8/5e-3, "
-                 "C_F=0.55/sqrt(K), nu=0.052, b = 1e-4/768 x (pressure drop 1e-4 as a body "
-                 "force); MLUPS count every cell, solid walls included")
-    msk = 1 if w.mask is not None else 0
-    storage = {"f32": capi.LBM_F32, "f64": capi.LBM_F64, "f16": capi.LBM_F16_SHIFTED,
-               "bf16": capi.LBM_BF16_SHIFTED}[args.storage]
-    s_bytes = 8 if args.storage == "f64" else 4
-    sp_bytes = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[args.storage]
-    shift = capi.LBM_SHIFT_POROUS if args.shift == "porous" else capi.LBM_SHIFT_WEIGHTS
-    lagged = args.scheme == "lagged"
-    solver = capi.Solver.from_workload(
-        w, storage=storage, shift=shift,
-        scheme=capi.LBM_SCHEME_LAGGED if lagged else capi.LBM_SCHEME_TWO_PASS)
-    N = w.cells
-    print(f"[bench] created {w.name}, {args.storage}, workspace {solver.nbytes / 2**30:.2f} GiB",
-          file=sys.stderr, flush=True)
-
-    solver.step(args.warmup)
-    torch.cuda.synchronize()
-    print(f"[bench] warm-up {args.warmup} steps done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    kms = solver.step_timed(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = solver.residual()
-    wall = t1 - t0
-    mlups = N * args.steps / wall / 1e6
-    print(f"[bench] timed {args.steps} steps in {wall:.3f} s; mass {st.mass:.9e} "
-          f"vmax {st.vmax:.3e}", file=sys.stderr, flush=True)
-    assert st.nonfinite == 0
-
-    Q, D = 27, 3
-    if lagged:
-        kb = {"fused": lagged_bytes_per_cell(Q, D, sp_bytes, s_bytes, msk)}
-        avg_ms = {"fused": kms[2] / args.steps}
-    else:
-        kb = kernel_bytes_per_cell(Q, D, sp_bytes, s_bytes, msk)
-        avg_ms = {"moments": kms[0] / args.steps, "vcorrect": kms[1] / args.steps,
-                  "collide": kms[2] / args.steps}
-    dom = max(avg_ms, key=avg_ms.get)
-    algo = kb[dom] * N
-    achieved = algo / (avg_ms[dom] * 1e-3) / 1e9
     src = source_hash()
-    tag = args.storage if sp_bytes != 2 else f"{args.storage}_{args.shift}"
-    traffic = (traffic_from_profiles(dom, tag, src)
-               if args.workload == "box" and n == 256 else None)
-    step_bytes = method_bytes_per_cell(Q, D, sp_bytes, s_bytes, lagged, msk)
-    kernels = {k: {"avg_ms": round(avg_ms[k], 4), "bytes_per_cell": kb[k],
-                   "achieved_GBps": round(kb[k] * N / (avg_ms[k] * 1e-3) / 1e9, 1)}
-               for k in avg_ms}
+    w, desc = make_workload(args.workload, args.n, args.steps)
+    row = measure(w, desc, args.storage, args.shift, args.scheme, args.steps, args.warmup, src,
+                  args.workload, args.n)
+    del w
     line = {
         "metric": METRIC,
-        "value": round(mlups, 1),
+        "value": row["value"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "ms_per_step": row["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.storage == "f64" else "f32",
+        "dtype": row["dtype"],
         "data": "synthetic",
-        "config": {"workload": wdesc, "lattice": "D3Q27",
-                   "cells": N, "scheme": args.scheme,
-                   "storage": args.storage if sp_bytes != 2 else
-                   f"{args.storage} shifted ({args.shift})"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": None if traffic is None else round(traffic, 0),
-                     "algorithmic_bytes_per_launch": algo},
-        "step_hbm": {"method_bytes_per_cell": step_bytes,
-                     "effective_GBps": round(mlups * 1e6 * step_bytes / 1e9, 1),
-                     "frac_of_peak": round(mlups * 1e6 * step_bytes / 1e9 / HBM_PEAK_GBPS, 4)},
-        "kernels": kernels,
+        "config": row["config"],
+        "roofline": row["roofline"],
+        "step_hbm": row["step_hbm"],
+        "kernels": row["kernels"],
         "source_hash": src,
     }
-    solver.close()
-    del solver
-    torch.cuda.empty_cache()
     copy = copy_bandwidth()
     line["roofline"]["copy_GBps"] = copy
-    line["roofline"]["frac_of_copy"] = round(achieved / copy, 4)
+    line["roofline"]["frac_of_copy"] = round(row["roofline"]["achieved"] / copy, 4)
     if args.copy_probe_mib:
         nb = args.copy_probe_mib * 2 ** 20
         a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
@@ -296,6 +341,21 @@ def main():
         torch.cuda.synchronize()
         line["copy_probe_bytes"] = {"read": nb, "write": nb}
         del a, b
+    if not args.no_secondary:
+        steps2 = args.secondary_steps or min(args.steps, 200)
+        warm2 = min(args.warmup, 20)
+        rows, cache = [], {}
+        for kind, storage, shift, scheme in SECONDARY:
+            if (kind, storage, scheme) == (args.workload, args.storage, args.scheme):
+                continue
+            if kind not in cache:
+                cache.clear()
+                cache[kind] = make_workload(kind, args.n, steps2)
+            wk, dk = cache[kind]
+            r = measure(wk, dk, storage, shift, scheme, steps2, warm2, src, kind, args.n)
+            rows.append(dict(r, steps=steps2, warmup=warm2))
+        cache.clear()
+        line["secondary"] = rows
     if not args.no_serving:
         line["serving"] = serving_sample(args.serve_requests, args.serve_max_steps)
     if not args.no_cpu_baseline:

@@ -15,7 +15,12 @@
  * periodically; walls are layers of solid cells (mask = 1), which reflect populations by
  * halfway (link-wise) bounce-back.  The porosity is read on every cell, solid cells included;
  * its derivatives are central differences.  Derivatives of moment fields become one-sided next
- * to solid cells (Sec. 3.5, last paragraph).
+ * to solid cells (Sec. 3.5, last paragraph).  Consequence: the porosity given to a solid cell
+ * enters grad eps and the Hessian of eps at its fluid neighbours, and through them the
+ * RT grad eps force of eqs. (v_(0), accel) and Delta_nu (eq. porosity_correction_expanded) of
+ * the first fluid layer.  Give solid cells a smooth continuation of the fluid porosity (for a
+ * flat wall, the value of the adjacent fluid cell) unless a porosity jump at the wall is meant;
+ * analytic derivatives (lbm_params.grad_eps, hess_eps) avoid the question.
  *
  * Conventions common to every entry point:
  *   - every function returns LBM_OK (0) or a negative LBM_ERR_* code and never throws;
@@ -119,6 +124,10 @@ extern "C" {
 #define LBM_BC_RHO_CONTINUITY 0
 #define LBM_BC_RHO_BOUNCE_BACK 1
 
+/* Workgroup tiles (lbm_params.tiles). */
+#define LBM_TILES_AUTO 0
+#define LBM_TILES_RECTANGULAR 1
+
 /* Output element type for lbm_moments / lbm_get_populations / lbm_set_populations. */
 #define LBM_DTYPE_F64 0
 #define LBM_DTYPE_F32 1
@@ -152,7 +161,9 @@ typedef struct lbm_params {
                              (eq. eta_0_no_corr) */
     double b[3];          /* body acceleration (b[2] ignored for D2Q9) */
     double rho0;          /* initial intrinsic density where rho_init is NULL, > 0 */
-    const double *eps;    /* [N] porosity in (0, 1] on every cell (solid cells included) */
+    const double *eps;    /* [N] porosity in (0, 1] on every cell (solid cells included: their
+                             values enter the differenced derivatives of the neighbouring fluid
+                             cells, see Geometry above) */
     const double *kappa;  /* [N] permeability > 0 on fluid cells; +inf means free fluid */
     const double *forch;  /* [N] Forchheimer coefficient C_F >= 0 on fluid cells, so that
                              mu_F = eps C_F (eq. mu_F_Ergun_perm with C_F = F_eps/sqrt(kappa)) */
@@ -183,6 +194,12 @@ typedef struct lbm_params {
      * that is not finite on a fluid cell: LBM_ERR_INVALID_ARG. */
     const double *grad_eps;
     const double *hess_eps;
+    /* Workgroup tiles of the cell passes: LBM_TILES_AUTO picks rows of 256, 128 or 64 cells and,
+     * for FP64/FP32 storage with an x extent that is not a multiple of 64, packed rows (256
+     * consecutive cells of a plane, wrapping from row to row); LBM_TILES_RECTANGULAR never
+     * packs.  The tiles decide only which thread updates which cell: results are bitwise the
+     * same. */
+    int tiles;
 } lbm_params;
 
 /* Global statistics of the current state, accumulated in FP64 on the device. */

@@ -23,8 +23,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
-CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-          "-Wall", "-Wextra", "-Wno-unused-parameter"]
+CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+          "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter"]
 
 
 def build(force: bool = True) -> str:
@@ -84,8 +84,16 @@ def lib():
         L.orc_weights.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         L.orc_product_form.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         L.orc_drag_solve.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's per-cell passes (0: the OpenMP default, OMP_NUM_THREADS or the
+    core count); returns the number in use.  Results do not depend on it."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def _dp(a: Optional[np.ndarray]):

@@ -20,12 +20,20 @@
  * derivatives become one-sided next to solids (Sec. 3.5, last paragraph).
  *
  * Build with -ffp-contract=off: the expressions below are evaluated exactly as written.
+ *
+ * Threads (OpenMP): the per-cell passes split the cells among threads.  Every iteration writes
+ * only its own cell's results (streaming writes each destination slot exactly once) and reads
+ * fields that the pass does not write, and the global sums stay sequential, so the result is
+ * bit for bit the same for any number of threads.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_MAXQ 27
 
@@ -226,24 +234,27 @@ static void build_neighbours(orc_solver *S)
 /* Derivative of a moment field g along axis a at fluid cell n (Sec. 3.5, last paragraph):
  * second-order central difference when both axis neighbours are fluid, second-order one-sided
  * difference into the fluid next to a solid, first order when only one fluid cell is available
- * on that side, and zero for a cell with no fluid neighbour along the axis. */
-static double deriv(const orc_solver *S, const double *g, long n, int a)
+ * on that side, and zero for a cell with no fluid neighbour along the axis.  g0 is the cell's own
+ * value: g[n] itself, or the current value where the lagged scheme takes the neighbour values
+ * from the previous step. */
+static double deriv_own(const orc_solver *S, const double *g, long n, int a, double g0)
 {
     long p1 = shift(S, n, a, 1), m1 = shift(S, n, a, -1);
     int fp1 = !S->solid[p1], fm1 = !S->solid[m1];
     if (fp1 && fm1) return (g[p1] - g[m1]) * 0.5;
     if (fp1) {
         long p2 = shift(S, n, a, 2);
-        if (!S->solid[p2]) return ((-3.0 * g[n] + 4.0 * g[p1]) - g[p2]) * 0.5;
-        return g[p1] - g[n];
+        if (!S->solid[p2]) return ((-3.0 * g0 + 4.0 * g[p1]) - g[p2]) * 0.5;
+        return g[p1] - g0;
     }
     if (fm1) {
         long m2 = shift(S, n, a, -2);
-        if (!S->solid[m2]) return ((3.0 * g[n] - 4.0 * g[m1]) + g[m2]) * 0.5;
-        return g[n] - g[m1];
+        if (!S->solid[m2]) return ((3.0 * g0 - 4.0 * g[m1]) + g[m2]) * 0.5;
+        return g0 - g[m1];
     }
     return 0.0;
 }
+
 
 /* Porosity gradient and Hessian.  Sec. 3.5 prefers analytic derivatives of eps where eps(x) is
  * given in closed form: then they are the caller's.  Otherwise central differences on the
@@ -267,6 +278,7 @@ static void porosity_derivatives(orc_solver *S)
         }
         return;
     }
+#pragma omp parallel for private(a, b) schedule(static)
     for (n = 0; n < N; ++n) {
         for (a = 0; a < D; ++a) {
             long p = shift(S, n, a, 1), q = shift(S, n, a, -1);
@@ -322,16 +334,27 @@ static void delta_nu(const orc_solver *S, long n, const double *mv, const double
     }
 }
 
-/* Delta_nu of the vector field m (stored [D][N]) at fluid cell n. */
-static void delta_nu_field(const orc_solver *S, const double *m, long n, double *out)
+/* Delta_nu of the vector field m (stored [D][N]) at fluid cell n whose own value is mv (m at n
+ * itself, or the current value where the neighbours are the previous step's). */
+static void delta_nu_own(const orc_solver *S, const double *m, long n, const double *mv,
+                         double *out)
 {
     int D = S->D, a, b;
     long N = S->N;
-    double mv[3], J[3][3];
-    for (a = 0; a < D; ++a) mv[a] = m[a * N + n];
+    double J[3][3];
     for (a = 0; a < D; ++a)
-        for (b = 0; b < D; ++b) J[a][b] = deriv(S, m + a * N, n, b);
+        for (b = 0; b < D; ++b) J[a][b] = deriv_own(S, m + a * N, n, b, mv[a]);
     delta_nu(S, n, mv, (const double (*)[3])J, out);
+}
+
+/* Delta_nu of the vector field m (stored [D][N]) at fluid cell n. */
+static void delta_nu_field(const orc_solver *S, const double *m, long n, double *out)
+{
+    int D = S->D, a;
+    long N = S->N;
+    double mv[3];
+    for (a = 0; a < D; ++a) mv[a] = m[a * N + n];
+    delta_nu_own(S, m, n, mv, out);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -474,6 +497,7 @@ static void moments_v1(orc_solver *S)
 {
     int D = S->D, Q = S->Q, i, a;
     long n, N = S->N;
+#pragma omp parallel for private(i, a) schedule(static)
     for (n = 0; n < N; ++n) {
         double sum = 0.0, Pi[3] = {0.0, 0.0, 0.0}, v0[3], v1[3], rho, e;
         if (S->solid[n]) {
@@ -502,6 +526,7 @@ static void momentum_over_eps(orc_solver *S, const double *r, const double *w)
 {
     int D = S->D, a;
     long n, N = S->N;
+#pragma omp parallel for private(a) schedule(static)
     for (n = 0; n < N; ++n)
         for (a = 0; a < D; ++a)
             S->m[a * N + n] = S->solid[n] ? 0.0 : (r[n] * w[a * N + n]) / S->eps[n];
@@ -520,6 +545,7 @@ static void correct_velocity(orc_solver *S)
     }
     if (S->p.lagged && S->have_prev) momentum_over_eps(S, S->prho, S->pv1);
     else momentum_over_eps(S, S->rho, S->v1);
+#pragma omp parallel for private(a) schedule(static)
     for (n = 0; n < N; ++n) {
         double dn[3];
         if (S->solid[n]) {
@@ -528,13 +554,9 @@ static void correct_velocity(orc_solver *S)
         }
         if (S->p.lagged && S->have_prev) {
             /* own value current, neighbour values lagged */
-            double save[3];
-            for (a = 0; a < D; ++a) {
-                save[a] = S->m[a * N + n];
-                S->m[a * N + n] = (S->rho[n] * S->v1[a * N + n]) / S->eps[n];
-            }
-            delta_nu_field(S, S->m, n, dn);
-            for (a = 0; a < D; ++a) S->m[a * N + n] = save[a];
+            double own[3];
+            for (a = 0; a < D; ++a) own[a] = (S->rho[n] * S->v1[a * N + n]) / S->eps[n];
+            delta_nu_own(S, S->m, n, own, dn);
         } else {
             delta_nu_field(S, S->m, n, dn);
         }
@@ -686,6 +708,7 @@ static void forcing(orc_solver *S, const double *rho, const double *v, const dou
     double *gext = (double *)xcalloc(D * N, sizeof(double));
     double *vw = S->vw;
     /* neighbour fields: m = rho v / eps, g_a = rho v_a (1 - 3RT) - rho v_a^3 / eps^2 and v */
+#pragma omp parallel for private(a) schedule(static)
     for (n = 0; n < N; ++n)
         for (a = 0; a < D; ++a) {
             double r = nrho[n], va = nv[a * N + n], e = S->eps[n];
@@ -697,9 +720,10 @@ static void forcing(orc_solver *S, const double *rho, const double *v, const dou
             gext[a * N + n] = (r * va) * omr - (r * ((va * va) * va)) / (e * e);
             vw[a * N + n] = va;
         }
+#pragma omp parallel for private(a) schedule(static)
     for (n = 0; n < N; ++n) {
         double vv[3], dm[3] = {0.0, 0.0, 0.0}, acc[3], phx[3], pheta = 0.0, s = 0.0, vm;
-        double e, r, save_m[3], save_g[3], save_v[3];
+        double e, r, own_m[3], own_g[3];
         if (S->solid[n]) continue;
         e = S->eps[n];
         r = rho[n];
@@ -707,32 +731,24 @@ static void forcing(orc_solver *S, const double *rho, const double *v, const dou
         /* the cell's own values are always current (they differ from the neighbour fields
          * only in lagged mode) */
         for (a = 0; a < D; ++a) {
-            save_m[a] = S->m[a * N + n];
-            save_g[a] = gext[a * N + n];
-            save_v[a] = vw[a * N + n];
-            S->m[a * N + n] = (r * vv[a]) / e;
-            gext[a * N + n] = (r * vv[a]) * omr - (r * ((vv[a] * vv[a]) * vv[a])) / (e * e);
-            vw[a * N + n] = vv[a];
+            own_m[a] = (r * vv[a]) / e;
+            own_g[a] = (r * vv[a]) * omr - (r * ((vv[a] * vv[a]) * vv[a])) / (e * e);
         }
         /* acceleration, eq. (accel), with Delta_nu(rho u) = Delta_nu(rho v / eps) */
-        if (S->p.visc_corr) delta_nu_field(S, S->m, n, dm);
+        if (S->p.visc_corr) delta_nu_own(S, S->m, n, own_m, dm);
         for (a = 0; a < D; ++a) s = s + vv[a] * vv[a];
         vm = sqrt(s);
         for (a = 0; a < D; ++a)
             acc[a] = (((e * S->p.b[a] - S->muD[n] * vv[a]) - (S->muF[n] * vm) * vv[a]) +
                       RT * S->ge[a * N + n]) + dm[a] / r;
         /* extended-equilibrium correction, eq. (ex_corr): one axis at a time, no summation */
-        for (a = 0; a < D; ++a) phx[a] = S->p.ext_corr ? deriv(S, gext + a * N, n, a) : 0.0;
+        for (a = 0; a < D; ++a)
+            phx[a] = S->p.ext_corr ? deriv_own(S, gext + a * N, n, a, own_g[a]) : 0.0;
         /* bulk-viscosity correction, eq. (eta_corr) */
         if (eta_on) {
             double divv = 0.0;
-            for (a = 0; a < D; ++a) divv = divv + deriv(S, vw + a * N, n, a);
+            for (a = 0; a < D; ++a) divv = divv + deriv_own(S, vw + a * N, n, a, vv[a]);
             pheta = ((r * RT) * (2.0 / (double)D - S->p.eta_eff / S->nu[n])) * divv;
-        }
-        for (a = 0; a < D; ++a) {
-            S->m[a * N + n] = save_m[a];
-            gext[a * N + n] = save_g[a];
-            vw[a * N + n] = save_v[a];
         }
         /* equilibrium and shifted-equilibrium arguments, eqs. (xi_alpha_eq),
          * (P_alpha_alpha_eq), (xi_alpha_*), (P_aa_*) with lambda = 1 */
@@ -880,6 +896,7 @@ static void picard_velocity(orc_solver *S)
     double *vn = S->vw;
     for (it = 0; it < S->p.picard_iters; ++it) {
         momentum_over_eps(S, S->rho, S->v);
+#pragma omp parallel for private(a) schedule(static)
         for (n = 0; n < N; ++n) {
             double dn[3], sv[3], vk[3];
             int bnode = S->p.bc_type && (S->p.bc_type[n] == 1 || S->p.bc_type[n] == 2);
@@ -944,6 +961,8 @@ static void step_once(orc_solver *S)
     if (S->p.lagged && S->have_prev) forcing(S, S->rho, S->v, S->prho, S->pv, &o);
     else forcing(S, S->rho, S->v, S->rho, S->v, &o);
     if (S->nb) reconstruct_boundaries(S, o.acc);
+    /* every destination slot is written by exactly one cell: the loop needs no ordering */
+#pragma omp parallel for private(i) schedule(static)
     for (n = 0; n < N; ++n) {
         double fpc[ORC_MAXQ];
         if (S->solid[n]) continue;
@@ -971,6 +990,18 @@ int orc_step(orc_solver *S, long nsteps)
 }
 
 long orc_time(const orc_solver *S) { return S->t; }
+
+/* Threads of the per-cell passes (n <= 0: the OpenMP default); returns the count now in use. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* Macroscopic output of the current state: intrinsic density rho and corrected superficial
  * velocity v (steps v_(0), v_(1), v_final on the current populations).  Solid cells give 0.
@@ -1066,7 +1097,8 @@ void orc_post_collision(orc_solver *S, long ncells, const long *cells, double *f
 /* Global statistics of the current state (Sec. 4.2's steady-state measure and the
  * conservation sums), in FP64:
  *   out[0] total mass sum_x sum_i f-bar_i;  out[1..3] sum_x rho v;  out[4] max |v|;
- *   out[5] sum |v - v_snap|^2;  out[6] sum |v_snap|^2;  out[7] count of non-finite values.
+ *   out[5] sum |v - v_snap|^2;  out[6] sum |v_snap|^2;  out[7] number of fluid cells whose
+ *   populations or velocity are not finite.
  * The snapshot then takes the current v. */
 void orc_stats(orc_solver *S, double *out)
 {
@@ -1079,7 +1111,6 @@ void orc_stats(orc_solver *S, double *out)
         if (S->solid[n]) continue;
         for (i = 0; i < Q; ++i) cell = cell + S->F[(long)i * N + n];
         mass = mass + cell;
-        if (!isfinite(cell)) bad = bad + 1.0;
         for (a = 0; a < D; ++a) {
             double va = S->v[a * N + n], sa = S->vsnap[a * N + n];
             mom[a] = mom[a] + S->rho[n] * va;
@@ -1087,8 +1118,8 @@ void orc_stats(orc_solver *S, double *out)
             d2 = d2 + (va - sa) * (va - sa);
             s2 = s2 + sa * sa;
         }
-        if (!isfinite(vv)) bad = bad + 1.0;
-        else if (sqrt(vv) > vmax) vmax = sqrt(vv);
+        if (!isfinite(cell) || !isfinite(vv)) bad = bad + 1.0;   /* each cell counts once */
+        if (isfinite(vv) && sqrt(vv) > vmax) vmax = sqrt(vv);
     }
     out[0] = mass;
     out[1] = mom[0]; out[2] = mom[1]; out[3] = mom[2];

@@ -15,8 +15,7 @@ from typing import Optional
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-# LBM_LIBRARY points the binding at another build of the same ABI (kernel-variant timing).
-LIB_PATH = os.environ.get("LBM_LIBRARY", os.path.join(_PKG, "liblbm.so"))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
 LBM_OK = 0
 LBM_ERR_INVALID_ARG = -1
@@ -39,6 +38,8 @@ LBM_BC_EQUILIBRIUM, LBM_BC_NEEM, LBM_BC_TMS = 0, 1, 2
 LBM_BC_RHO_CONTINUITY, LBM_BC_RHO_BOUNCE_BACK = 0, 1
 LBM_SCHEME_TWO_PASS = 0
 LBM_SCHEME_LAGGED = 1
+LBM_TILES_AUTO = 0
+LBM_TILES_RECTANGULAR = 1
 LBM_DTYPE_F64 = 0
 LBM_DTYPE_F32 = 1
 LBM_VELOCITY_SUPERFICIAL = 0
@@ -62,6 +63,7 @@ class lbm_params(ctypes.Structure):
         ("bc_scheme", ctypes.c_int), ("bc_rho_rule", ctypes.c_int),
         ("picard_iters", ctypes.c_int), ("picard_omega", ctypes.c_double),
         ("grad_eps", _dp), ("hess_eps", _dp),
+        ("tiles", ctypes.c_int),
     ]
 
 
@@ -290,7 +292,7 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
                 bc_density: Optional[np.ndarray] = None, bc_scheme: int = LBM_BC_NEEM,
                 bc_rho_rule: int = LBM_BC_RHO_CONTINUITY, picard_iters: int = 0,
                 picard_omega: float = 1.0, grad_eps: Optional[np.ndarray] = None,
-                hess_eps: Optional[np.ndarray] = None):
+                hess_eps: Optional[np.ndarray] = None, tiles: int = LBM_TILES_AUTO):
     """Build an lbm_params from numpy arrays shaped [nz, ny, nx]; returns (params, keepalive).
     grad_eps [D][nz, ny, nx] and hess_eps [D(D+1)/2][nz, ny, nx] (upper triangle row by row)
     are the optional analytic porosity derivatives."""
@@ -339,6 +341,7 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
     p.picard_iters, p.picard_omega = picard_iters, picard_omega
     p.grad_eps = arr(grad_eps, (D,) + eps.shape)
     p.hess_eps = arr(hess_eps, (D * (D + 1) // 2,) + eps.shape)
+    p.tiles = tiles
     return p, keep
 
 
@@ -369,7 +372,7 @@ class Solver:
 
     @classmethod
     def from_workload(cls, w, storage: int = LBM_F32, scheme: int = LBM_SCHEME_TWO_PASS,
-                      shift: int = LBM_SHIFT_WEIGHTS, **kw):
+                      shift: int = LBM_SHIFT_WEIGHTS, tiles: int = LBM_TILES_AUTO, **kw):
         p, keep = make_params(w.lattice, storage, w.eps, w.kappa, w.forch, w.mask, RT=w.RT,
                               nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow,
                               eta_eff=w.eta_eff, b=w.b, rho0=w.rho0, rho_init=w.rho_init,
@@ -383,7 +386,7 @@ class Solver:
                               picard_iters=getattr(w, "picard_iters", 0),
                               picard_omega=getattr(w, "picard_omega", 1.0),
                               grad_eps=getattr(w, "grad_eps", None),
-                              hess_eps=getattr(w, "hess_eps", None))
+                              hess_eps=getattr(w, "hess_eps", None), tiles=tiles)
         return cls(p, keep, **kw)
 
     def close(self):

@@ -94,9 +94,10 @@ int check_handle(const lbm_solver *h) {
 }
 
 // Packed-row tiles serve the storages whose kernels read porosity from global memory (the
-// 16-bit kernels stage it in LDS over rectangular tiles).
+// 16-bit kernels stage it in LDS over rectangular tiles), unless the caller asks for
+// rectangular tiles.
 bool packed_rows_ok(const lbm_params *p) {
-    return p->storage == LBM_F32 || p->storage == LBM_F64;
+    return (p->storage == LBM_F32 || p->storage == LBM_F64) && p->tiles != LBM_TILES_RECTANGULAR;
 }
 
 int validate_shape(const lbm_params *p, int *D, int *Q, size_t *sp, size_t *s, int64_t *N) {
@@ -120,6 +121,8 @@ int validate_shape(const lbm_params *p, int *D, int *Q, size_t *sp, size_t *s, i
         return fail(LBM_ERR_UNSUPPORTED, "Picard iterations need LBM_SCHEME_TWO_PASS");
     if ((p->grad_eps == nullptr) != (p->hess_eps == nullptr))
         return fail(LBM_ERR_INVALID_ARG, "grad_eps and hess_eps go together (both or neither)");
+    if (p->tiles != LBM_TILES_AUTO && p->tiles != LBM_TILES_RECTANGULAR)
+        return fail(LBM_ERR_INVALID_ARG, "tiles must be LBM_TILES_AUTO or LBM_TILES_RECTANGULAR, got %d", p->tiles);
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LBM_ERR_INVALID_ARG, "dimensions must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
     if (*D == 2 && p->nz != 1) return fail(LBM_ERR_INVALID_ARG, "D2Q9 needs nz = 1 (got %d)", p->nz);
@@ -185,14 +188,13 @@ int boundary_nodes(const lbm_params *p, int D, int64_t N, uint32_t *count, bool 
     return LBM_OK;
 }
 
-int enqueue_stats(lbm_solver *h) {
+int enqueue_stats(lbm_solver *h, double *part, double *res) {
     const size_t m2 = current_moments(h);
     LAUNCH_CHECK();
-    dispatch(h, StatsPass{h, m2});
+    dispatch(h, StatsPass{h, m2, part});
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(lbm::k_stats_final, dim3(1), dim3(256), 0, h->stream,
-                       ws_ptr<const double>(h, h->L.part), stats_blocks(h),
-                       ws_ptr<double>(h, h->L.res));
+    hipLaunchKernelGGL(lbm::k_stats_final, dim3(1), dim3(256), 0, h->stream, part,
+                       stats_blocks(h), res);
     LAUNCH_CHECK();
     return LBM_OK;
 }
@@ -235,10 +237,11 @@ LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes) {
     bool bo, bv;
     rc = boundary_nodes(p, D, N, &nb, &bo, &bv);
     if (rc) return rc;
-    const size_t ntiles = 8 * (size_t)make_tiling(p->nx, p->ny, p->nz, packed_rows_ok(p)).per;
+    const lbm::Tiling tl = make_tiling(p->nx, p->ny, p->nz, packed_rows_ok(p));
     *workspace_bytes = make_layout(Q, D, (size_t)N, sp, s, p->mask != nullptr,
-                                   p->scheme == LBM_SCHEME_LAGGED, ntiles, nb,
-                                   p->picard_iters > 0, p->grad_eps != nullptr).total;
+                                   p->scheme == LBM_SCHEME_LAGGED, 8 * (size_t)tl.per,
+                                   zflag_count(tl, p->nz), nb, p->picard_iters > 0,
+                                   p->grad_eps != nullptr).total;
     return LBM_OK;
 }
 
@@ -296,8 +299,8 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     if (rc) return rc;
     const lbm::Tiling tiles = make_tiling(p->nx, p->ny, p->nz, packed_rows_ok(p));
     const Layout L = make_layout(Q, D, (size_t)N, sp, s, solids, p->scheme == LBM_SCHEME_LAGGED,
-                                 8 * (size_t)tiles.per, nb, p->picard_iters > 0,
-                                 p->grad_eps != nullptr);
+                                 8 * (size_t)tiles.per, zflag_count(tiles, p->nz), nb,
+                                 p->picard_iters > 0, p->grad_eps != nullptr);
     if (!dev_workspace) return fail(LBM_ERR_INVALID_ARG, "dev_workspace is NULL");
     if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
         return fail(LBM_ERR_WORKSPACE, "dev_workspace must be 256-byte aligned");
@@ -318,6 +321,7 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->ws = reinterpret_cast<char *>(dev_workspace);
     h->L = L;
     h->tiles = tiles;
+    h->zm = make_zmarch(tiles, p->nz);
     h->step = 0;
     h->phase = 0;
     h->scheme = p->scheme;
@@ -338,6 +342,10 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->picard_iters = p->picard_iters;
     h->picard_omega = p->picard_omega;
     h->analytic = p->grad_eps != nullptr;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(LBM_ERR_HIP, "hipGetDevice failed");
+    }
     for (int a = 0; a < 3; ++a) h->b[a] = a < D ? p->b[a] : 0.0;
 
     auto cleanup = [&](int code) {
@@ -370,17 +378,19 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
                            ws_ptr<float>(h, L.eps), ws_ptr<float>(h, L.muD), ws_ptr<float>(h, L.muF), N, p->nu_f);
     if ((e = hipGetLastError()) != hipSuccess)
         return cleanup(fail(LBM_ERR_HIP, "static-field kernel failed: %s", hipGetErrorString(e)));
-    if (!h->analytic) {  // after the static-field kernel has written eps (same stream)
-        uint8_t *tf = reinterpret_cast<uint8_t *>(h->ws + L.tflat);
+    {  // after the static-field kernel has written eps and the mask is uploaded (same stream)
+        uint8_t *zf = reinterpret_cast<uint8_t *>(h->ws + L.zflags);
+        const dim3 zg((unsigned)zflag_count(tiles, p->nz));
+        const int an = h->analytic ? 1 : 0;
         if (h->storage == LBM_F64) {
-            if (D == 2) hipLaunchKernelGGL((lbm::k_tile_flat<2, double>), cell_tiles(h), dim3(256), 0, h->stream, ws_ptr<const double>(h, L.eps), grid_of(h), h->tiles, tf);
-            else hipLaunchKernelGGL((lbm::k_tile_flat<3, double>), cell_tiles(h), dim3(256), 0, h->stream, ws_ptr<const double>(h, L.eps), grid_of(h), h->tiles, tf);
+            if (D == 2) hipLaunchKernelGGL((lbm::k_zflags<2, double>), zg, dim3(256), 0, h->stream, ws_ptr<const double>(h, L.eps), mask_ptr(h), an, grid_of(h), h->tiles, h->zm, zf);
+            else hipLaunchKernelGGL((lbm::k_zflags<3, double>), zg, dim3(256), 0, h->stream, ws_ptr<const double>(h, L.eps), mask_ptr(h), an, grid_of(h), h->tiles, h->zm, zf);
         } else {
-            if (D == 2) hipLaunchKernelGGL((lbm::k_tile_flat<2, float>), cell_tiles(h), dim3(256), 0, h->stream, ws_ptr<const float>(h, L.eps), grid_of(h), h->tiles, tf);
-            else hipLaunchKernelGGL((lbm::k_tile_flat<3, float>), cell_tiles(h), dim3(256), 0, h->stream, ws_ptr<const float>(h, L.eps), grid_of(h), h->tiles, tf);
+            if (D == 2) hipLaunchKernelGGL((lbm::k_zflags<2, float>), zg, dim3(256), 0, h->stream, ws_ptr<const float>(h, L.eps), mask_ptr(h), an, grid_of(h), h->tiles, h->zm, zf);
+            else hipLaunchKernelGGL((lbm::k_zflags<3, float>), zg, dim3(256), 0, h->stream, ws_ptr<const float>(h, L.eps), mask_ptr(h), an, grid_of(h), h->tiles, h->zm, zf);
         }
         if ((e = hipGetLastError()) != hipSuccess)
-            return cleanup(fail(LBM_ERR_HIP, "flat-tile kernel failed: %s", hipGetErrorString(e)));
+            return cleanup(fail(LBM_ERR_HIP, "z-march flag kernel failed: %s", hipGetErrorString(e)));
     }
     const double *rho_st = nullptr, *v_st = nullptr;
     if (p->rho_init) {

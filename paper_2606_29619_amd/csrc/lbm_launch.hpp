@@ -38,10 +38,11 @@ void launch_picard(const lbm_solver *h, size_t vin, size_t vout) {
 template <int D, typename T, bool S, bool AD>
 void launch_vcorrect(const lbm_solver *h, size_t own_src, size_t m1, size_t m2_out) {
     auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_vcorrect<D, T, S, AD>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<const lbm::P4<T>>(h, own_src), ws_ptr<const lbm::P4<T>>(h, m1),
-                       ws_ptr<const T>(h, h->L.eps), mask_ptr(h), tsolid_ptr(h), tflat_ptr(h),
-                       ws_ptr<lbm::P4<T>>(h, m2_out), grid_of(h), h->tiles, ph);
+    hipLaunchKernelGGL((lbm::k_vcorrect_z<D, T, S, AD>), dim3(8 * h->zm.per), dim3(256), 0,
+                       h->stream, ws_ptr<const lbm::P4<T>>(h, own_src),
+                       ws_ptr<const lbm::P4<T>>(h, m1), ws_ptr<const T>(h, h->L.eps),
+                       mask_ptr(h), zflags_ptr(h), ws_ptr<lbm::P4<T>>(h, m2_out), grid_of(h),
+                       h->tiles, h->zm, ph);
 }
 
 template <int D, typename T, typename P, bool S, int PH, bool AD>
@@ -96,11 +97,11 @@ inline int stats_blocks(const lbm_solver *h) {
 }
 
 template <int D, typename T, typename P, bool S, int PH>
-void launch_stats(const lbm_solver *h, size_t m2) {
+void launch_stats(const lbm_solver *h, size_t m2, double *part) {
     hipLaunchKernelGGL((lbm::k_stats<D, T, P, S, PH>), dim3(stats_blocks(h)), dim3(256), 0,
                        h->stream, ws_ptr<const P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
                        ws_ptr<T>(h, h->L.vsnap), mask_ptr(h), ws_ptr<const T>(h, h->L.eps),
-                       ws_ptr<double>(h, h->L.part), grid_of(h), phys_of<T>(h));
+                       part, grid_of(h), phys_of<T>(h));
 }
 
 // ---- wet-node boundary kernels (one thread per boundary node; boundaries imply solids) -----
@@ -259,8 +260,9 @@ struct StatsPass {
     static constexpr bool kDerivs = false;
     const lbm_solver *h;
     size_t m2;
+    double *part;  // per-block partial sums (stats_blocks(h) rows of kStatsSlots)
     template <int D, typename T, typename P, bool S, int PH>
-    void operator()() { launch_stats<D, T, P, S, PH>(h, m2); }
+    void operator()() { launch_stats<D, T, P, S, PH>(h, m2, part); }
 };
 struct ExportPass {
     static constexpr bool kDerivs = false;

@@ -72,6 +72,69 @@ def test_uniform_box_is_trapezoidal_rule(D):
     np.testing.assert_allclose(v.reshape(D, -1)[:, 0], vstar * np.asarray(b) / bn, rtol=1e-12)
 
 
+def test_statistics_of_uniform_box_follow_trapezoidal_rule():
+    """The global statistics (Sec. 4.2, eq. SS_convergence_L2, and the conservation sums) in a
+    uniform periodic box, against values fixed without the oracle: every cell carries the same
+    v_n of the trapezoidal recurrence and rho = rho0 (mass conservation), so the momentum is
+    N rho0 v_n, max|v| = |v_n| and the residual between two calls is |v_n - v_m| / |v_m|."""
+    eps, K, cf, nu, rho0 = 0.45, 0.3, 1.2, 0.04, 1.1
+    b = (1.5e-3, -8e-4, 6e-4)
+    shape = (3, 4, 5)
+    N = 60
+    o = oracle.Oracle(oracle.OracleConfig(
+        D=3, eps=np.full(shape, eps), kappa=np.full(shape, K), cf=np.full(shape, cf),
+        nu_f=nu, nu_eff_ref=nu, b=b, rho0=rho0))
+    muD, muF = eps * nu / K, eps * cf
+    ref = _trapezoid_reference(eps, b, muD, muF, 120)
+    s0 = o.stats()
+    assert math.isinf(s0["residual"]) and s0["vmax"] < 1e-15      # v_0 = 0 up to rounding
+    np.testing.assert_allclose(s0["mass"], N * eps * rho0, rtol=1e-14)
+    prev = 0
+    for t in (7, 30, 31, 120):
+        o.step(t - prev)
+        s = o.stats()
+        vn, vm = ref[t], ref[prev]
+        np.testing.assert_allclose(s["momentum"], N * rho0 * vn, rtol=1e-13)
+        np.testing.assert_allclose(s["vmax"], np.linalg.norm(vn), rtol=1e-13)
+        if prev > 0:
+            want = np.linalg.norm(vn - vm) / np.linalg.norm(vm)
+            np.testing.assert_allclose(s["residual"], want, rtol=1e-9)
+        np.testing.assert_allclose(s["mass"], N * eps * rho0, rtol=1e-14)
+        assert s["nonfinite"] == 0
+        prev = t
+
+
+def test_statistics_use_the_corrected_velocity():
+    """Where the porosity varies, the corrected velocity v of eq. (v_final) differs from the
+    drag-solve velocity v^(1); the statistics are those of v (the velocity the paper's
+    convergence measure and momentum refer to), which the channel and BVP pins fix.  The
+    case is chosen so that statistics taken from v^(1) would miss by far more than rounding."""
+    w = workloads.random_porosity_3d(shape=(8, 10, 12), seed=5, ell=2.0, nu=0.05, b=4e-4)
+    mask = np.zeros(w.shape, dtype=np.uint8)
+    mask[2:4, 3:6, 4:7] = 1
+    o = oracle.Oracle(oracle.OracleConfig(
+        D=3, eps=w.eps, kappa=w.kappa, cf=w.forch, mask=mask, nu_f=w.nu_f,
+        nu_eff_ref=w.nu_eff_ref, b=w.b))
+    fluid = ~o.mask
+    o.step(20)
+    o.stats()
+    _, v_prev, _ = o.moments()
+    o.step(9)
+    s = o.stats()
+    rho, v, v1 = o.moments()
+    mom = np.array([(rho * v[a])[fluid].sum() for a in range(3)])
+    mom1 = np.array([(rho * v1[a])[fluid].sum() for a in range(3)])
+    np.testing.assert_allclose(s["momentum"], mom, rtol=1e-12)
+    assert np.abs(mom1 - mom).max() > 1e-6 * np.abs(mom).max()
+    speed = np.sqrt((v ** 2).sum(0))[fluid]
+    speed1 = np.sqrt((v1 ** 2).sum(0))[fluid]
+    np.testing.assert_allclose(s["vmax"], speed.max(), rtol=1e-14)
+    assert abs(speed1.max() - speed.max()) > 1e-6 * speed.max()
+    d = v - v_prev
+    want = math.sqrt((d ** 2).sum(0)[fluid].sum() / (v_prev ** 2).sum(0)[fluid].sum())
+    np.testing.assert_allclose(s["residual"], want, rtol=1e-10)
+
+
 def test_darcy_limit_of_uniform_box():
     """Darcy limit (mu_F = 0): the steady superficial velocity is kappa b / nu_f."""
     eps, K, nu = 0.3, 0.05, 0.02

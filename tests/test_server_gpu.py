@@ -159,3 +159,51 @@ def test_diverging_request_fails_without_disturbing_others():
     gi = srv.info(g_id)
     assert gi.state == capi.LBM_REQ_CENSORED and gi.steps == 300
     assert _same(srv.solver(g_id), _alone(good, capi.LBM_F64, capi.LBM_SCHEME_TWO_PASS, 300))
+
+
+def _field_err(srv_solver, o):
+    import oracle  # noqa: F401  (the checker; test infrastructure)
+    f_gpu = srv_solver.populations(torch.float64).cpu().numpy()
+    rho_gpu, v_gpu = (t.cpu().numpy() for t in srv_solver.moments(torch.float64))
+    f_ref = o.populations()
+    rho_ref, v_ref, _ = o.moments()
+    rel = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())
+    errs = {"f": rel(f_gpu, f_ref), "rho": rel(rho_gpu, rho_ref)}
+    for a in range(v_ref.shape[0]):
+        errs[f"v{a}"] = rel(v_gpu[a], v_ref[a])
+    return errs
+
+
+def test_served_fp64_requests_match_the_oracle():
+    """Served results against the FP64 oracle itself, not only against runs alone: two FP64
+    requests (D3Q27 with solid cells and the bulk-viscosity correction, two-pass; D2Q9
+    lagged) are served in one batch with FP32 and FP16 requests for 200 steps (censored at the
+    step cap) and must match the oracle's fields to 1e-12 (normwise per field)."""
+    import oracle
+    c = _mix()[2][0]
+    c.eta_eff = 0.015
+    a = _mix()[0][0]
+    fill = _mix()
+    srv = capi.Server(pool_bytes=512 << 20, check_every=100)
+    ids = [srv.submit(w, storage=st, scheme=sc, tol=1e-300, max_steps=200)
+           for w, st, sc in fill[:2] + fill[3:5]]
+    r_c = srv.submit(c, storage=capi.LBM_F64, scheme=capi.LBM_SCHEME_TWO_PASS, tol=1e-300,
+                     max_steps=200)
+    r_a = srv.submit(a, storage=capi.LBM_F64, scheme=capi.LBM_SCHEME_LAGGED, tol=1e-300,
+                     max_steps=200)
+    _drain(srv)
+    for rid, w, lagged in ((r_c, c, 0), (r_a, a, 1)):
+        info = srv.info(rid)
+        assert info.state == capi.LBM_REQ_CENSORED and info.steps == 200
+        o = oracle.Oracle(oracle.OracleConfig(
+            D=w.D, eps=w.eps, kappa=w.kappa, cf=w.forch, mask=w.mask, RT=w.RT, nu_f=w.nu_f,
+            nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow, eta_eff=w.eta_eff, b=w.b,
+            rho0=w.rho0, lagged=lagged))
+        o.step(200)
+        errs = _field_err(srv.solver(rid), o)
+        print(f"served fp64 request {rid} (lagged={lagged}) vs oracle:",
+              " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+        assert max(errs.values()) <= 1e-12, errs
+    for rid in ids + [r_c, r_a]:
+        srv.release(rid)
+    srv.close()
