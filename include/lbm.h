@@ -311,8 +311,9 @@ LBM_API int lbm_lattice_info(int lattice, int *c_out, int *opp_out);
  * solids flag, scheme and AA phase (kernel boundaries are the per-request step barriers), so
  * small runs fill the GPU together.  After each round the server takes each run's statistics
  * (lbm_residual's FP64 reductions) and retires runs whose relative L2 change of v over the
- * round fell below tol (converged), that reached max_steps (censored) or that hold non-finite
- * values (failed).  Each run's arithmetic is that of lbm_step, so its result is bitwise the same
+ * round fell below tol (converged), whose residual stopped falling (at the rounding floor of
+ * their storage, when the caller asks for that rule), that reached max_steps (censored) or that
+ * hold non-finite values (failed).  Each run's arithmetic is that of lbm_step, so its result is bitwise the same
  * alone and in any mix.  All work is enqueued on the server's stream; progress synchronises it
  * once per round.  A server handle must not be used from two threads at once.
  * ------------------------------------------------------------------------------------------ */
@@ -323,6 +324,7 @@ typedef struct lbm_server lbm_server;
 #define LBM_REQ_CONVERGED 2
 #define LBM_REQ_CENSORED 3   /* reached max_steps before tol */
 #define LBM_REQ_FAILED 4     /* creation failed or the state became non-finite */
+#define LBM_REQ_FLOOR 5      /* the residual stopped falling above tol (see lbm_server_submit) */
 
 typedef struct lbm_request_info {
     int64_t id;
@@ -359,14 +361,20 @@ LBM_API int lbm_server_create(void *dev_pool, size_t pool_bytes, int64_t check_e
 /*
  * Queue a run.  The params and every host array they point to are copied, so the caller may
  * free them on return.  tol > 0 is the steady-state threshold on the relative L2 change of v
- * over one round; max_steps >= check_every caps the run.  *id receives the request id (ids
- * count from 0 in submission order).  Errors: those of lbm_footprint, LBM_ERR_INVALID_ARG,
- * LBM_ERR_WORKSPACE (the run can never fit in the pool), LBM_ERR_UNSUPPORTED for runs with
- * wet-node boundaries (bc_type), Picard iterations or analytic porosity derivatives, which
- * lbm_create serves one run at a time.
+ * over one round (Sec. 4.2's measure, eq. SS_convergence_L2, taken over check_every steps);
+ * max_steps >= check_every caps the run.  floor_checks > 0 adds a retirement rule for storage
+ * whose rounding keeps the residual above tol: the state keeps changing by rounding noise
+ * about the steady state, so the residual stops falling at a floor set by the precision (FP32
+ * and the 16-bit forms stay far above 1e-7); a run whose residual has made no new minimum (1 %
+ * below the previous one) for floor_checks rounds retires as LBM_REQ_FLOOR with its residual
+ * reported.  0 leaves the rule off.  *id receives the request id (ids count from 0 in
+ * submission order).  Errors: those of lbm_footprint, LBM_ERR_INVALID_ARG, LBM_ERR_WORKSPACE
+ * (the run can never fit in the pool), LBM_ERR_UNSUPPORTED for runs with wet-node boundaries
+ * (bc_type), Picard iterations or analytic porosity derivatives, which lbm_create serves one
+ * run at a time.
  */
 LBM_API int lbm_server_submit(lbm_server *s, const lbm_params *p, double tol, int64_t max_steps,
-                              int64_t *id);
+                              int floor_checks, int64_t *id);
 
 /*
  * Run up to max_rounds rounds (admission, check_every steps of every active run, statistics,

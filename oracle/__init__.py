@@ -21,17 +21,23 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
-_LIB = os.path.join(_HERE, "liblbm_oracle.so")
+# LBM_ORACLE_SANITIZE=1 selects a build with AddressSanitizer and UndefinedBehaviorSanitizer
+# (host code only; the process must preload libasan, see tests/test_oracle_sanitized.py)
+SANITIZE = os.environ.get("LBM_ORACLE_SANITIZE", "") == "1"
+_LIB = os.path.join(_HERE, "liblbm_oracle_san.so" if SANITIZE else "liblbm_oracle.so")
 
 CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
           "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                  "-fno-omit-frame-pointer", "-g"]
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, no vectorisation-sensitive flags)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        extra = SANITIZE_FLAGS if SANITIZE else []
+        subprocess.check_call(["gcc", *CFLAGS, *extra, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

@@ -80,6 +80,7 @@ LBM_REQ_ACTIVE = 1
 LBM_REQ_CONVERGED = 2
 LBM_REQ_CENSORED = 3
 LBM_REQ_FAILED = 4
+LBM_REQ_FLOOR = 5
 
 
 class lbm_request_info(ctypes.Structure):
@@ -138,7 +139,7 @@ def load() -> ctypes.CDLL:
     L.lbm_server_create.argtypes = [vp, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int, vp,
                                     ctypes.POINTER(vp)]
     L.lbm_server_submit.argtypes = [vp, ctypes.POINTER(lbm_params), ctypes.c_double,
-                                    ctypes.c_int64, i64p]
+                                    ctypes.c_int64, ctypes.c_int, i64p]
     L.lbm_server_progress.argtypes = [vp, ctypes.c_int64, i64p, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]
     L.lbm_server_info.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(lbm_request_info)]
@@ -237,10 +238,11 @@ def lbm_server_create(pool_ptr: int, pool_bytes: int, check_every: int, max_acti
     return h
 
 
-def lbm_server_submit(s, p: lbm_params, tol: float, max_steps: int) -> int:
+def lbm_server_submit(s, p: lbm_params, tol: float, max_steps: int,
+                      floor_checks: int = 0) -> int:
     rid = ctypes.c_int64(-1)
     _check(load().lbm_server_submit(s, ctypes.byref(p), float(tol), int(max_steps),
-                                    ctypes.byref(rid)), "lbm_server_submit")
+                                    int(floor_checks), ctypes.byref(rid)), "lbm_server_submit")
     return rid.value
 
 
@@ -460,13 +462,15 @@ class Server:
         self._h = lbm_server_create(self.pool.data_ptr(), int(pool_bytes), check_every,
                                     max_active, self.stream.cuda_stream)
 
-    def submit_params(self, params: lbm_params, tol: float, max_steps: int) -> int:
-        rid = lbm_server_submit(self._h, params, tol, max_steps)
+    def submit_params(self, params: lbm_params, tol: float, max_steps: int,
+                      floor_checks: int = 0) -> int:
+        rid = lbm_server_submit(self._h, params, tol, max_steps, floor_checks)
         self._params[rid] = params
         return rid
 
     def submit(self, w, storage: int = LBM_F32, tol: float = 1e-7, max_steps: int = 200000,
-               scheme: int = LBM_SCHEME_TWO_PASS, shift: int = LBM_SHIFT_POROUS) -> int:
+               scheme: int = LBM_SCHEME_TWO_PASS, shift: int = LBM_SHIFT_POROUS,
+               floor_checks: int = 0) -> int:
         p, _keep = make_params(w.lattice, storage, w.eps, w.kappa, w.forch, w.mask, RT=w.RT,
                                nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow,
                                eta_eff=w.eta_eff, b=w.b, rho0=w.rho0, rho_init=w.rho_init,
@@ -479,7 +483,7 @@ class Server:
                               bc_rho_rule=getattr(w, "bc_rho_rule", LBM_BC_RHO_CONTINUITY),
                               picard_iters=getattr(w, "picard_iters", 0),
                               picard_omega=getattr(w, "picard_omega", 1.0))
-        rid = self.submit_params(p, tol, max_steps)   # the library copies the arrays
+        rid = self.submit_params(p, tol, max_steps, floor_checks)  # the library copies the arrays
         return rid
 
     def progress(self, max_rounds: int = 1):

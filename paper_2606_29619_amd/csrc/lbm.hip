@@ -239,9 +239,8 @@ LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes) {
     if (rc) return rc;
     const lbm::Tiling tl = make_tiling(p->nx, p->ny, p->nz, packed_rows_ok(p));
     *workspace_bytes = make_layout(Q, D, (size_t)N, sp, s, p->mask != nullptr,
-                                   p->scheme == LBM_SCHEME_LAGGED, 8 * (size_t)tl.per,
-                                   zflag_count(tl, p->nz), nb, p->picard_iters > 0,
-                                   p->grad_eps != nullptr).total;
+                                   p->scheme == LBM_SCHEME_LAGGED, 8 * (size_t)tl.per, nb,
+                                   p->picard_iters > 0, p->grad_eps != nullptr).total;
     return LBM_OK;
 }
 
@@ -299,8 +298,8 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     if (rc) return rc;
     const lbm::Tiling tiles = make_tiling(p->nx, p->ny, p->nz, packed_rows_ok(p));
     const Layout L = make_layout(Q, D, (size_t)N, sp, s, solids, p->scheme == LBM_SCHEME_LAGGED,
-                                 8 * (size_t)tiles.per, zflag_count(tiles, p->nz), nb,
-                                 p->picard_iters > 0, p->grad_eps != nullptr);
+                                 8 * (size_t)tiles.per, nb, p->picard_iters > 0,
+                                 p->grad_eps != nullptr);
     if (!dev_workspace) return fail(LBM_ERR_INVALID_ARG, "dev_workspace is NULL");
     if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
         return fail(LBM_ERR_WORKSPACE, "dev_workspace must be 256-byte aligned");
@@ -321,7 +320,6 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->ws = reinterpret_cast<char *>(dev_workspace);
     h->L = L;
     h->tiles = tiles;
-    h->zm = make_zmarch(tiles, p->nz);
     h->step = 0;
     h->phase = 0;
     h->scheme = p->scheme;
@@ -378,19 +376,17 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
                            ws_ptr<float>(h, L.eps), ws_ptr<float>(h, L.muD), ws_ptr<float>(h, L.muF), N, p->nu_f);
     if ((e = hipGetLastError()) != hipSuccess)
         return cleanup(fail(LBM_ERR_HIP, "static-field kernel failed: %s", hipGetErrorString(e)));
-    {  // after the static-field kernel has written eps and the mask is uploaded (same stream)
-        uint8_t *zf = reinterpret_cast<uint8_t *>(h->ws + L.zflags);
-        const dim3 zg((unsigned)zflag_count(tiles, p->nz));
-        const int an = h->analytic ? 1 : 0;
+    if (!h->analytic) {  // after the static-field kernel has written eps (same stream)
+        uint8_t *tf = reinterpret_cast<uint8_t *>(h->ws + L.tflat);
         if (h->storage == LBM_F64) {
-            if (D == 2) hipLaunchKernelGGL((lbm::k_zflags<2, double>), zg, dim3(256), 0, h->stream, ws_ptr<const double>(h, L.eps), mask_ptr(h), an, grid_of(h), h->tiles, h->zm, zf);
-            else hipLaunchKernelGGL((lbm::k_zflags<3, double>), zg, dim3(256), 0, h->stream, ws_ptr<const double>(h, L.eps), mask_ptr(h), an, grid_of(h), h->tiles, h->zm, zf);
+            if (D == 2) hipLaunchKernelGGL((lbm::k_tile_flat<2, double>), cell_tiles(h), dim3(256), 0, h->stream, ws_ptr<const double>(h, L.eps), grid_of(h), h->tiles, tf);
+            else hipLaunchKernelGGL((lbm::k_tile_flat<3, double>), cell_tiles(h), dim3(256), 0, h->stream, ws_ptr<const double>(h, L.eps), grid_of(h), h->tiles, tf);
         } else {
-            if (D == 2) hipLaunchKernelGGL((lbm::k_zflags<2, float>), zg, dim3(256), 0, h->stream, ws_ptr<const float>(h, L.eps), mask_ptr(h), an, grid_of(h), h->tiles, h->zm, zf);
-            else hipLaunchKernelGGL((lbm::k_zflags<3, float>), zg, dim3(256), 0, h->stream, ws_ptr<const float>(h, L.eps), mask_ptr(h), an, grid_of(h), h->tiles, h->zm, zf);
+            if (D == 2) hipLaunchKernelGGL((lbm::k_tile_flat<2, float>), cell_tiles(h), dim3(256), 0, h->stream, ws_ptr<const float>(h, L.eps), grid_of(h), h->tiles, tf);
+            else hipLaunchKernelGGL((lbm::k_tile_flat<3, float>), cell_tiles(h), dim3(256), 0, h->stream, ws_ptr<const float>(h, L.eps), grid_of(h), h->tiles, tf);
         }
         if ((e = hipGetLastError()) != hipSuccess)
-            return cleanup(fail(LBM_ERR_HIP, "z-march flag kernel failed: %s", hipGetErrorString(e)));
+            return cleanup(fail(LBM_ERR_HIP, "flat-tile kernel failed: %s", hipGetErrorString(e)));
     }
     const double *rho_st = nullptr, *v_st = nullptr;
     if (p->rho_init) {

@@ -453,48 +453,11 @@ __device__ __forceinline__ T load_pop(const P *__restrict__ f, const uint8_t *__
     return decode<D, I, T>(raw, load_sigma<D, SOLIDS, I, P>(mask, ev, ph, nb));
 }
 
-// One-lane rotation within a wave (DPP wave_ror:1 for R = +1: lane k receives lane k - 1 and
-// lane 0 receives lane 63; wave_rol:1 for R = -1: lane k receives lane k + 1, lane 63 lane 0).
-template <int R>
-__device__ __forceinline__ uint32_t rot1(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, R > 0 ? 0x13C : 0x134, 0xf, 0xf,
-                                                 false);
-}
-template <int R, typename P>
-__device__ __forceinline__ P rot_lane(P v) {
-    if constexpr (sizeof(P) == 8) {
-        uint2 u = __builtin_bit_cast(uint2, v);
-        u.x = rot1<R>(u.x);
-        u.y = rot1<R>(u.y);
-        return __builtin_bit_cast(P, u);
-    } else if constexpr (sizeof(P) == 4) {
-        return __builtin_bit_cast(P, rot1<R>(__builtin_bit_cast(uint32_t, v)));
-    } else {
-        const uint32_t u = rot1<R>((uint32_t)__builtin_bit_cast(uint16_t, v));
-        return __builtin_bit_cast(P, (uint16_t)u);
-    }
-}
-
-// Rotated stores of the swapped AA phase.  There a population moving along x is written to
-// the neighbour x + c_x, so a wave's store is offset by one element from the cache lines and
-// straddles one line more than it fills.  When a wave holds 64 consecutive cells of one row
-// (rectangular tiles, all lanes active, no solid cell near the tile), the value is rotated by
-// one lane instead: 63 lanes store at their own x in the destination row and one lane, at the
-// wave edge, stores the element across it (x + 64 for c_x = +1 on lane 0, x - 64 for
-// c_x = -1 on lane 63, periodic).  Same slots, same values; measured on the bare 27-plane
-// pattern at 256^3: 0.749 -> 0.708 ms per pass.
-struct RotStore {
-    bool on;      // wave-uniform
-    uint32_t xp;  // lane 0: x + 64 (wrapped), other lanes: x
-    uint32_t xm;  // lane 63: x - 64 (wrapped), other lanes: x
-};
-
 // Store of the post-collision f_I of the cell; base is the cell's own shift base
 // (rho0 or rho0 eps(n)) for the 16-bit formats.
 template <int D, bool SOLIDS, int PH, int I, typename T, typename P>
 __device__ __forceinline__ void store_pop(P *__restrict__ f, const uint8_t *__restrict__ mask,
-                                          const Grid &g, const Nbr<D> &nb, T val, float base,
-                                          const RotStore &rs = RotStore{false, 0u, 0u}) {
+                                          const Grid &g, const Nbr<D> &nb, T val, float base) {
     using L = Lat<D>;
     constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
     const uint32_t n = nb.self();
@@ -507,13 +470,6 @@ __device__ __forceinline__ void store_pop(P *__restrict__ f, const uint8_t *__re
         if constexpr (SOLIDS) {
             if (mask[d]) {
                 st_pop<NT>(plane(f, L::opp[I], g.N), n, raw);
-                return;
-            }
-        } else if constexpr (cx != 0) {
-            if (rs.on) {
-                const P r = rot_lane<cx>(raw);
-                const uint32_t xd = cx > 0 ? rs.xp : rs.xm;
-                st_pop<NT>(plane(f, I, g.N), nb.row[cy + 1][cz + 1] + xd, r);
                 return;
             }
         }
@@ -1019,21 +975,6 @@ __device__ __forceinline__ int tile_cell(const Grid &g, const Tiling &tl, uint32
     return x < g.nx && y < g.ny ? 1 : 0;
 }
 
-template <int D>
-__device__ __forceinline__ RotStore rot_store_of(const Grid &g, const Tiling &tl, int x,
-                                                 bool eligible) {
-    RotStore r{false, (uint32_t)x, (uint32_t)x};
-    if (!eligible || tl.packed) return r;
-    // x of the wave's first lane (lane 0 is active whenever any lane of the wave is: it has the
-    // smallest x of the row segment); a wave of a rectangular tile lies in one row
-    const int xw = __builtin_amdgcn_readfirstlane(x);
-    r.on = xw + 64 <= g.nx;
-    const uint32_t lane = threadIdx.x & 63u;
-    if (lane == 0u) r.xp = (uint32_t)(x + 64 >= g.nx ? x + 64 - g.nx : x + 64);
-    if (lane == 63u) r.xm = (uint32_t)(x - 64 < 0 ? x - 64 + g.nx : x - 64);
-    return r;
-}
-
 // Cell prologue of the kernels that read porosity from global memory.
 #define LBM_CELL_PROLOGUE_W(D, W)                                    \
     int x, y, z, x0_, y0_;                                           \
@@ -1152,8 +1093,7 @@ __device__ __forceinline__ void collide_stream(P *__restrict__ f,
                                                const uint8_t *__restrict__ mask, const Grid &g,
                                                const Nbr<D> &nb, const T fi[], T beta, float base,
                                                const ProductForm<D, T> &peq,
-                                               const ProductForm<D, T> &pst,
-                                               const RotStore &rs) {
+                                               const ProductForm<D, T> &pst) {
     using L = Lat<D>;
     const T two_beta = T(2) * beta;
     const T omb = T(1) - beta;
@@ -1162,7 +1102,7 @@ __device__ __forceinline__ void collide_stream(P *__restrict__ f,
         const T feq = peq.template at<i>();
         const T fst = pst.template at<i>();
         const T fpc = (fi[i] + two_beta * (feq - fi[i])) + omb * (fst - feq);
-        store_pop<D, SOLIDS, PH, i>(f, mask, g, nb, fpc, base, rs);
+        store_pop<D, SOLIDS, PH, i>(f, mask, g, nb, fpc, base);
     });
 }
 
@@ -1249,7 +1189,6 @@ __device__ __forceinline__ void collide_body(P *__restrict__ f,
     // fast as before, and the recomputation cost 1 %.
     constexpr bool kOpaque = PH == 1 && sizeof(P) != 4;
     const Nbr<D> nbp = kOpaque ? nb.opaque() : nb;
-    const RotStore rs = rot_store_of<D>(g, tl, x, PH == 1 && !SOLIDS);
     unroll<0, PairGroups<D>::n>([&](auto gg) {
         constexpr int k = decltype(gg)::value;
         constexpr int g0 = PairGroups<D>::begin(k), g1 = PairGroups<D>::begin(k + 1);
@@ -1280,7 +1219,7 @@ __device__ __forceinline__ void collide_body(P *__restrict__ f,
             const T feq = peq.template at<i>();
             const T fst = pst.template at<i>();
             const T fpc = (fi[i - g0] + two_beta * (feq - fi[i - g0])) + omb * (fst - feq);
-            store_pop<D, SOLIDS, PH, i>(f, mask, g, nbp, fpc, base, rs);
+            store_pop<D, SOLIDS, PH, i>(f, mask, g, nbp, fpc, base);
         });
         __builtin_amdgcn_sched_barrier(0);
     });
@@ -1321,8 +1260,7 @@ __device__ __forceinline__ void fused_body(P *__restrict__ f, const P4<T> *__res
     ProductForm<D, T> peq, pst;
     cell_equilibria<D, T, SOLIDS>(m2p, ev, eps, muD, muF, mask, g, ph, nb, own2, cs, peq, pst);
     collide_stream<D, T, P, SOLIDS, PH>(f, mask, g, PH == 1 ? nb.opaque() : nb, fi, cs.vs.beta,
-                                        own_base<P>(ev.at(0, 0, 0), ph), peq, pst,
-                                        rot_store_of<D>(g, tl, x, PH == 1 && !SOLIDS));
+                                        own_base<P>(ev.at(0, 0, 0), ph), peq, pst);
     store_rec<D>(m1n, n, own1.r, own1.w);
     store_rec<D>(m2n, n, own2.r, own2.w);
 }
@@ -1417,126 +1355,42 @@ __global__ __launch_bounds__(256) void k_moments(const P *__restrict__ f,
                                           blockIdx.x);
 }
 
-// ------------------------------------------------------------------------------------------
-// Velocity correction marching along z.  The correction of a cell reads the (rho, v^(1))
-// records and the porosity of its neighbours in the planes z - 1, z, z + 1.  A workgroup owns
-// one in-plane tile (the tiles of the plane passes) and a chunk of consecutive planes, which it
-// walks in order: a neighbour plane is read again from the caches while the next plane is
-// corrected, the tile's position is decoded once per chunk instead of once per plane, and the
-// eight XCDs take contiguous ranges of (chunk, tile) with the tile index fastest, so that the
-// workgroups of one XCD correct neighbouring rows of the same planes at the same time.
-// ------------------------------------------------------------------------------------------
-struct ZMarch {
-    uint32_t ntile;  // in-plane tiles: ntx * nty (rectangular) or nty (packed rows)
-    uint32_t zc;     // planes per chunk
-    uint32_t nwork;  // ntile * ceil(nz / zc)
-    uint32_t per;    // workgroups per XCD: ceil(nwork / 8)
-    uint64_t mnt;    // ceil(2^64 / ntile) (ntile >= 2): t / ntile = umulhi64(t, mnt)
-};
-
-// Cell of this thread in in-plane tile `it`: 1 when it lies in the grid, else 0.
-__device__ __forceinline__ int plane_cell(const Grid &g, const Tiling &tl, uint32_t it, int &x,
-                                          int &y) {
-    if (tl.packed) {
-        const uint32_t p = it * 256u + threadIdx.x;
-        if (p >= tl.pn) return 0;
-        const uint32_t q = g.nx > 1 ? (uint32_t)__umul64hi((uint64_t)p, tl.mnx) : p;
-        y = (int)q;
-        x = (int)(p - q * (uint32_t)g.nx);
-        return 1;
-    }
-    const uint32_t ty = it / (uint32_t)tl.ntx;  // uniform, once per workgroup
-    const uint32_t tx = it - ty * (uint32_t)tl.ntx;
-    x = (int)(tx * (uint32_t)tl.tx) + (int)(threadIdx.x & (uint32_t)(tl.tx - 1));
-    y = (int)(ty * (uint32_t)tl.ty) + (int)(threadIdx.x >> (uint32_t)tl.ltx);
-    return x < g.nx && y < g.ny ? 1 : 0;
-}
-
-// Per (in-plane tile, plane) flags of the z-marching passes, zflags[z * ntile + it]:
-// bit 0: a solid cell lies within one cell (26 directions, periodic) of a cell of the tile;
-// bit 1: some cell of the tile has a porosity neighbourhood (3 x 3 x 3, periodic) that is not
-// uniform, so differenced porosity derivatives can be nonzero there (always set with analytic
-// derivatives).
+// Velocity correction of a tile whose every cell has a uniform porosity neighbourhood: Delta_nu
+// vanishes, v = v^(1) + 0 (the value of the full evaluation), from the cell's own record only.
+// A solid cell's record is zero (the moment pass writes it so), and so is its copy: no mask
+// read is needed.
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_zflags(const T *__restrict__ eps,
-                                                const uint8_t *__restrict__ mask, int analytic,
-                                                Grid g, Tiling tl, ZMarch zm,
-                                                uint8_t *__restrict__ zflags) {
-    const uint32_t it = blockIdx.x % zm.ntile, z = blockIdx.x / zm.ntile;
-    int x = 0, y = 0;
-    const int act = plane_cell(g, tl, it, x, y);
-    int solid = 0, bumpy = analytic;
-    if (act) {
-        Nbr<D> nb;
-        nb.init(g, x, y, (int)z);
-        const T e0 = ld(eps, nb.self());
-        unroll<0, Lat<D>::Q>([&](auto ii) {
-            constexpr int i = decltype(ii)::value;
-            const uint32_t m = nb.at(Lat<D>::c[i][0], Lat<D>::c[i][1], Lat<D>::c[i][2]);
-            if (mask) solid |= mask[m];
-            bumpy |= ld(eps, m) != e0;
-        });
-    }
-    solid = __syncthreads_or(solid);
-    bumpy = __syncthreads_or(bumpy);
-    if (threadIdx.x == 0) zflags[blockIdx.x] = (uint8_t)((solid ? 1 : 0) | (bumpy ? 2 : 0));
+__device__ __forceinline__ void vcorrect_flat_body(const P4<T> *__restrict__ own_src,
+                                                   P4<T> *__restrict__ m2_out, Grid g,
+                                                   Tiling tl, uint32_t wg) {
+    int x, y, z, x0_, y0_;
+    if (tile_cell(g, tl, wg, x, y, z, x0_, y0_) != 1) return;
+    const uint32_t n = (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+    const P4<T> q = ld(own_src, n);
+    *at(m2_out, n) = pack(q.x, q.y + T(0), q.z + T(0), D == 3 ? q.w + T(0) : T(0));
 }
 
-// Correction of one cell (v_final) from the records in m1 and the porosity: writes (rho, v).
 template <int D, typename T, bool SOLIDS, bool AD>
-__device__ __forceinline__ void vcorrect_cell(const P4<T> *__restrict__ own_src,
-                                              const P4<T> *__restrict__ m1,
-                                              const T *__restrict__ eps,
-                                              const uint8_t *__restrict__ mask,
-                                              P4<T> *__restrict__ m2_out, const Grid &g,
-                                              const Phys<T> &ph, const Nbr<D> &nb) {
-    const uint32_t n = nb.self();
+__global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ own_src,
+                                                  const P4<T> *__restrict__ m1,
+                                                  const T *__restrict__ eps,
+                                                  const uint8_t *__restrict__ mask,
+                                                  const uint8_t *__restrict__ tsolid,
+                                                  const uint8_t *__restrict__ tflat,
+                                                  P4<T> *__restrict__ m2_out, Grid g, Tiling tl,
+                                                  Phys<T> ph) {
+    // tflat[w] = 0: no cell of tile w has a porosity gradient or Hessian (k_tile_flat)
+    if (tflat && !tflat[blockIdx.x]) {
+        vcorrect_flat_body<D, T>(own_src, m2_out, g, tl, blockIdx.x);
+        return;
+    }
     if constexpr (SOLIDS) {
-        if (mask[n]) {
-            *at(m2_out, n) = pack(T(0), T(0), T(0), T(0));
+        if (tile_free(tsolid)) {
+            vcorrect_body<D, T, false, AD>(own_src, m1, eps, mask, m2_out, g, tl, ph, blockIdx.x);
             return;
         }
     }
-    const EpsGlobal<D, T> ev{eps, &nb};
-    const Rec<T> own = load_rec<D>(own_src, n, ev.at(0, 0, 0));
-    const CellStatic<D, T> cs = cell_static<D, AD>(ev, ph, n, own.e);
-    T v[3];
-    corrected_velocity<D, T, SOLIDS>(m1, ev, eps, mask, g, nb, own, cs, v);
-    store_rec<D>(m2_out, n, own.r, v);
-}
-
-template <int D, typename T, bool SOLIDS, bool AD>
-__global__ __launch_bounds__(256) void k_vcorrect_z(const P4<T> *__restrict__ own_src,
-                                                    const P4<T> *__restrict__ m1,
-                                                    const T *__restrict__ eps,
-                                                    const uint8_t *__restrict__ mask,
-                                                    const uint8_t *__restrict__ zflags,
-                                                    P4<T> *__restrict__ m2_out, Grid g,
-                                                    Tiling tl, ZMarch zm, Phys<T> ph) {
-    const uint32_t t = (blockIdx.x & 7u) * zm.per + (blockIdx.x >> 3);
-    if (t >= zm.nwork) return;  // uniform over the workgroup
-    const uint32_t chunk = zm.ntile > 1 ? (uint32_t)__umul64hi((uint64_t)t, zm.mnt) : t;
-    const uint32_t it = t - chunk * zm.ntile;
-    int x = 0, y = 0;
-    if (!plane_cell(g, tl, it, x, y)) return;  // no barrier follows
-    const uint32_t z0 = chunk * zm.zc;
-    const uint32_t z1 = z0 + zm.zc < (uint32_t)g.nz ? z0 + zm.zc : (uint32_t)g.nz;
-    for (uint32_t z = z0; z < z1; ++z) {
-        const uint32_t fl = zflags[z * zm.ntile + it];  // uniform
-        Nbr<D> nb;
-        nb.init(g, x, y, (int)z);
-        const uint32_t n = nb.self();
-        if (!(fl & 2u)) {
-            // flat porosity around every cell of the tile: Delta_nu = 0, v = v^(1) + 0 (the
-            // value of the full evaluation; a solid cell's record is zero and stays so)
-            const P4<T> q = ld(own_src, n);
-            *at(m2_out, n) = pack(q.x, q.y + T(0), q.z + T(0), D == 3 ? q.w + T(0) : T(0));
-        } else if (SOLIDS && (fl & 1u)) {
-            vcorrect_cell<D, T, SOLIDS, AD>(own_src, m1, eps, mask, m2_out, g, ph, nb);
-        } else {
-            vcorrect_cell<D, T, false, AD>(own_src, m1, eps, mask, m2_out, g, ph, nb);
-        }
-    }
+    vcorrect_body<D, T, SOLIDS, AD>(own_src, m1, eps, mask, m2_out, g, tl, ph, blockIdx.x);
 }
 
 // Waves per SIMD requested for the kernels of runs with solids.  Such a kernel holds the
@@ -1610,6 +1464,29 @@ __global__ __launch_bounds__(256) void k_tile_solid(const uint8_t *__restrict__ 
     }
     any = __syncthreads_or(any);
     if (threadIdx.x == 0) tsolid[blockIdx.x] = any ? 1 : 0;
+}
+
+// tflat[w] = 1 when some cell of tile w has a porosity neighbourhood (the 3 x 3 (x 3) cells
+// around it, through the periodic wrap) that is not uniform, i.e. when differenced porosity
+// derivatives can be nonzero there; 0 lets the velocity correction skip the whole tile.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_tile_flat(const T *__restrict__ eps, Grid g, Tiling tl,
+                                                   uint8_t *__restrict__ tflat) {
+    int x, y, z, x0, y0;
+    const int act = tile_cell(g, tl, blockIdx.x, x, y, z, x0, y0);
+    if (act < 0) return;  // uniform over the workgroup
+    int bumpy = 0;
+    if (act) {
+        Nbr<D> nb;
+        nb.init(g, x, y, z);
+        const T e0 = ld(eps, nb.self());
+        unroll<0, Lat<D>::Q>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            bumpy |= ld(eps, nb.at(Lat<D>::c[i][0], Lat<D>::c[i][1], Lat<D>::c[i][2])) != e0;
+        });
+    }
+    bumpy = __syncthreads_or(bumpy);
+    if (threadIdx.x == 0) tflat[blockIdx.x] = bumpy ? 1 : 0;
 }
 
 // Initial populations, eq. (eq_bc_f_bar) with lambda = dt = 1, from the moment fields (rho, v):

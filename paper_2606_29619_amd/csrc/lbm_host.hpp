@@ -52,16 +52,15 @@ struct Layout {
     size_t m0, mx;              // (rho, v_0) records and a second velocity buffer (Picard)
     size_t deps;                // analytic porosity derivatives, D + D(D+1)/2 planes
     size_t tsolid;              // per-tile flag: a solid cell within one cell of the tile
-    size_t zflags;              // per (in-plane tile, plane) flags of the z-marching passes
+    size_t tflat;               // per-tile flag: a porosity gradient somewhere in the tile
     size_t total;
 };
 
 // sp: bytes per population value; s: bytes per value of the static fields and moment records.
-// ntiles: workgroups of the tiled passes (solid runs keep one flag byte per tile);
-// nzflags: (in-plane tile, plane) pairs of the z-marching passes (one flag byte each).
+// ntiles: workgroups of the tiled passes (solid runs keep one flag byte per tile).
 inline Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool solids, bool lagged,
-                          size_t ntiles, size_t nzflags, size_t nbnodes = 0,
-                          bool picard = false, bool analytic = false) {
+                          size_t ntiles, size_t nbnodes = 0, bool picard = false,
+                          bool analytic = false) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -91,7 +90,7 @@ inline Layout make_layout(int Q, int D, size_t N, size_t sp, size_t s, bool soli
     L.mx = picard ? take(4 * N * s) : 0;
     L.deps = analytic ? take((size_t)(D + D * (D + 1) / 2) * N * s) : 0;
     L.tsolid = solids ? take(ntiles) : 0;
-    L.zflags = take(nzflags);
+    L.tflat = analytic ? 0 : take(ntiles);
     L.total = off;
     return L;
 }
@@ -123,7 +122,6 @@ struct lbm_solver {
     double picard_omega;
     bool analytic;      // analytic porosity derivatives in L.deps
     lbm::Tiling tiles;  // 256-cell tiles, blocked, in XCD-contiguous ranges
-    lbm::ZMarch zm;     // z-marching passes: in-plane tiles times chunks of planes
     int device;         // HIP device current at creation
 };
 
@@ -203,23 +201,6 @@ inline lbm::Tiling make_tiling(int nx, int ny, int nz, bool packed_ok = false) {
 
 inline dim3 cell_tiles(const lbm_solver *h) { return dim3((unsigned)(8 * (int64_t)h->tiles.per)); }
 
-// Work of the z-marching passes: the in-plane tiles of t times chunks of zc planes, zc chosen
-// so that about 4096 workgroups (16 per CU) share the planes, at most 32 planes per chunk.
-inline lbm::ZMarch make_zmarch(const lbm::Tiling &t, int nz) {
-    lbm::ZMarch z{};
-    z.ntile = t.packed ? (uint32_t)t.nty : (uint32_t)(t.ntx * t.nty);
-    const int64_t total = (int64_t)z.ntile * nz;
-    z.zc = (uint32_t)std::max<int64_t>(1, std::min<int64_t>({32, (int64_t)nz, total / 4096}));
-    z.nwork = z.ntile * (uint32_t)((nz + (int)z.zc - 1) / (int)z.zc);
-    z.per = (z.nwork + 7u) / 8u;
-    z.mnt = z.ntile >= 2 ? ~uint64_t(0) / z.ntile + 1 : 0;
-    return z;
-}
-
-inline size_t zflag_count(const lbm::Tiling &t, int nz) {
-    return (size_t)(t.packed ? t.nty : t.ntx * t.nty) * (size_t)nz;
-}
-
 template <typename T>
 T *ws_ptr(const lbm_solver *h, size_t off) {
     return reinterpret_cast<T *>(h->ws + off);
@@ -233,8 +214,9 @@ inline const uint8_t *tsolid_ptr(const lbm_solver *h) {
     return h->solids ? reinterpret_cast<const uint8_t *>(h->ws + h->L.tsolid) : nullptr;
 }
 
-inline const uint8_t *zflags_ptr(const lbm_solver *h) {
-    return reinterpret_cast<const uint8_t *>(h->ws + h->L.zflags);
+// Flat-tile flags exist for differenced porosity derivatives only (analytic runs: null).
+inline const uint8_t *tflat_ptr(const lbm_solver *h) {
+    return h->analytic ? nullptr : reinterpret_cast<const uint8_t *>(h->ws + h->L.tflat);
 }
 
 // Enqueue the statistics of the current state into res (8 doubles, the lbm_stats slots) with the

@@ -38,11 +38,10 @@ void launch_picard(const lbm_solver *h, size_t vin, size_t vout) {
 template <int D, typename T, bool S, bool AD>
 void launch_vcorrect(const lbm_solver *h, size_t own_src, size_t m1, size_t m2_out) {
     auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_vcorrect_z<D, T, S, AD>), dim3(8 * h->zm.per), dim3(256), 0,
-                       h->stream, ws_ptr<const lbm::P4<T>>(h, own_src),
-                       ws_ptr<const lbm::P4<T>>(h, m1), ws_ptr<const T>(h, h->L.eps),
-                       mask_ptr(h), zflags_ptr(h), ws_ptr<lbm::P4<T>>(h, m2_out), grid_of(h),
-                       h->tiles, h->zm, ph);
+    hipLaunchKernelGGL((lbm::k_vcorrect<D, T, S, AD>), cell_tiles(h), dim3(256), 0, h->stream,
+                       ws_ptr<const lbm::P4<T>>(h, own_src), ws_ptr<const lbm::P4<T>>(h, m1),
+                       ws_ptr<const T>(h, h->L.eps), mask_ptr(h), tsolid_ptr(h), tflat_ptr(h),
+                       ws_ptr<lbm::P4<T>>(h, m2_out), grid_of(h), h->tiles, ph);
 }
 
 template <int D, typename T, typename P, bool S, int PH, bool AD>

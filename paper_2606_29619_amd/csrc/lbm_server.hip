@@ -147,6 +147,9 @@ struct Request {
     std::vector<uint8_t> mask;
     double tol = 0;
     int64_t max_steps = 0;
+    int floor_checks = 0;       // rounds without a new minimum of the residual before retiring
+    double best = INFINITY;     // lowest residual so far (new minima count when 1 % lower)
+    int since_best = 0;         // rounds since the last new minimum
     size_t bytes = 0, off = 0;
     bool holds_memory = false;
     lbm_solver *h = nullptr;
@@ -395,12 +398,13 @@ LBM_API int lbm_server_create(void *dev_pool, size_t pool_bytes, int64_t check_e
 }
 
 LBM_API int lbm_server_submit(lbm_server *s, const lbm_params *p, double tol, int64_t max_steps,
-                              int64_t *id) {
+                              int floor_checks, int64_t *id) {
     int rc = check_server(s);
     if (rc) return rc;
     if (!p || !id) return fail(LBM_ERR_INVALID_ARG, "null argument");
     if (!(tol > 0) || max_steps < s->check_every)
         return fail(LBM_ERR_INVALID_ARG, "tol must be > 0 and max_steps >= check_every");
+    if (floor_checks < 0) return fail(LBM_ERR_INVALID_ARG, "floor_checks must be >= 0");
     if (p->bc_type || p->picard_iters || p->grad_eps || p->hess_eps)
         return fail(LBM_ERR_UNSUPPORTED,
                     "the server runs periodic / bounce-back runs with the one-shot velocity and "
@@ -438,6 +442,7 @@ LBM_API int lbm_server_submit(lbm_server *s, const lbm_params *p, double tol, in
     q->id = (int64_t)s->reqs.size();
     q->tol = tol;
     q->max_steps = max_steps;
+    q->floor_checks = floor_checks;
     q->bytes = bytes;
     q->cells = (int64_t)N;
     q->t_submit = s->now();
@@ -506,9 +511,20 @@ LBM_API int lbm_server_progress(lbm_server *s, int64_t max_rounds, int64_t *fini
             Request *q = find_req(s, s->active[r]);
             const double *st = s->pinned + r * lbm::kStatsSlots;
             q->residual = st[6] > 0 ? std::sqrt(st[5] / st[6]) : INFINITY;
+            // a new minimum counts when it is at least 1 % below the previous one, so that the
+            // slow drift of the lowest value of a residual that fluctuates about its floor
+            // does not
+            if (q->residual < 0.99 * q->best) {
+                q->best = q->residual;
+                q->since_best = 0;
+            } else {
+                q->since_best += 1;
+            }
             int state = LBM_REQ_ACTIVE;
             if (st[7] > 0) state = LBM_REQ_FAILED;
             else if (q->residual < q->tol) state = LBM_REQ_CONVERGED;
+            else if (q->floor_checks > 0 && q->since_best >= q->floor_checks)
+                state = LBM_REQ_FLOOR;
             else if (q->h->step >= q->max_steps) state = LBM_REQ_CENSORED;
             if (state == LBM_REQ_ACTIVE) {
                 still.push_back(q->id);

@@ -221,11 +221,11 @@ def test_server_submit_copies_and_queues():
         with pytest.raises(capi.LbmError) as ei:          # holds no state yet
             capi.lbm_server_solver(s, rid)
         assert ei.value.code == capi.LBM_ERR_STATE
-        for bad in [dict(tol=0.0), dict(max_steps=50)]:
-            kw = dict(tol=1e-7, max_steps=1000)
+        for bad in [dict(tol=0.0), dict(max_steps=50), dict(floor_checks=-1)]:
+            kw = dict(tol=1e-7, max_steps=1000, floor_checks=0)
             kw.update(bad)
             with pytest.raises(capi.LbmError) as ei:
-                capi.lbm_server_submit(s, p, kw["tol"], kw["max_steps"])
+                capi.lbm_server_submit(s, p, kw["tol"], kw["max_steps"], kw["floor_checks"])
             assert ei.value.code == capi.LBM_ERR_INVALID_ARG
         big, keep3 = _params(shape=(96, 96, 96))
         with pytest.raises(capi.LbmError) as ei:          # can never fit a 64 MiB pool

@@ -125,8 +125,12 @@ def test_analytic_derivatives_reduced_precision(storage, lagged):
     print(f"differenced {storage} lagged={lagged}:", errs_fd, flush=True)
     f_bound = 3e-5 if storage == "f32" else 5e-5
     assert errs["f"] < f_bound and errs["rho"] < 5e-5, errs
+    # |v| is only ~1e-5 here, so the rounding of populations ~0.3 (3e-8 in FP32) is about 1 % of
+    # it: measured on MI355X 0.8-2.1 % (FP32) and 6-17 % (FP16 storage) normwise per component
+    v_bound = 0.05 if storage == "f32" else 0.4
     for k in ("v0", "v1", "v2"):
         assert errs[k] < 2 * errs_fd[k] + 1e-4, (k, errs, errs_fd)
+        assert errs[k] < v_bound, (k, errs)
 
 
 def test_analytic_and_differenced_runs_agree_on_quadratic_porosity():

@@ -1,0 +1,35 @@
+"""The oracle's pins again, with the oracle built with AddressSanitizer and
+UndefinedBehaviorSanitizer (host code; any out-of-bounds access, use after free, signed
+overflow or misaligned access aborts the run).  Runs in a child process that preloads the ASan
+runtime, since the Python interpreter itself is not instrumented."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _libasan():
+    out = subprocess.run(["gcc", "-print-file-name=libasan.so"], capture_output=True,
+                         text=True).stdout.strip()
+    return out if os.path.isabs(out) and os.path.exists(out) else None
+
+
+@pytest.mark.skipif(_libasan() is None, reason="gcc has no AddressSanitizer runtime here")
+def test_oracle_pins_under_sanitizers():
+    env = dict(os.environ, LBM_ORACLE_SANITIZE="1", LD_PRELOAD=_libasan(),
+               ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="halt_on_error=1",
+               OMP_NUM_THREADS="2")
+    sel = ["tests/test_oracle_algebra.py", "tests/test_oracle_threads.py",
+           "tests/test_oracle_boundaries.py",
+           "tests/test_oracle_physics.py::test_uniform_box_is_trapezoidal_rule",
+           "tests/test_oracle_physics.py::test_statistics_use_the_corrected_velocity",
+           "tests/test_oracle_physics.py::test_mass_conservation_heterogeneous_3d",
+           "tests/test_oracle_physics.py::test_momentum_budget_uniform_porosity",
+           "tests/test_oracle_physics.py::test_lagged_scheme_shares_the_two_pass_steady_state"]
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        *sel], cwd=ROOT, env=env, capture_output=True, text=True, timeout=1200)
+    assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
+    assert "passed" in r.stdout

@@ -295,13 +295,14 @@ def test_lagged_statistics_match_oracle():
 
 def test_lagged_fp32_tracks_fp64_oracle():
     """FP32 lagged scheme against the FP64 lagged oracle on the random-porosity recipe (32^3,
-    100 steps), with the tolerances of the two-pass FP32 case."""
+    100 steps), with the tolerances of the two-pass FP32 case (measured on MI355X: f 2.3e-6,
+    rho 2.2e-6, v 1.7e-4..3.2e-4)."""
     w = workloads.random_porosity_3d(shape=(32, 32, 32), seed=0, ell=16.0)
     s, o = _run_pair(w, 100, storage=capi.LBM_F32, lagged=True)
     errs = _field_errors(s, o)
     _print("lagged fp32 vs fp64 oracle:", errs)
-    assert errs["f"] < 3e-5 and errs["rho"] < 5e-5
-    assert max(errs[k] for k in ("v0", "v1", "v2")) < 2e-3
+    assert errs["f"] < 5e-6 and errs["rho"] < 5e-6
+    assert max(errs[k] for k in ("v0", "v1", "v2")) < 7e-4
 
 
 # --------------------------------------------------------------------------------------------
@@ -370,13 +371,13 @@ def test_d3q27_fp32_tracks_fp64_oracle():
     population (~0.3) a few times at u = 6e-8, so after n steps f-bar drifts by ~sqrt(n) * 5u
     ~ 3e-6 of its maximum; rho = S/eps sums 27 of them (~1e-5); v is a difference of
     populations divided by rho, ~1e-8 absolute against |v| ~ 1e-5..1e-4 here.  Measured on
-    MI355X: f 6.5e-6, rho 1.4e-5, v 1.6e-4..4.0e-4; the bounds below leave a factor ~3-5."""
+    MI355X: f 2.2e-6, rho 2.3e-6, v 1.4e-4..2.8e-4; the bounds below leave a factor ~2."""
     w = workloads.random_porosity_3d(shape=(32, 32, 32), seed=0, ell=16.0)
     s, o = _run_pair(w, 100, storage=capi.LBM_F32)
     errs = _field_errors(s, o)
     _print("d3q27 fp32 vs fp64 oracle:", errs)
-    assert errs["f"] < 3e-5 and errs["rho"] < 5e-5
-    assert max(errs[k] for k in ("v0", "v1", "v2")) < 2e-3
+    assert errs["f"] < 5e-6 and errs["rho"] < 5e-6
+    assert max(errs[k] for k in ("v0", "v1", "v2")) < 6e-4
 
 
 # --------------------------------------------------------------------------------------------
@@ -392,18 +393,18 @@ _SHIFTED = {"f16": capi.LBM_F16_SHIFTED, "bf16": capi.LBM_BF16_SHIFTED}
 _SHIFTS = {"weights": capi.LBM_SHIFT_WEIGHTS, "porous": capi.LBM_SHIFT_POROUS}
 
 
-# Bounds are about 3x the errors measured on MI355X (v L2 / v Linf / f / mass drift):
-#   f16 porous  2.0e-3 / 1.9e-3 / 1.7e-5 / 8.1e-6     bf16 porous  1.5e-2 / 1.9e-2 / 9.5e-5 / 8.5e-6
-#   f16 weights 4.8e-2 / 3.7e-2 / 6.1e-4 / 7.6e-5     bf16 weights 0.38   / 0.30   / 4.5e-3 / 2.6e-4
+# Bounds are 2-3x the errors measured on MI355X (v L2 / v Linf / f / mass drift):
+#   f16 porous  1.9e-3 / 2.3e-3 / 1.3e-5 / 5.7e-7     bf16 porous  1.5e-2 / 1.6e-2 / 1.1e-4 / 2.9e-7
+#   f16 weights 4.8e-2 / 3.5e-2 / 6.0e-4 / 6.9e-5     bf16 weights 0.38   / 0.29   / 4.7e-3 / 2.3e-4
 # (FP32 storage: v 1.6e-4..4e-4).  Model: a stored deviation d carries a relative rounding
 # error of 2^-11 (FP16) or 2^-8 (BF16).  With the porous shift d is the flow's own deviation
 # from eps rho0 w_i, ~1e-3 of f here, so FP16 costs about as much as FP32 arithmetic; with the
 # weight shift d includes (eps - 1) rho0 w_i, up to 0.7 w_i at eps = 0.3, and the velocity error
 # grows ~25-fold.
-_SHIFT_BOUNDS = {("f16", "porous"): (6e-3, 6e-3, 5e-5, 3e-5),
-                 ("bf16", "porous"): (5e-2, 6e-2, 3e-4, 3e-5),
-                 ("f16", "weights"): (0.15, 0.12, 2e-3, 3e-4),
-                 ("bf16", "weights"): (1.2, 1.0, 1.5e-2, 1e-3)}
+_SHIFT_BOUNDS = {("f16", "porous"): (4e-3, 5e-3, 3e-5, 2e-6),
+                 ("bf16", "porous"): (3e-2, 3.5e-2, 2.5e-4, 1e-6),
+                 ("f16", "weights"): (0.1, 0.08, 1.3e-3, 1.5e-4),
+                 ("bf16", "weights"): (0.8, 0.6, 1e-2, 5e-4)}
 
 
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
@@ -500,13 +501,14 @@ def test_full_width_tiles_fp64(shape, solids, lagged):
     assert max(errs.values()) <= FP64_TOL, errs
 
 
-# Bounds for 9 steps at (12, 72, 256), b = 3e-4 (v up to ~3e-3): about 3x the errors measured on
-# MI355X, printed by the test.  FP32: every population is rounded (u = 6e-8) a few times per step;
+# Bounds for 9 steps at (12, 72, 256), b = 3e-4 (v up to ~3e-3): about 2x the errors measured on
+# MI355X (f / rho / v: FP32 1.1e-6 / 7.5e-7 / 1.1e-5, FP16 4.0e-5 / 3.5e-5 / 7.0e-4, BF16
+# 2.8e-4 / 3.0e-4 / 5.5e-3), printed by the test.  FP32: every population is rounded (u = 6e-8) a few times per step;
 # 16-bit forms: each stored deviation from the porous shift carries a relative error of 2^-11
 # (FP16) or 2^-8 (BF16) of a deviation ~1e-3 of f here.
-_WIDE_BOUNDS = {"f32": dict(f=3e-6, rho=3e-6, v=3e-5),
-                "f16": dict(f=1.2e-4, rho=1e-4, v=2e-3),
-                "bf16": dict(f=1e-3, rho=1e-3, v=2e-2)}
+_WIDE_BOUNDS = {"f32": dict(f=2.5e-6, rho=2e-6, v=2.5e-5),
+                "f16": dict(f=8e-5, rho=8e-5, v=1.5e-3),
+                "bf16": dict(f=6e-4, rho=6e-4, v=1.2e-2)}
 
 
 @pytest.mark.parametrize("fmt", ["f32", "f16", "bf16"])
@@ -579,3 +581,42 @@ def test_headline_box_sampled_cells(fmt, steps):
     # one step of FP32 arithmetic on populations ~0.3: a few ulp (6e-8); FP16 storage: the
     # stored deviation (|f - eps rho0 w_i| ~ 1e-5 w_i here) scaled to ~4096 carries 2^-11
     assert err < (2e-6 if fmt == "f32" else 2e-5), err
+
+
+# --------------------------------------------------------------------------------------------
+# Small periodic boxes whose neighbour stencils wrap onto themselves
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(7, 16, 64), (3, 8, 32), (1, 8, 32), (2, 24, 96),
+                                   (21, 16, 32)])
+def test_small_periodic_boxes_fp64(shape):
+    """One, two and three planes (the z neighbours are the plane itself or the other one),
+    rows of one 32- or 64-cell wave, several tile blocks along z, with every option of the
+    forcing on (RT != 1/3, Phi^eta, nu_eff = nu_ref / eps): bitwise to the oracle after 5
+    steps (swapped AA layout next) and after 8."""
+    w = workloads.random_porosity_3d(shape=shape, seed=17, ell=2.5, nu=0.03, b=2e-4)
+    w.RT = 0.36
+    w.eta_eff = 0.02
+    w.nu_eff_pow = -1
+    s, o = _run_pair(w, 5)
+    errs = _field_errors(s, o)
+    _print(f"small box {shape} t=5:", errs)
+    assert max(errs.values()) <= FP64_TOL, errs
+    s.step(3)
+    o.step(3)
+    errs = _field_errors(s, o)
+    _print(f"small box {shape} t=8:", errs)
+    assert max(errs.values()) <= FP64_TOL, errs
+
+
+def test_analytic_derivatives_on_a_tile_multiple_box():
+    """Analytic porosity derivatives (Sec. 3.5) on a box of whole 32-cell rows and 8-row tile
+    blocks, against the oracle given the same derivatives."""
+    w = workloads.sine_porosity(D=3, shape=(8, 16, 32))
+    s = capi.Solver.from_workload(w, storage=capi.LBM_F64)
+    o = _oracle_for(w, grad_eps=w.grad_eps, hess_eps=w.hess_eps)
+    s.step(6)
+    o.step(6)
+    torch.cuda.synchronize()
+    errs = _field_errors(s, o)
+    _print("analytic box:", errs)
+    assert max(errs.values()) <= FP64_TOL, errs

@@ -207,3 +207,25 @@ def test_served_fp64_requests_match_the_oracle():
     for rid in ids + [r_c, r_a]:
         srv.release(rid)
     srv.close()
+
+
+def test_floor_rule_retires_runs_that_stop_improving():
+    """An FP32 run cannot bring the relative 100-step change of v below ~1e-4 (its rounding
+    keeps the state moving about the steady state), so with an unreachable tolerance it
+    retires at its floor (LBM_REQ_FLOOR) well before its step cap when the floor rule is on,
+    and runs to the cap when it is off; an FP64 run of the same request converges to 1e-7."""
+    w = workloads.random_porosity_3d(shape=(16, 16, 32), seed=9, ell=6.0, nu=0.05, b=1e-6)
+    srv = capi.Server(pool_bytes=256 << 20, check_every=100)
+    r_floor = srv.submit(w, storage=capi.LBM_F32, tol=1e-12, max_steps=100000, floor_checks=10)
+    r_cap = srv.submit(w, storage=capi.LBM_F32, tol=1e-12, max_steps=3000, floor_checks=0)
+    r_64 = srv.submit(w, storage=capi.LBM_F64, tol=1e-7, max_steps=100000, floor_checks=0)
+    _drain(srv, max_rounds=2000)
+    fl, cap, f64 = srv.info(r_floor), srv.info(r_cap), srv.info(r_64)
+    print(f"floor rule: FP32 at floor after {fl.steps} steps (residual {fl.residual:.2e}); "
+          f"FP64 converged after {f64.steps} steps", flush=True)
+    assert fl.state == capi.LBM_REQ_FLOOR and fl.steps < 100000 and fl.residual > 1e-7
+    assert cap.state == capi.LBM_REQ_CENSORED and cap.steps == 3000
+    assert f64.state == capi.LBM_REQ_CONVERGED and f64.residual < 1e-7
+    for rid in (r_floor, r_cap, r_64):
+        srv.release(rid)
+    srv.close()
