@@ -275,6 +275,24 @@ LBM_API int lbm_moments(lbm_solver *h, void *rho_dev, void *v_dev, int dtype, in
 LBM_API int lbm_residual(lbm_solver *h, lbm_stats *out);
 
 /*
+ * Statistics for callers that cannot allocate device memory or synchronise: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The same statistics as
+ * lbm_residual (same kernels, same order of summation, so the values are bitwise those of
+ * lbm_residual on the same state), enqueued on the handle's stream without synchronising:
+ * stats_dev (device memory on the handle's device, caller-owned) receives 8 doubles in the
+ * slot order mass, momentum x, y, z, max|v|, sum |v - v_prev|^2, sum |v_prev|^2, number of
+ * non-finite fluid cells (the residual is sqrt(slot 5 / slot 6)); the current v becomes v_prev
+ * of the next statistics call, as in lbm_residual.  No device memory is allocated: the
+ * per-block partial sums go to a file-scope device array of the library (at most 1024 rows of 8
+ * doubles, 64 KiB per device, kept until the process ends), whose address is looked up once per
+ * device on the first call there.  Every call on a GPU shares that GPU's array, so calls that
+ * overlap on one GPU (other streams, other threads) race; nothing in it needs clearing.
+ * Errors: LBM_ERR_INVALID_ARG (NULL pointer), LBM_ERR_UNSUPPORTED (a device index above 63),
+ * LBM_ERR_HIP; a non-finite state is reported in slot 7, not as an error.
+ */
+LBM_API int lbm_stats_noalloc(lbm_solver *h, double *stats_dev);
+
+/*
  * Copy the populations f-bar_i(x) of the current state in natural layout [Q][N] (the value
  * that streamed into cell x along c_i) into a caller device buffer of dtype.  Solid cells get
  * 0; the incoming populations of outflow nodes are their zero-gradient copies.  With

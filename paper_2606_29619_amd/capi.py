@@ -127,6 +127,7 @@ def load() -> ctypes.CDLL:
     L.lbm_step_timed.argtypes = [vp, ctypes.c_int64, _dp]
     L.lbm_moments.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
     L.lbm_residual.argtypes = [vp, ctypes.POINTER(lbm_stats)]
+    L.lbm_stats_noalloc.argtypes = [vp, vp]
     L.lbm_get_populations.argtypes = [vp, vp, ctypes.c_int]
     L.lbm_set_populations.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int64]
     L.lbm_get_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
@@ -208,6 +209,10 @@ def lbm_residual(h, allow_nonfinite: bool = False) -> lbm_stats:
     ok = (LBM_OK, LBM_ERR_NONFINITE) if allow_nonfinite else (LBM_OK,)
     _check(load().lbm_residual(h, ctypes.byref(s)), "lbm_residual", ok)
     return s
+
+
+def lbm_stats_noalloc(h, stats_dev_ptr: int):
+    _check(load().lbm_stats_noalloc(h, stats_dev_ptr), "lbm_stats_noalloc")
 
 
 def lbm_get_populations(h, dev_ptr: int, dtype: int):

@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <mutex>
 
 #include "lbm_bc.hpp"
 #include "lbm_device.hpp"
@@ -196,6 +197,38 @@ int enqueue_stats(lbm_solver *h, double *part, double *res) {
     hipLaunchKernelGGL(lbm::k_stats_final, dim3(1), dim3(256), 0, h->stream, part,
                        stats_blocks(h), res);
     LAUNCH_CHECK();
+    return LBM_OK;
+}
+
+// ---- statistics without allocation ---------------------------------------------------------
+// Per-block partial sums of lbm_stats_noalloc: at most kStatsBlocks rows of kStatsSlots doubles
+// (64 KiB).  Every GPU the library runs on holds its own copy until the process ends.  In host
+// code the name stands for no device address: kernels get the pointer that hipGetSymbolAddress
+// returns for the device, looked up once per device and kept.
+static __device__ __align__(256) double scratch[lbm::kStatsBlocks * lbm::kStatsSlots];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_device(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(LBM_ERR_UNSUPPORTED, "device %d is beyond the %d devices the statistics "
+                    "scratch serves", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) HIP_TRY(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) HIP_TRY(hipSetDevice(cur));
+        if (e != hipSuccess)
+            return fail(LBM_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
     return LBM_OK;
 }
 
@@ -561,6 +594,20 @@ LBM_API int lbm_residual(lbm_solver *h, lbm_stats *out) {
     out->step = h->step;
     if (out->nonfinite > 0) return fail(LBM_ERR_NONFINITE, "%lld fluid cells are not finite", (long long)out->nonfinite);
     return LBM_OK;
+}
+
+LBM_API int lbm_stats_noalloc(lbm_solver *h, double *stats_dev) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!stats_dev) return fail(LBM_ERR_INVALID_ARG, "stats_dev is NULL");
+    const int nblocks = stats_blocks(h);
+    if (nblocks > lbm::kStatsBlocks)  // a guard: the reduction never uses more blocks
+        return fail(LBM_ERR_UNSUPPORTED, "%d statistics blocks exceed the scratch of %d",
+                    nblocks, lbm::kStatsBlocks);
+    double *part = nullptr;
+    rc = scratch_of_device(h->device, &part);
+    if (rc) return rc;
+    return enqueue_stats(h, part, stats_dev);
 }
 
 LBM_API int lbm_get_populations(lbm_solver *h, void *dev_out, int dtype) {

@@ -343,3 +343,10 @@ def test_analytic_derivative_validation_and_footprint():
         assert ei.value.code == capi.LBM_ERR_UNSUPPORTED
     finally:
         capi.lbm_server_destroy(srv)
+
+
+def test_stats_noalloc_rejects_a_null_handle():
+    """The allocation-free statistics entry point validates its handle before any device work."""
+    with pytest.raises(capi.LbmError) as ei:
+        capi.lbm_stats_noalloc(None, 0)
+    assert ei.value.code == capi.LBM_ERR_INVALID_ARG
