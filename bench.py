@@ -68,11 +68,17 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel, tag, src_hash):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary of the 256^3 box with this
-    storage (tag: "f32", "f16_porous", ...), when it was taken on the current kernel source;
-    otherwise None."""
-    path = os.path.join(ROOT, "profiles", f"pmc_d3q27_{tag}_256.json")
+def traffic_from_profiles(kernel, tag, src_hash, kind="box", n=256):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary of this row (the 256^3 box
+    or the 768x384x384 sphere duct; tag: "f32", "f16_porous", "f32_lagged", ...), when it was
+    taken on the current kernel source; otherwise None."""
+    if kind == "box" and n == 256:
+        name = f"pmc_d3q27_{tag}_256.json"
+    elif kind == "sphere":
+        name = f"pmc_d3q27_sphere_{tag}_768.json"
+    else:
+        return None
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -234,8 +240,7 @@ def measure(w, desc, storage, shift, scheme, steps, warmup, src, kind="box", n=2
     tag = storage if sp_bytes != 2 else f"{storage}_{shift}"
     if lagged:
         tag += "_lagged"
-    traffic = (traffic_from_profiles(dom, tag, src)
-               if kind == "box" and n == 256 else None)
+    traffic = traffic_from_profiles(dom, tag, src, kind, n)
     step_bytes = method_bytes_per_cell(Q, D, sp_bytes, s_bytes, lagged, msk)
     return {
         "value": round(mlups, 1),
