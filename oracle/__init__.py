@@ -90,6 +90,8 @@ def lib():
         L.orc_weights.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         L.orc_product_form.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         L.orc_drag_solve.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_boundary_viscous_term.argtypes = [ctypes.c_void_p, dp, ctypes.c_long,
+                                                ctypes.POINTER(ctypes.c_long), dp]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = ctypes.c_int
         _lib = L
@@ -290,6 +292,17 @@ class Oracle:
         m = np.ascontiguousarray(m, dtype=np.float64).reshape((self.D,) + self.shape)
         out = np.zeros_like(m)
         lib().orc_delta_nu_field(self._h, _dp(m), _dp(out))
+        return out
+
+    def boundary_viscous_term(self, v: np.ndarray, nodes: np.ndarray) -> np.ndarray:
+        """The viscous term of eq. (accel_approx_boundary) at the given face nodes (flat cell
+        indices), from the velocity field v [D, ...] (overwrites the v^(1) records)."""
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape((self.D,) + self.shape)
+        nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+        out = np.zeros(len(nodes))
+        lib().orc_boundary_viscous_term(self._h, _dp(v), len(nodes),
+                                        nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                                        _dp(out))
         return out
 
     def porosity_derivatives(self):

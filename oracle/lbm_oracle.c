@@ -57,15 +57,20 @@ typedef struct {
     const double *rho_init; /* [N] or NULL */
     const double *v_init;   /* [D][N] superficial velocity or NULL (zero) */
     /* Wet-node boundaries (Sec. 3.4); bc_type NULL = none.  A boundary node is a fluid cell
-     * whose outward neighbour (along its normal) is solid and whose inward neighbour is a bulk
-     * fluid cell. */
+     * whose outward neighbour along each of its normals is solid.  A node with one normal (a
+     * face) has a bulk fluid cell as inward neighbour; a velocity node may have two or three
+     * (an edge or corner, Sec. 3.4.1), and then the two cells x_b + d and x_b + 2d along the
+     * inward diagonal d = -(sum of its normals) are bulk fluid cells. */
     const uint8_t *bc_type;   /* [N] 0 bulk, 1 velocity node, 2 pressure node, 3 outflow node */
-    const uint8_t *bc_normal; /* [N] outward normal: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z */
+    const uint8_t *bc_normal; /* [N] one outward normal: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z; or
+                                 several: 64 + sx + 4 sy + 16 sz with s = 0 none, 1 minus,
+                                 2 plus along that axis */
     const double *bc_vel;     /* [D][N] prescribed superficial velocity (velocity nodes), or NULL */
     const double *bc_rho;     /* [N] prescribed intrinsic density (pressure nodes), or NULL */
     int bc_scheme;            /* 0 equilibrium (eq_bc_f_bar), 1 NEEM (NEEM_bc_f_bar), 2 TMS */
-    int bc_density;           /* velocity nodes: 0 mass continuity (bc_density_impermWall),
-                                 1 bounce-back (bc_density_BounceBack) */
+    int bc_density;           /* velocity nodes: 0 mass continuity (bc_density_impermWall) on
+                                 faces and extrapolation from the bulk on edges and corners,
+                                 1 bounce-back (bc_density_BounceBack) everywhere */
     /* Second-order velocity evaluation (App. F): Picard iterations after the one-shot
      * correction (0 = one-shot only) and the under-relaxation factor omega in (0, 1]. */
     int picard_iters;
@@ -369,6 +374,8 @@ static void *xcalloc(long n, long sz)
 }
 
 static void init_populations(orc_solver *S);
+static int bc_normal_vec(const orc_solver *S, long b, int *nv);
+static long bc_inner(const orc_solver *S, long b, const int *nv);
 
 void orc_destroy(orc_solver *S)
 {
@@ -481,6 +488,22 @@ orc_solver *orc_create(const orc_params *p, char *err, int errlen)
         k = 0;
         for (n = 0; n < N; ++n)
             if (p->bc_type[n]) S->bnodes[k++] = n;
+        /* edge and corner nodes: velocity nodes whose two inward-diagonal cells are bulk fluid
+         * (their density may be extrapolated from them) */
+        for (k = 0; k < S->nb; ++k) {
+            int nv[3];
+            long b = S->bnodes[k], f1, f2;
+            if (bc_normal_vec(S, b, nv) < 2) continue;
+            f1 = bc_inner(S, b, nv);
+            f2 = bc_inner(S, f1, nv);
+            if (p->bc_type[b] != 1 || S->solid[f1] || S->solid[f2] || p->bc_type[f1] ||
+                p->bc_type[f2]) {
+                snprintf(err, (size_t)errlen, "edge or corner node %ld: velocity nodes only, with "
+                         "bulk fluid along the inward diagonal", b);
+                orc_destroy(S);
+                return NULL;
+            }
+        }
     }
     porosity_derivatives(S);
     S->p.grad_eps = NULL;   /* the caller's arrays are read only here */
@@ -569,11 +592,22 @@ static void correct_velocity(orc_solver *S)
 /* post-advection populations split into P- (c_i . n < 0: incoming from outside, unknown),     */
 /* P0 (c_i . n = 0) and P+ (c_i . n > 0), eq. (bc_rho_components_def).                         */
 /* ------------------------------------------------------------------------------------------ */
-static void bc_normal_vec(const orc_solver *S, long b, int *nv)
+/* Outward normal(s) of boundary node b as a vector with one entry per axis in {-1, 0, 1};
+ * returns how many axes carry a normal (1 on a face, 2 on an edge, 3 on a corner). */
+static int bc_normal_vec(const orc_solver *S, long b, int *nv)
 {
-    int code = S->p.bc_normal[b];
+    int code = S->p.bc_normal[b], a, k = 0;
     nv[0] = nv[1] = nv[2] = 0;
+    if (code >= 64) {
+        for (a = 0; a < 3; ++a) {
+            int sa = (code - 64) >> (2 * a) & 3;
+            nv[a] = sa == 1 ? -1 : (sa == 2 ? 1 : 0);
+            if (nv[a] != 0) k = k + 1;
+        }
+        return k;
+    }
     nv[code / 2] = (code % 2) ? 1 : -1;
+    return 1;
 }
 
 static int c_dot(const orc_solver *S, int i, const int *nv)
@@ -581,7 +615,18 @@ static int c_dot(const orc_solver *S, int i, const int *nv)
     return S->c[i][0] * nv[0] + S->c[i][1] * nv[1] + S->c[i][2] * nv[2];
 }
 
-/* The bulk node next to boundary node b along its inward normal. */
+/* Is population i one of the unknown incoming ones (P-)?  It arrives from outside through one
+ * of the node's faces: c_i points inwards along some normal axis. */
+static int in_pminus(const orc_solver *S, int i, const int *nv)
+{
+    int a;
+    for (a = 0; a < 3; ++a)
+        if (nv[a] != 0 && S->c[i][a] == -nv[a]) return 1;
+    return 0;
+}
+
+/* The bulk node next to boundary node b along its inward normal (the inward diagonal on edges
+ * and corners). */
 static long bc_inner(const orc_solver *S, long b, const int *nv)
 {
     int m[3] = {-nv[0], -nv[1], -nv[2]};
@@ -600,67 +645,118 @@ static void apply_outflow(orc_solver *S)
         bc_normal_vec(S, b, nv);
         f = bc_inner(S, b, nv);
         for (i = 0; i < S->Q; ++i)
-            if (c_dot(S, i, nv) < 0) S->F[(long)i * N + b] = S->F[(long)i * N + f];
+            if (in_pminus(S, i, nv)) S->F[(long)i * N + b] = S->F[(long)i * N + f];
     }
 }
 
-/* Density and velocity of the velocity and pressure nodes, written over the bulk moments.
- * Velocity node: v_b prescribed; rho_b from mass continuity, eq. (bc_density_impermWall),
- *   rho_b = (S0 + 2 S+) / (eps_b + v_b,perp - a_b,perp / 2), S0 and S+ the sums of the known
- *   populations in P0 and P+, with a_b,perp = eps_b b_perp - mu_D v_perp - mu_F |v_b| v_perp
- *   + RT (d eps / dn) (eq. accel_approx_boundary without its viscous term, which vanishes where
- *   the porosity is flat at the boundary); or from bounce-back, eq. (bc_density_BounceBack),
- *   which with halfway bounce-back in the streaming is the sum of all post-advection
- *   populations over eps_b.
- * Pressure node: rho_b prescribed, tangential velocity zero, and the same continuity relation
- *   solved for v_perp: v_perp (1 + mu_D / 2) + (mu_F / 2) |v_perp| v_perp = R with
- *   R = (S0 + 2 S+) / rho_b - eps_b + (eps_b b_perp + RT d eps / dn) / 2, in closed form as in
- *   eq. (v_(1)). */
+/* Viscous term of eq. (accel_approx_boundary) at face node b with outward normal nv: the
+ * normal component of Delta_nu(rho v / eps) / rho with the density taken outside the
+ * divergence of eq. (porosity_correction),
+ *   div W,  W(x) = nu_eff(x) [ (v(x) / eps(x)) (n . grad eps)(x) + grad eps(x) (n . v(x)) / eps(x) ],
+ * n fixed to the node's normal, v the velocities of the records at this point of the step
+ * (v^(1) on bulk cells, the boundary velocity on boundary nodes), grad eps as everywhere else
+ * (R6), and each d/dx_beta by the derivative rule of moment fields (one-sided next to solids).
+ * The W_beta values of the stencil go through the scratch field g. */
+static double bc_flux(const orc_solver *S, long c, const int *nv, int beta)
+{
+    int D = S->D, a;
+    long N = S->N;
+    double e = S->eps[c], gn = 0.0, vn = 0.0;
+    for (a = 0; a < D; ++a) {
+        gn = gn + (double)nv[a] * S->ge[a * N + c];
+        vn = vn + (double)nv[a] * S->v1[a * N + c];
+    }
+    return S->nu[c] * ((S->v1[beta * N + c] / e) * gn + S->ge[beta * N + c] * (vn / e));
+}
+
+static double bc_viscous_term(orc_solver *S, long b, const int *nv)
+{
+    int beta, k;
+    double div = 0.0;
+    for (beta = 0; beta < S->D; ++beta) {
+        for (k = -2; k <= 2; ++k) {
+            long c = shift(S, b, beta, k);
+            if (k != 0 && !S->solid[c]) S->g[c] = bc_flux(S, c, nv, beta);
+        }
+        div = div + deriv_own(S, S->g, b, beta, bc_flux(S, b, nv, beta));
+    }
+    return div;
+}
+
+/* Density and velocity of the velocity and pressure nodes, written over the bulk moments, in
+ * two stages.
+ * Stage 1, every node:
+ *   velocity node, v_b prescribed, density rho_b:
+ *     bounce-back rule: eq. (bc_density_BounceBack), which with halfway bounce-back in the
+ *       streaming is the sum of all post-advection populations over eps_b;
+ *     continuity rule, face node (one normal): mass continuity, eq. (bc_density_impermWall),
+ *       rho_b = (S0 + 2 S+) / (eps_b + v_b,perp - a_b,perp / 2), S0 and S+ the sums of the known
+ *       populations in P0 and P+, a_b,perp from eq. (accel_approx_boundary) without its viscous
+ *       term in this stage: eps_b b_perp - mu_D v_perp - mu_F |v_b| v_perp + RT (d eps / dn);
+ *     continuity rule, edge or corner node: the relation does not apply there (Sec. 3.4.1), and
+ *       the density is extrapolated from the bulk along the inward diagonal d:
+ *       rho_b = 2 rho(x_b + d) - rho(x_b + 2 d);
+ *   pressure node (one normal): rho_b prescribed, tangential velocity zero, and the same
+ *     continuity relation solved for v_perp: v_perp (1 + mu_D / 2) + (mu_F / 2) |v_perp| v_perp = R
+ *     with R = (S0 + 2 S+) / rho_b - eps_b + (eps_b b_perp + RT d eps / dn) / 2, in closed form as
+ *     in eq. (v_(1)).
+ * Stage 2, face velocity nodes under the continuity rule, with the viscous correction on: the
+ *   density again, now with the viscous term of eq. (accel_approx_boundary) in a_b,perp, from
+ *   the velocities stage 1 left in the records. */
 static void boundary_records(orc_solver *S)
 {
-    int D = S->D, a, i, nv[3];
+    int D = S->D, a, i, nv[3], stage;
     long k, N = S->N;
-    for (k = 0; k < S->nb; ++k) {
-        long b = S->bnodes[k];
-        int type = S->p.bc_type[b];
-        double e = S->eps[b], s0 = 0.0, sp = 0.0, gperp = 0.0, bperp = 0.0, vb[3] = {0.0, 0.0, 0.0};
-        if (type != 1 && type != 2) continue;
-        bc_normal_vec(S, b, nv);
-        for (i = 0; i < S->Q; ++i) {
-            int cn = c_dot(S, i, nv);
-            double f = S->F[(long)i * N + b];
-            if (cn == 0) s0 = s0 + f;
-            else if (cn > 0) sp = sp + f;
-        }
-        for (a = 0; a < D; ++a) {
-            gperp = gperp + (double)nv[a] * S->ge[a * N + b];
-            bperp = bperp + (double)nv[a] * S->p.b[a];
-        }
-        if (type == 1) {
-            double vperp = 0.0, vm = 0.0, aperp, rho;
-            for (a = 0; a < D; ++a) vb[a] = S->p.bc_vel ? S->p.bc_vel[a * N + b] : 0.0;
-            for (a = 0; a < D; ++a) vperp = vperp + (double)nv[a] * vb[a];
-            for (a = 0; a < D; ++a) vm = vm + vb[a] * vb[a];
-            vm = sqrt(vm);
-            if (S->p.bc_density == 1) {
-                double sum = 0.0;
-                for (i = 0; i < S->Q; ++i) sum = sum + S->F[(long)i * N + b];
-                rho = sum / e;
-            } else {
-                aperp = ((e * bperp - S->muD[b] * vperp) - (S->muF[b] * vm) * vperp) +
-                        S->p.RT * gperp;
-                rho = (s0 + 2.0 * sp) / ((e + vperp) - 0.5 * aperp);
+    for (stage = 1; stage <= 2; ++stage) {
+        if (stage == 2 && !(S->p.visc_corr && S->p.bc_density == 0)) break;
+        for (k = 0; k < S->nb; ++k) {
+            long b = S->bnodes[k];
+            int type = S->p.bc_type[b], nn;
+            double e = S->eps[b], s0 = 0.0, sp = 0.0, gperp = 0.0, bperp = 0.0;
+            double vb[3] = {0.0, 0.0, 0.0};
+            if (type != 1 && type != 2) continue;
+            nn = bc_normal_vec(S, b, nv);
+            if (stage == 2 && (type != 1 || nn != 1)) continue;
+            for (i = 0; i < S->Q; ++i) {
+                int cn = c_dot(S, i, nv);
+                double f = S->F[(long)i * N + b];
+                if (cn == 0) s0 = s0 + f;
+                else if (cn > 0) sp = sp + f;
             }
-            S->rho[b] = rho;
-        } else {
-            double rho = S->p.bc_rho[b];
-            double R = ((s0 + 2.0 * sp) / rho - e) + 0.5 * (e * bperp + S->p.RT * gperp);
-            double c1 = 1.0 + 0.5 * S->muD[b], c2 = 0.5 * S->muF[b];
-            double vperp = (2.0 * R) / (c1 + sqrt(c1 * c1 + (4.0 * c2) * fabs(R)));
-            for (a = 0; a < D; ++a) vb[a] = (double)nv[a] * vperp;
-            S->rho[b] = rho;
+            for (a = 0; a < D; ++a) {
+                gperp = gperp + (double)nv[a] * S->ge[a * N + b];
+                bperp = bperp + (double)nv[a] * S->p.b[a];
+            }
+            if (type == 1) {
+                double vperp = 0.0, vm = 0.0, aperp, rho;
+                for (a = 0; a < D; ++a) vb[a] = S->p.bc_vel ? S->p.bc_vel[a * N + b] : 0.0;
+                for (a = 0; a < D; ++a) vperp = vperp + (double)nv[a] * vb[a];
+                for (a = 0; a < D; ++a) vm = vm + vb[a] * vb[a];
+                vm = sqrt(vm);
+                if (S->p.bc_density == 1) {
+                    double sum = 0.0;
+                    for (i = 0; i < S->Q; ++i) sum = sum + S->F[(long)i * N + b];
+                    rho = sum / e;
+                } else if (nn > 1) {
+                    long f1 = bc_inner(S, b, nv), f2 = bc_inner(S, f1, nv);
+                    rho = 2.0 * S->rho[f1] - S->rho[f2];
+                } else {
+                    aperp = ((e * bperp - S->muD[b] * vperp) - (S->muF[b] * vm) * vperp) +
+                            S->p.RT * gperp;
+                    if (stage == 2) aperp = aperp + bc_viscous_term(S, b, nv);
+                    rho = (s0 + 2.0 * sp) / ((e + vperp) - 0.5 * aperp);
+                }
+                S->rho[b] = rho;
+            } else {
+                double rho = S->p.bc_rho[b];
+                double R = ((s0 + 2.0 * sp) / rho - e) + 0.5 * (e * bperp + S->p.RT * gperp);
+                double c1 = 1.0 + 0.5 * S->muD[b], c2 = 0.5 * S->muF[b];
+                double vperp = (2.0 * R) / (c1 + sqrt(c1 * c1 + (4.0 * c2) * fabs(R)));
+                for (a = 0; a < D; ++a) vb[a] = (double)nv[a] * vperp;
+                S->rho[b] = rho;
+            }
+            for (a = 0; a < D; ++a) S->v1[a * N + b] = vb[a];
         }
-        for (a = 0; a < D; ++a) S->v1[a * N + b] = vb[a];
     }
 }
 
@@ -865,7 +961,7 @@ static void reconstruct_boundaries(orc_solver *S, const double *acc)
             double floc[ORC_MAXQ];
             for (i = 0; i < Q; ++i) {
                 double d;
-                if (c_dot(S, i, nv) < 0) continue;
+                if (in_pminus(S, i, nv)) continue;
                 d = (S->F[(long)i * N + b] - 1.5 * ftgt[i]) + 0.5 * fst[i];
                 s0 = s0 + d;
                 for (a = 0; a < D; ++a) s1[a] = s1[a] + (double)S->c[i][a] * d;
@@ -875,7 +971,7 @@ static void reconstruct_boundaries(orc_solver *S, const double *acc)
             equilibrium_at(S, e, rloc, vloc, floc);
             for (i = 0; i < Q; ++i) {
                 double neq = (ftgt[i] - floc[i]) / omb;
-                if (c_dot(S, i, nv) < 0) S->F[(long)i * N + b] = neq + (1.5 * ftgt[i] - 0.5 * fst[i]);
+                if (in_pminus(S, i, nv)) S->F[(long)i * N + b] = neq + (1.5 * ftgt[i] - 0.5 * fst[i]);
                 else S->F[(long)i * N + b] = neq + S->F[(long)i * N + b];
             }
         }
@@ -1060,6 +1156,22 @@ void orc_delta_nu_field(orc_solver *S, const double *m_in, double *out)
         double dn[3] = {0.0, 0.0, 0.0};
         if (!S->solid[n]) delta_nu_field(S, m_in, n, dn);
         for (a = 0; a < D; ++a) out[a * N + n] = dn[a];
+    }
+}
+
+/* The viscous term of eq. (accel_approx_boundary) at each face node of `nodes` (boundary
+ * nodes with one normal), evaluated as in the boundary records from the velocity field v_in
+ * [D][N] in place of the records' velocities.  Test diagnostic: the solver's v^(1) records are
+ * overwritten (the next step recomputes them). */
+void orc_boundary_viscous_term(orc_solver *S, const double *v_in, long nnodes, const long *nodes,
+                               double *out)
+{
+    long k;
+    int nv[3];
+    memcpy(S->v1, v_in, sizeof(double) * (size_t)(S->D * S->N));
+    for (k = 0; k < nnodes; ++k) {
+        if (!S->p.bc_type || bc_normal_vec(S, nodes[k], nv) != 1) { out[k] = NAN; continue; }
+        out[k] = bc_viscous_term(S, nodes[k], nv);
     }
 }
 

@@ -442,6 +442,89 @@ def couette_gravity_2d(H=32, eps=0.5, Da=1e-2, nu=0.1, Gamma=1.0, V0=0.01, nx=4,
                     meta={"H": H, "g": g, "V0": V0, "Da": Da})
 
 
+def normal_code(sx: int = 0, sy: int = 0, sz: int = 0) -> int:
+    """bc_normal value of a node whose outward normals point along the axes with s != 0 (s in
+    {-1, 0, 1}): the single-normal codes 0..5 (-x, +x, -y, +y, -z, +z) for one axis, else
+    64 + ax + 4 ay + 16 az with a = 1 for minus, 2 for plus, 0 for none."""
+    s = (sx, sy, sz)
+    if sum(1 for v in s if v) == 1:
+        a = next(i for i, v in enumerate(s) if v)
+        return 2 * a + (1 if s[a] > 0 else 0)
+    return 64 + sum((1 if v < 0 else 2 if v > 0 else 0) << (2 * i) for i, v in enumerate(s))
+
+
+def wet_box(D=2, n=(32, 8, 1), faces=None, V=0.02, rho_faces=None, nu=1.0 / 6.0, b=(0, 0, 0),
+            eps=None, kappa=None, forch=None, nu_eff_pow=0, scheme=1, rho_rule=0,
+            v_init=None, rho_init=None) -> Workload:
+    """A box of wet-node boundaries (Sec. 3.4): n = (Lx, Ly, Lz) node spacings between the
+    boundary planes of each non-periodic axis (nodes at 1 .. L + 1, solid layers at 0 and
+    L + 2), or the period of a periodic one.  faces maps "x-", "x+", "y-", "y+", "z-", "z+" to
+    "wall" (velocity node, v = 0), "inlet" (velocity node with the profile of the inlet, x- or
+    x+ only: V times the product of the parabolas across the other non-periodic axes, zero on
+    their walls), "pressure" (pressure node, density rho_faces[face]) or "periodic" (both faces
+    of that axis).  Nodes on two or three faces (edges, corners) are velocity nodes with v = 0."""
+    faces = dict(faces or {})
+    rho_faces = dict(rho_faces or {})
+    axes = "xyz"[:D]
+    periodic = [faces.get(f"{a}-") == "periodic" for a in axes]
+    ext = [n[i] if periodic[i] else n[i] + 3 for i in range(D)]
+    nx, ny = ext[0], ext[1]
+    nz = ext[2] if D == 3 else 1
+    shape = (nz, ny, nx)
+    mask = np.zeros(shape, np.uint8)
+    bct = np.zeros(shape, np.uint8)
+    bcn = np.zeros(shape, np.uint8)
+    vel = np.zeros((D,) + shape)
+    brho = np.ones(shape)
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    coords = [xx, yy, zz]
+    sides = []
+    for i in range(D):
+        c = coords[i]
+        if periodic[i]:
+            sides.append(np.zeros(shape, int))
+            continue
+        mask[(c == 0) | (c == ext[i] - 1)] = 1
+        sides.append(np.where(c == 1, -1, np.where(c == ext[i] - 2, 1, 0)))
+    fluid = mask == 0
+    # inlet profile: parabolas across the non-periodic axes other than x, zero on their walls
+    prof = np.full(shape, float(V))
+    for i in range(1, D):
+        if not periodic[i]:
+            t = (coords[i] - 1) / float(n[i])
+            prof = prof * 4.0 * t * (1.0 - t)
+    nsides = sum(np.abs(sd) for sd in sides)
+    for idx in zip(*np.nonzero(fluid & (nsides > 0))):
+        sv = [int(sd[idx]) for sd in sides] + [0] * (3 - D)
+        k = sum(1 for v in sv if v)
+        bcn[idx] = normal_code(*sv)
+        if k > 1:
+            bct[idx] = 1
+            continue
+        a = next(i for i, v in enumerate(sv) if v)
+        face = f"{'xyz'[a]}{'-' if sv[a] < 0 else '+'}"
+        kind = faces.get(face, "wall")
+        if kind == "wall":
+            bct[idx] = 1
+        elif kind == "inlet":
+            bct[idx] = 1
+            vel[(0,) + idx] = prof[idx]
+        elif kind == "pressure":
+            bct[idx] = 2
+            brho[idx] = rho_faces.get(face, 1.0)
+        else:
+            raise ValueError(f"face {face}: {kind}")
+    e = np.ones(shape) if eps is None else np.asarray(eps, float)
+    k_ = np.full(shape, np.inf) if kappa is None else np.asarray(kappa, float)
+    c_ = np.zeros(shape) if forch is None else np.asarray(forch, float)
+    return Workload(name=f"wet-node box D{D} {n[:D]}", lattice=9 if D == 2 else 27, eps=e,
+                    kappa=k_, forch=c_, mask=mask, nu_f=nu, nu_eff_ref=nu, nu_eff_pow=nu_eff_pow,
+                    b=tuple(float(x) for x in b), rho_init=rho_init, v_init=v_init,
+                    bc_type=bct, bc_normal=bcn, bc_velocity=vel, bc_density=brho,
+                    bc_scheme=scheme, bc_rho_rule=rho_rule,
+                    meta={"n": n[:D], "V": V, "profile": prof})
+
+
 def pressure_channel(D=2, L=64, H=16, W=8, drho=1e-3, outflow=False, body=0.0, eps=None,
                      kappa=None, forch=None, nu=0.1):
     """Channel along x between solid walls (halfway bounce-back): pressure nodes at x = 1

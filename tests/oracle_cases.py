@@ -161,3 +161,14 @@ def wall_profile(o):
     """(rho, v_x) along the channel nodes y = 0..H."""
     rho, v, _ = o.moments()
     return rho[0, 1:-1, 0], v[0, 0, 1:-1, 0]
+
+
+def from_workload(w, **extra):
+    """An oracle for a workload of paper_2606_29619_amd.workloads (every field it carries)."""
+    cfg = oracle.OracleConfig(D=w.D, eps=w.eps, kappa=w.kappa, cf=w.forch, mask=w.mask,
+                              RT=w.RT, nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref,
+                              nu_eff_pow=w.nu_eff_pow, eta_eff=w.eta_eff, b=w.b, rho0=w.rho0,
+                              rho_init=w.rho_init, v_init=w.v_init, bc_type=w.bc_type,
+                              bc_normal=w.bc_normal, bc_vel=w.bc_velocity, bc_rho=w.bc_density,
+                              bc_scheme=w.bc_scheme, bc_density=w.bc_rho_rule, **extra)
+    return oracle.Oracle(cfg)
