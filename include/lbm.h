@@ -94,19 +94,32 @@ extern "C" {
 #define LBM_SCHEME_LAGGED 1
 
 /*
- * Wet-node boundaries (Sec. 3.4), two-pass scheme.  A boundary node is a fluid cell with an
- * outward normal along one axis; its outward neighbour must be solid (mask = 1) and its inward
- * neighbour a bulk fluid cell.  Node types (lbm_params.bc_type):
- *   LBM_NODE_VELOCITY: superficial velocity v_b prescribed; density from mass continuity,
- *     eq. (bc_density_impermWall) with a_b,perp = eps_b b_perp - mu_D v_perp - mu_F |v_b| v_perp
- *     + RT d(eps)/dn (eq. accel_approx_boundary without its viscous term), or from bounce-back,
- *     eq. (bc_density_BounceBack); all populations rebuilt by lbm_params.bc_scheme;
- *   LBM_NODE_PRESSURE: intrinsic density rho_b prescribed, tangential velocity zero, normal
- *     velocity from the same continuity relation; populations rebuilt by bc_scheme;
- *   LBM_NODE_OUTFLOW: zero-gradient outflow, eq. (f_bar_outflow_BC).
- * Schemes: LBM_BC_EQUILIBRIUM (eq_bc_f_bar), LBM_BC_NEEM (NEEM_bc_f_bar, zeta_beta_NEEM),
- * LBM_BC_TMS (Sec. 3.4.4, f_i_neq_TMS).  Links of bulk cells into solid cells keep halfway
- * bounce-back.
+ * Wet-node boundaries (Sec. 3.4), two-pass scheme.  A boundary node is a fluid cell whose
+ * outward neighbour along each of its outward normals is solid (mask = 1).
+ *   Face nodes (one normal): the inward neighbour must be a bulk fluid cell.
+ *   Edge and corner nodes (two or three normals, Sec. 3.4.1): velocity nodes only; the two
+ *     cells x_b + d and x_b + 2d along the inward diagonal d = -(sum of the normals) must be
+ *     bulk fluid cells.
+ * Node types (lbm_params.bc_type):
+ *   LBM_NODE_VELOCITY: superficial velocity v_b prescribed.  Density under
+ *     LBM_BC_RHO_CONTINUITY: on faces from mass continuity, eq. (bc_density_impermWall), with
+ *     a_b,perp of eq. (accel_approx_boundary), viscous term included (evaluated from the
+ *     drag-solved velocities v^(1) of the bulk cells and the boundary velocities of the nodes at
+ *     that point of the step); on edges and corners, where that relation does not apply,
+ *     extrapolated from the bulk, rho_b = 2 rho(x_b + d) - rho(x_b + 2d).  Under
+ *     LBM_BC_RHO_BOUNCE_BACK: eq. (bc_density_BounceBack) everywhere (meant for solid walls;
+ *     an inflow boundary needs the continuity rule).  All populations rebuilt by
+ *     lbm_params.bc_scheme;
+ *   LBM_NODE_PRESSURE (faces only): intrinsic density rho_b prescribed, tangential velocity zero,
+ *     normal velocity from the same continuity relation (a_b,perp without the viscous term);
+ *     populations rebuilt by bc_scheme;
+ *   LBM_NODE_OUTFLOW (faces only): zero-gradient outflow, eq. (f_bar_outflow_BC).
+ * Schemes: LBM_BC_EQUILIBRIUM (eq_bc_f_bar), LBM_BC_NEEM (NEEM_bc_f_bar, zeta_beta_NEEM; on edges
+ * and corners the inner node is x_b + d), LBM_BC_TMS (Sec. 3.4.4, f_i_neq_TMS; the unknown set
+ * P- holds every population that enters through one of the node's faces).  Links of bulk cells
+ * into solid cells keep halfway bounce-back.
+ * bc_normal: LBM_NORMAL_XM .. LBM_NORMAL_ZP for one normal, LBM_NORMAL_AXES(sx, sy, sz) with
+ * s in {-1, 0, 1} per axis for any number (sz = 0 in 2D).
  */
 #define LBM_NODE_BULK 0
 #define LBM_NODE_VELOCITY 1
@@ -118,6 +131,9 @@ extern "C" {
 #define LBM_NORMAL_YP 3
 #define LBM_NORMAL_ZM 4
 #define LBM_NORMAL_ZP 5
+#define LBM_NORMAL_SIGN_(s) ((s) < 0 ? 1 : ((s) > 0 ? 2 : 0))
+#define LBM_NORMAL_AXES(sx, sy, sz) \
+    (64 + LBM_NORMAL_SIGN_(sx) + 4 * LBM_NORMAL_SIGN_(sy) + 16 * LBM_NORMAL_SIGN_(sz))
 #define LBM_BC_EQUILIBRIUM 0
 #define LBM_BC_NEEM 1
 #define LBM_BC_TMS 2
@@ -171,7 +187,7 @@ typedef struct lbm_params {
     const double *rho_init; /* [N] initial intrinsic density > 0, or NULL (uniform rho0) */
     const double *v_init;   /* [D][N] initial superficial velocity, or NULL (zero) */
     const uint8_t *bc_type;     /* [N] LBM_NODE_*, or NULL (no wet-node boundaries) */
-    const uint8_t *bc_normal;   /* [N] LBM_NORMAL_* of each boundary node */
+    const uint8_t *bc_normal;   /* [N] LBM_NORMAL_* or LBM_NORMAL_AXES() of each node */
     const double *bc_velocity;  /* [D][N] v_b of velocity nodes, or NULL (zero) */
     const double *bc_density;   /* [N] rho_b of pressure nodes, or NULL (rho0) */
     int bc_scheme;              /* LBM_BC_EQUILIBRIUM, LBM_BC_NEEM or LBM_BC_TMS */

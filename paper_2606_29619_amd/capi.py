@@ -34,6 +34,12 @@ LBM_SHIFT_WEIGHTS = 0
 LBM_SHIFT_POROUS = 1
 LBM_NODE_BULK, LBM_NODE_VELOCITY, LBM_NODE_PRESSURE, LBM_NODE_OUTFLOW = 0, 1, 2, 3
 LBM_NORMAL_XM, LBM_NORMAL_XP, LBM_NORMAL_YM, LBM_NORMAL_YP, LBM_NORMAL_ZM, LBM_NORMAL_ZP = range(6)
+
+
+def LBM_NORMAL_AXES(sx: int, sy: int, sz: int = 0) -> int:
+    """bc_normal code of a node with outward normals along every axis whose s is -1 or 1."""
+    sign = lambda s: 1 if s < 0 else (2 if s > 0 else 0)  # noqa: E731
+    return 64 + sign(sx) + 4 * sign(sy) + 16 * sign(sz)
 LBM_BC_EQUILIBRIUM, LBM_BC_NEEM, LBM_BC_TMS = 0, 1, 2
 LBM_BC_RHO_CONTINUITY, LBM_BC_RHO_BOUNCE_BACK = 0, 1
 LBM_SCHEME_TWO_PASS = 0

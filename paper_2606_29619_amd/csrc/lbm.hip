@@ -38,6 +38,14 @@ size_t velocity_stage(lbm_solver *h, size_t m1, size_t m2) {
     return a;
 }
 
+// Boundary records over the bulk moments in m1: every node, then the face velocity nodes
+// again with the viscous term of their wall-normal acceleration.
+void boundary_records(lbm_solver *h, size_t m1) {
+    if (!h->bc_vp) return;
+    dispatch(h, BcRecordsPass{h, m1, 0});
+    if (h->bc_visc) dispatch(h, BcRecordsPass{h, m1, 1});
+}
+
 // Moments of the current state into internal packed records; returns the offset of the
 // (rho, v) records.  Under the lagged scheme with a valid history the correction takes its
 // neighbour values from the previous step's records, which stay untouched.
@@ -51,7 +59,7 @@ size_t current_moments(lbm_solver *h) {
     const int c = h->cur;
     if (h->bc_outflow) dispatch(h, BcOutflowPass{h});
     dispatch(h, MomentsPass{h, h->L.m1[c]});
-    if (h->bc_vp) dispatch(h, BcRecordsPass{h, h->L.m1[c]});
+    boundary_records(h, h->L.m1[c]);
     dispatch(h, VcorrectPass{h, h->L.m1[c], h->L.m1[c], h->L.m2[c]});
     return velocity_stage(h, h->L.m1[c], h->L.m2[c]);
 }
@@ -72,7 +80,7 @@ hipError_t one_step(lbm_solver *h, hipEvent_t *ev) {
         // the bulk passes (they are timed with the pass they follow)
         if (h->bc_outflow) dispatch(h, BcOutflowPass{h});
         dispatch(h, MomentsPass{h, h->L.m1[c]});
-        if (h->bc_vp) dispatch(h, BcRecordsPass{h, h->L.m1[c]});
+        boundary_records(h, h->L.m1[c]);
         if (ev) e = hipEventRecord(ev[0], h->stream);
         dispatch(h, VcorrectPass{h, h->L.m1[c], h->L.m1[c], h->L.m2[c]});
         const size_t mv = velocity_stage(h, h->L.m1[c], h->L.m2[c]);
@@ -138,11 +146,44 @@ int validate_shape(const lbm_params *p, int *D, int *Q, size_t *sp, size_t *s, i
     return LBM_OK;
 }
 
-// Boundary nodes of a run: validates them and returns their count (host only).
+// Outward normal(s) of a bc_normal code (LBM_NORMAL_* or LBM_NORMAL_AXES) as one entry per axis
+// in {-1, 0, 1}; returns their number, or -1 for a code that is not one of those.
+int decode_normal(int code, int D, int nv[3]) {
+    nv[0] = nv[1] = nv[2] = 0;
+    if (code >= 0 && code < 2 * D) {
+        nv[code >> 1] = (code & 1) ? 1 : -1;
+        return 1;
+    }
+    if (code < 64 || code >= 128) return -1;
+    int k = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int sa = ((code - 64) >> (2 * a)) & 3;
+        if (sa == 3 || (sa != 0 && a >= D)) return -1;
+        nv[a] = sa == 1 ? -1 : (sa == 2 ? 1 : 0);
+        k += nv[a] != 0 ? 1 : 0;
+    }
+    return k > 0 ? k : -1;
+}
+
+// The normal code the kernels use: 0..5 for one normal, 64 + fields for two or three.
+uint32_t canonical_normal(const int nv[3]) {
+    int k = 0, a1 = 0;
+    uint32_t c = 64;
+    for (int a = 0; a < 3; ++a)
+        if (nv[a] != 0) {
+            ++k;
+            a1 = a;
+            c += (uint32_t)(nv[a] < 0 ? 1 : 2) << (2 * a);
+        }
+    return k == 1 ? (uint32_t)(2 * a1 + (nv[a1] > 0 ? 1 : 0)) : c;
+}
+
+// Boundary nodes of a run: validates them and returns their count (host only); visc: some face
+// velocity node takes its density from mass continuity (the viscous term then needs a stage).
 int boundary_nodes(const lbm_params *p, int D, int64_t N, uint32_t *count, bool *outflow,
-                   bool *vp) {
+                   bool *vp, bool *visc) {
     *count = 0;
-    *outflow = *vp = false;
+    *outflow = *vp = *visc = false;
     if (!p->bc_type) return LBM_OK;
     if (p->scheme != LBM_SCHEME_TWO_PASS)
         return fail(LBM_ERR_UNSUPPORTED, "wet-node boundaries need LBM_SCHEME_TWO_PASS");
@@ -151,6 +192,7 @@ int boundary_nodes(const lbm_params *p, int D, int64_t N, uint32_t *count, bool 
     if (p->bc_rho_rule != LBM_BC_RHO_CONTINUITY && p->bc_rho_rule != LBM_BC_RHO_BOUNCE_BACK)
         return fail(LBM_ERR_INVALID_ARG, "bad bc_rho_rule %d", p->bc_rho_rule);
     if (!p->bc_normal) return fail(LBM_ERR_INVALID_ARG, "bc_normal is required with bc_type");
+    if (!p->mask) return fail(LBM_ERR_INVALID_ARG, "wet-node boundaries need solid cells (mask)");
     const int nx = p->nx, ny = p->ny, nz = p->nz;
     auto cell = [&](int x, int y, int z) {
         x = (x % nx + nx) % nx;
@@ -158,23 +200,32 @@ int boundary_nodes(const lbm_params *p, int D, int64_t N, uint32_t *count, bool 
         z = (z % nz + nz) % nz;
         return (int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z);
     };
+    auto bulk = [&](int64_t c) { return !p->mask[c] && p->bc_type[c] == LBM_NODE_BULK; };
     uint32_t k = 0;
     for (int64_t n = 0; n < N; ++n) {
         const int t = p->bc_type[n];
         if (t == LBM_NODE_BULK) continue;
         if (t > LBM_NODE_OUTFLOW) return fail(LBM_ERR_INVALID_ARG, "bc_type[%lld] = %d", (long long)n, t);
-        const int nm = p->bc_normal[n];
-        if (nm >= 2 * D) return fail(LBM_ERR_INVALID_ARG, "bc_normal[%lld] = %d", (long long)n, nm);
-        if (p->mask && p->mask[n]) return fail(LBM_ERR_INVALID_ARG, "boundary node %lld is solid", (long long)n);
+        int o[3];
+        const int nn = decode_normal(p->bc_normal[n], D, o);
+        if (nn < 0) return fail(LBM_ERR_INVALID_ARG, "bc_normal[%lld] = %d", (long long)n, p->bc_normal[n]);
+        if (p->mask[n]) return fail(LBM_ERR_INVALID_ARG, "boundary node %lld is solid", (long long)n);
         const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
-        int o[3] = {0, 0, 0};
-        o[nm >> 1] = (nm & 1) ? 1 : -1;
-        const int64_t out = cell(x + o[0], y + o[1], z + o[2]);
-        const int64_t in = cell(x - o[0], y - o[1], z - o[2]);
-        if (!p->mask || !p->mask[out])
-            return fail(LBM_ERR_INVALID_ARG, "the outward neighbour of boundary node %lld must be solid", (long long)n);
-        if (p->mask[in] || p->bc_type[in] != LBM_NODE_BULK)
-            return fail(LBM_ERR_INVALID_ARG, "the inward neighbour of boundary node %lld must be a bulk fluid cell", (long long)n);
+        for (int a = 0; a < 3; ++a) {
+            if (o[a] == 0) continue;
+            const int64_t out = cell(x + (a == 0 ? o[0] : 0), y + (a == 1 ? o[1] : 0), z + (a == 2 ? o[2] : 0));
+            if (!p->mask[out])
+                return fail(LBM_ERR_INVALID_ARG, "the outward neighbour of boundary node %lld along axis %d must be solid", (long long)n, a);
+        }
+        if (nn == 1) {
+            if (!bulk(cell(x - o[0], y - o[1], z - o[2])))
+                return fail(LBM_ERR_INVALID_ARG, "the inward neighbour of boundary node %lld must be a bulk fluid cell", (long long)n);
+        } else {
+            if (t != LBM_NODE_VELOCITY)
+                return fail(LBM_ERR_INVALID_ARG, "edge or corner node %lld must be a velocity node", (long long)n);
+            if (!bulk(cell(x - o[0], y - o[1], z - o[2])) || !bulk(cell(x - 2 * o[0], y - 2 * o[1], z - 2 * o[2])))
+                return fail(LBM_ERR_INVALID_ARG, "edge or corner node %lld needs two bulk fluid cells along its inward diagonal", (long long)n);
+        }
         if (t == LBM_NODE_VELOCITY && p->bc_velocity)
             for (int a = 0; a < D; ++a)
                 if (!is_finite(p->bc_velocity[(int64_t)a * N + n]))
@@ -183,6 +234,7 @@ int boundary_nodes(const lbm_params *p, int D, int64_t N, uint32_t *count, bool 
             return fail(LBM_ERR_INVALID_ARG, "bc_density[%lld] must be finite and > 0", (long long)n);
         if (t == LBM_NODE_OUTFLOW) *outflow = true;
         else *vp = true;
+        if (t == LBM_NODE_VELOCITY && nn == 1 && p->bc_rho_rule == LBM_BC_RHO_CONTINUITY) *visc = true;
         ++k;
     }
     *count = k;
@@ -267,8 +319,8 @@ LBM_API int lbm_footprint(const lbm_params *p, size_t *workspace_bytes) {
     int rc = validate_shape(p, &D, &Q, &sp, &s, &N);
     if (rc) return rc;
     uint32_t nb = 0;
-    bool bo, bv;
-    rc = boundary_nodes(p, D, N, &nb, &bo, &bv);
+    bool bo, bv, bvisc;
+    rc = boundary_nodes(p, D, N, &nb, &bo, &bv, &bvisc);
     if (rc) return rc;
     const lbm::Tiling tl = make_tiling(p->nx, p->ny, p->nz, packed_rows_ok(p));
     *workspace_bytes = make_layout(Q, D, (size_t)N, sp, s, p->mask != nullptr,
@@ -326,8 +378,8 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     if (!any_fluid) return fail(LBM_ERR_INVALID_ARG, "no fluid cell");
     const bool solids = p->mask != nullptr;
     uint32_t nb = 0;
-    bool bc_outflow = false, bc_vp = false;
-    rc = boundary_nodes(p, D, N, &nb, &bc_outflow, &bc_vp);
+    bool bc_outflow = false, bc_vp = false, bc_visc = false;
+    rc = boundary_nodes(p, D, N, &nb, &bc_outflow, &bc_vp, &bc_visc);
     if (rc) return rc;
     const lbm::Tiling tiles = make_tiling(p->nx, p->ny, p->nz, packed_rows_ok(p));
     const Layout L = make_layout(Q, D, (size_t)N, sp, s, solids, p->scheme == LBM_SCHEME_LAGGED,
@@ -368,6 +420,7 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->nb = nb;
     h->bc_outflow = bc_outflow;
     h->bc_vp = bc_vp;
+    h->bc_visc = bc_visc;
     h->bc_scheme = p->bc_scheme;
     h->bc_rho_rule = p->bc_rho_rule;
     h->picard_iters = p->picard_iters;
@@ -443,7 +496,9 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
         for (int64_t n = 0; n < N; ++n) {
             if (!p->bc_type[n]) continue;
             bcell.push_back((uint32_t)n);
-            bcode.push_back((uint32_t)p->bc_type[n] | ((uint32_t)p->bc_normal[n] << 8));
+            int o[3];
+            decode_normal(p->bc_normal[n], D, o);
+            bcode.push_back((uint32_t)p->bc_type[n] | (canonical_normal(o) << 8));
             double v4[4] = {0.0, 0.0, 0.0, p->bc_density ? p->bc_density[n] : p->rho0};
             if (p->bc_velocity)
                 for (int a = 0; a < D; ++a) v4[a] = p->bc_velocity[(int64_t)a * N + n];

@@ -117,6 +117,7 @@ struct lbm_solver {
     int shift;          // 16-bit population shift (LBM_SHIFT_*)
     uint32_t nb;        // boundary nodes
     bool bc_outflow, bc_vp;  // outflow nodes, velocity or pressure nodes present
+    bool bc_visc;            // face velocity nodes whose density takes the viscous term
     int bc_scheme, bc_rho_rule;
     int picard_iters;
     double picard_omega;

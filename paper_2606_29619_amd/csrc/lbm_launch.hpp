@@ -126,6 +126,7 @@ struct BcRecordsPass {
     static constexpr bool kDerivs = true;
     const lbm_solver *h;
     size_t m1;
+    int stage;  // 0: every node; 1: face velocity nodes again, with the viscous term
     template <int D, typename T, typename P, bool S, int PH, bool AD>
     void operator()() {
         if constexpr (S)
@@ -134,7 +135,7 @@ struct BcRecordsPass {
                                ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
                                ws_ptr<const T>(h, h->L.muF), ws_ptr<lbm::P4<T>>(h, m1),
                                bnodes_of<T>(h), grid_of(h), phys_of<T>(h),
-                               h->bc_rho_rule == LBM_BC_RHO_BOUNCE_BACK ? 1 : 0);
+                               h->bc_rho_rule == LBM_BC_RHO_BOUNCE_BACK ? 1 : 0, stage);
     }
 };
 struct BcFixPass {

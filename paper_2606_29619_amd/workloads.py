@@ -182,9 +182,12 @@ def bump(s: np.ndarray, m: int = 1) -> np.ndarray:
 
 def sphere_duct_3d(nx=768, ny=384, nz=384, radius=96.0, center=None, phi=0.5, K=5e-3,
                    nu=0.052, dp=1e-4, rho0=1.0, RT=1.0 / 3.0, steps=20000,
-                   bump_m=None) -> Workload:
-    """Duct with solid walls on the y and z faces and a porous sphere; the pressure drop dp is
-    carried by an equivalent body force b_x = dp / (rho0 L_x) with p = rho RT.  bump_m None:
+                   bump_m=None, drive="body") -> Workload:
+    """Duct with solid walls on the y and z faces and a porous sphere.  drive "body": periodic
+    in x, the pressure drop dp carried by an equivalent body force b_x = dp / (rho0 L_x) with
+    p = rho RT.  drive "pressure": the x faces are solid layers too, and pressure nodes (Sec.
+    3.4) at x = 1 and x = nx - 2 hold rho0 +- dp / (2 RT); the walls keep halfway bounce-back,
+    b = 0, and the initial density falls linearly between the two.  bump_m None:
     a sharp sphere (porosity phi and permeability K inside, free fluid outside).  bump_m = m:
     the smooth inclusion of eq. (Porous_Cylinder_Profile) in 3D, eps = 1 - (1 - phi) B_m(s),
     s = r^2 / R^2, with 1/kappa = B_m(s) / K and C_F = 0.55 / sqrt(kappa) following the same
@@ -212,10 +215,30 @@ def sphere_duct_3d(nx=768, ny=384, nz=384, radius=96.0, center=None, phi=0.5, K=
     mask[0, :, :] = 1
     mask[-1, :, :] = 1
     kind = "sharp" if bump_m is None else f"bump m={bump_m}"
-    return Workload(name=f"porous sphere ({kind}) in duct D3Q27 {nx}x{ny}x{nz}", lattice=27,
-                    eps=eps, kappa=kappa, forch=forchheimer(kappa), mask=mask, nu_f=nu,
-                    nu_eff_ref=nu, nu_eff_pow=0, b=(dp / (rho0 * nx), 0.0, 0.0), rho0=rho0,
-                    RT=RT, steps=steps)
+    w = Workload(name=f"porous sphere ({kind}) in duct D3Q27 {nx}x{ny}x{nz}", lattice=27,
+                 eps=eps, kappa=kappa, forch=forchheimer(kappa), mask=mask, nu_f=nu,
+                 nu_eff_ref=nu, nu_eff_pow=0, b=(dp / (rho0 * nx), 0.0, 0.0), rho0=rho0,
+                 RT=RT, steps=steps)
+    if drive == "body":
+        return w
+    if drive != "pressure":
+        raise ValueError(f"drive {drive!r}")
+    drho = dp / RT
+    mask[:, :, 0] = 1
+    mask[:, :, -1] = 1
+    bct = np.zeros(eps.shape, np.uint8)
+    bcn = np.zeros(eps.shape, np.uint8)
+    brho = np.full(eps.shape, rho0)
+    bct[1:-1, 1:-1, 1], bcn[1:-1, 1:-1, 1] = 2, 0
+    bct[1:-1, 1:-1, -2], bcn[1:-1, 1:-1, -2] = 2, 1
+    brho[:, :, 1] = rho0 + drho / 2
+    brho[:, :, -2] = rho0 - drho / 2
+    xr = rho0 + drho / 2 - drho * (np.arange(nx) - 1.0) / (nx - 3)
+    w.rho_init = np.broadcast_to(xr, eps.shape).copy()
+    w.b = (0.0, 0.0, 0.0)
+    w.bc_type, w.bc_normal, w.bc_density = bct, bcn, brho
+    w.name = w.name.replace("in duct", "in pressure-driven duct")
+    return w
 
 
 def uniform_box(D=2, n=8, eps=0.5, K=0.1, cf=0.0, nu=0.05, b=(1e-4, 0.0, 0.0)) -> Workload:

@@ -166,3 +166,70 @@ def test_picard_iterations_match_oracle(case):
     errs = _errors(s, o)
     print(f"picard {case}:", errs, flush=True)
     assert max(errs.values()) <= FP64_TOL, errs
+
+
+# --------------------------------------------------------------------------------------------
+# Edge and corner nodes (Sec. 3.4.1), the viscous term of eq. (accel_approx_boundary), and the
+# pressure-driven sphere duct
+# --------------------------------------------------------------------------------------------
+def _smooth_eps(shape, amp=0.15):
+    """A porosity that varies across every face, so that the viscous term of the wall-normal
+    acceleration is not zero at the inlet and wall nodes."""
+    nz, ny, nx = shape
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    fz = np.cos(2 * np.pi * zz / nz + 0.5) if nz > 1 else 1.0
+    return 0.7 + amp * np.sin(2 * np.pi * xx / nx + 0.3) * np.cos(2 * np.pi * yy / ny + 0.2) * fz
+
+
+def _porous(w, pow_=0):
+    w.eps = _smooth_eps(w.shape)
+    w.kappa = np.full(w.shape, 0.5)
+    w.forch = 0.55 / np.sqrt(w.kappa)
+    w.nu_eff_pow = pow_
+    return w
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("rule", [0, 1])
+def test_corner_nodes_match_oracle(scheme, rule):
+    """D2Q9 channel of wet-node walls with a parabolic velocity inlet and a pressure outlet: four
+    corner nodes with two normals (density extrapolated along the inward diagonal, or by
+    bounce-back), face nodes whose density takes the viscous term (porosity varying at the
+    inlet and the walls), each rebuild scheme; 41 + 40 steps."""
+    w = _porous(workloads.wet_box(2, (20, 10, 1), faces={"x-": "inlet", "x+": "pressure"},
+                                  V=0.01, nu=0.05, scheme=scheme, rho_rule=rule))
+    s, o = _pair(w, (41, 40))
+    errs = _errors(s, o)
+    print(f"corners scheme {scheme} rule {rule}:", errs, flush=True)
+    assert max(errs.values()) <= FP64_TOL, errs
+
+
+@pytest.mark.parametrize("scheme,rule,pow_", [(1, 0, 0), (2, 0, -1), (0, 1, 1), (1, 1, 0)])
+def test_edge_and_corner_nodes_3d_match_oracle(scheme, rule, pow_):
+    """D3Q27 box of wet-node walls on the y and z faces, velocity inlet and pressure outlet on
+    the x faces: face, edge (two normals) and corner (three normals) nodes, porosity varying
+    everywhere, nu_eff = nu eps^p; 21 + 20 steps."""
+    w = _porous(workloads.wet_box(3, (12, 6, 5), faces={"x-": "inlet", "x+": "pressure"},
+                                  V=0.01, nu=0.05, scheme=scheme, rho_rule=rule), pow_)
+    s, o = _pair(w, (21, 20))
+    errs = _errors(s, o)
+    print(f"edges 3D scheme {scheme} rule {rule} p {pow_}:", errs, flush=True)
+    assert max(errs.values()) <= FP64_TOL, errs
+
+
+def test_pressure_driven_sphere_duct_matches_oracle():
+    """The sphere duct with a true pressure inlet and outlet (pressure nodes on solid x faces,
+    halfway bounce-back walls, b = 0) at 48 x 24 x 24 with a sphere of radius 6: FP64 within
+    1e-12 after 21 + 20 steps, FP32 within its rounding after 41."""
+    w = workloads.sphere_duct_3d(48, 24, 24, radius=6.0, bump_m=8, drive="pressure")
+    s, o = _pair(w, (21, 20))
+    errs = _errors(s, o)
+    print("pressure sphere duct fp64:", errs, flush=True)
+    assert max(errs.values()) <= FP64_TOL, errs
+    s32 = capi.Solver.from_workload(w, storage=capi.LBM_F32)
+    s32.step(41)
+    torch.cuda.synchronize()
+    errs = _errors(s32, o)
+    print("pressure sphere duct fp32:", errs, flush=True)
+    assert errs["f"] < 5e-6 and errs["rho"] < 5e-6, errs
+    assert max(errs[f"v{a}"] for a in range(3)) < 1e-3, errs

@@ -281,6 +281,49 @@ def test_boundary_footprint_and_validation():
     assert ei.value.code == capi.LBM_ERR_INVALID_ARG
 
 
+def _box_params(w, **over):
+    kw = dict(bc_type=w.bc_type, bc_normal=w.bc_normal, bc_velocity=w.bc_velocity,
+              bc_density=w.bc_density)
+    kw.update(over)
+    return capi.make_params(capi.LBM_D2Q9, capi.LBM_F64, w.eps, w.kappa, w.forch, w.mask, **kw)
+
+
+def test_edge_and_corner_node_validation():
+    """Edge and corner nodes (Sec. 3.4.1): velocity nodes with every listed outward neighbour
+    solid and two bulk fluid cells along the inward diagonal; codes are LBM_NORMAL_* or
+    LBM_NORMAL_AXES."""
+    from paper_2606_29619_amd import workloads
+    w = workloads.wet_box(2, (8, 6, 1), faces={"x-": "inlet", "x+": "pressure"})
+    assert w.bc_normal[0, 1, 1] == capi.LBM_NORMAL_AXES(-1, -1)
+    p, keep = _box_params(w)
+    assert capi.lbm_footprint(p) > 0
+
+    def rejects(bct=None, bcn=None, what=""):
+        pp, kk = _box_params(w, bc_type=w.bc_type if bct is None else bct,
+                             bc_normal=w.bc_normal if bcn is None else bcn)
+        with pytest.raises(capi.LbmError) as ei:
+            capi.lbm_footprint(pp)
+        assert ei.value.code == capi.LBM_ERR_INVALID_ARG and what in str(ei.value), str(ei.value)
+
+    bct = w.bc_type.copy()
+    bct[0, 1, -2] = capi.LBM_NODE_PRESSURE                # a corner as a pressure node
+    rejects(bct=bct, what="velocity node")
+    bcn = w.bc_normal.copy()
+    bcn[0, 1, 3] = capi.LBM_NORMAL_AXES(-1, -1)           # a wall node claiming a -x face
+    rejects(bcn=bcn, what="outward")
+    bcn = w.bc_normal.copy()
+    bcn[0, 1, 1] = capi.LBM_NORMAL_AXES(-1, -1, 1)        # a z normal on a D2Q9 grid
+    rejects(bcn=bcn)
+    bcn = w.bc_normal.copy()
+    bcn[0, 1, 1] = 64 + 3                                 # not a sign code
+    rejects(bcn=bcn)
+    small = workloads.wet_box(2, (8, 2, 1))               # the diagonal runs into the far wall
+    pp, kk = _box_params(small)
+    with pytest.raises(capi.LbmError) as ei:
+        capi.lbm_footprint(pp)
+    assert "diagonal" in str(ei.value) or "inward" in str(ei.value), str(ei.value)
+
+
 def test_server_rejects_boundary_runs():
     (p, keep), _ = _bc_params()
     s = capi.lbm_server_create(_FAKE_POOL, 1 << 30, 100, 0, 0)

@@ -76,9 +76,22 @@ def _channel_with_sine_porosity(D):
     return w
 
 
+def _corner_box_with_sine_porosity(D):
+    """A box of wet-node walls with a velocity inlet and a pressure outlet (corner and, in 3D,
+    edge nodes) whose porosity is a product of sines given with its analytic derivatives: the
+    viscous term of the face nodes' wall-normal acceleration reads them."""
+    n = (16, 8, 1) if D == 2 else (10, 6, 5)
+    w = workloads.wet_box(D, n, faces={"x-": "inlet", "x+": "pressure"}, V=0.01, nu=0.05)
+    sw = workloads.sine_porosity(D, shape=w.shape, amp=0.1)
+    w.eps, w.grad_eps, w.hess_eps = sw.eps, sw.grad_eps, sw.hess_eps
+    w.kappa = np.full(w.shape, 0.5)
+    w.forch = 0.55 / np.sqrt(w.kappa)
+    return w
+
+
 @pytest.mark.parametrize("case", ["quadratic_d2", "quadratic_d3", "sine_d3_pow_eta",
                                   "sine_d2_lagged", "pressure_d2", "pressure_d3",
-                                  "picard_sine_d2"])
+                                  "picard_sine_d2", "corners_d2", "corners_d3"])
 def test_analytic_derivatives_match_oracle(case):
     """FP64, 41 + 40 steps (both AA phases at the checks): closed quadratic-porosity boxes in
     2D and 3D, a periodic sine field with nu_eff = nu/eps and Phi^eta on, the lagged scheme,
@@ -95,6 +108,8 @@ def test_analytic_derivatives_match_oracle(case):
         lagged = True
     elif case.startswith("pressure"):
         w = _channel_with_sine_porosity(2 if case.endswith("d2") else 3)
+    elif case.startswith("corners"):
+        w = _corner_box_with_sine_porosity(2 if case.endswith("d2") else 3)
     else:
         w = workloads.sine_porosity(2, shape=(1, 33, 45), b=(3e-4, 1e-4, 0.0))
         w.picard_iters = 3
