@@ -144,6 +144,11 @@ extern "C" {
 #define LBM_TILES_AUTO 0
 #define LBM_TILES_RECTANGULAR 1
 
+/* Kernels of a two-pass step (lbm_params.passes). */
+#define LBM_PASSES_AUTO 0
+#define LBM_PASSES_SEPARATE 1
+#define LBM_PASSES_FUSED 2
+
 /* Output element type for lbm_moments / lbm_get_populations / lbm_set_populations. */
 #define LBM_DTYPE_F64 0
 #define LBM_DTYPE_F32 1
@@ -216,6 +221,14 @@ typedef struct lbm_params {
      * packs.  The tiles decide only which thread updates which cell: results are bitwise the
      * same. */
     int tiles;
+    /* Kernels of a two-pass step.  LBM_PASSES_FUSED corrects the velocity inside the
+     * collision pass (two kernels per step, the corrected velocities shared through LDS)
+     * where the run allows it: D3Q27, FP32 or FP64 storage, no solid cells, no wet-node
+     * boundaries, no Picard iterations, no analytic porosity derivatives, nx a multiple of 64
+     * and ny of 8; LBM_PASSES_AUTO does so for FP32 storage only (measured faster there, slower
+     * in FP64); every other run, and LBM_PASSES_SEPARATE, uses the separate correction pass.
+     * All give bitwise the same results. */
+    int passes;
 } lbm_params;
 
 /* Global statistics of the current state, accumulated in FP64 on the device. */
@@ -270,7 +283,9 @@ LBM_API int lbm_step(lbm_solver *h, int64_t n);
  * As lbm_step, and also measures each kernel class with HIP events on the handle's stream;
  * synchronises.  kernel_ms[0..2] receive the summed durations (ms) of the moment, velocity
  * correction and collide-stream kernels over the n steps (lagged steps count their single
- * kernel under collide-stream).
+ * kernel under collide-stream; a two-pass step whose correction runs inside the collision pass,
+ * see lbm_params.passes, reports 0 for the correction and the fused kernel under
+ * collide-stream).
  */
 LBM_API int lbm_step_timed(lbm_solver *h, int64_t n, double kernel_ms[3]);
 

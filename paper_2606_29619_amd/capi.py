@@ -46,6 +46,9 @@ LBM_SCHEME_TWO_PASS = 0
 LBM_SCHEME_LAGGED = 1
 LBM_TILES_AUTO = 0
 LBM_TILES_RECTANGULAR = 1
+LBM_PASSES_AUTO = 0          # velocity correction inside the collision pass for FP32 runs
+LBM_PASSES_SEPARATE = 1
+LBM_PASSES_FUSED = 2           # fused wherever the kernel supports the run (FP32 and FP64)
 LBM_DTYPE_F64 = 0
 LBM_DTYPE_F32 = 1
 LBM_VELOCITY_SUPERFICIAL = 0
@@ -69,7 +72,7 @@ class lbm_params(ctypes.Structure):
         ("bc_scheme", ctypes.c_int), ("bc_rho_rule", ctypes.c_int),
         ("picard_iters", ctypes.c_int), ("picard_omega", ctypes.c_double),
         ("grad_eps", _dp), ("hess_eps", _dp),
-        ("tiles", ctypes.c_int),
+        ("tiles", ctypes.c_int), ("passes", ctypes.c_int),
     ]
 
 
@@ -305,7 +308,8 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
                 bc_density: Optional[np.ndarray] = None, bc_scheme: int = LBM_BC_NEEM,
                 bc_rho_rule: int = LBM_BC_RHO_CONTINUITY, picard_iters: int = 0,
                 picard_omega: float = 1.0, grad_eps: Optional[np.ndarray] = None,
-                hess_eps: Optional[np.ndarray] = None, tiles: int = LBM_TILES_AUTO):
+                hess_eps: Optional[np.ndarray] = None, tiles: int = LBM_TILES_AUTO,
+                passes: int = LBM_PASSES_AUTO):
     """Build an lbm_params from numpy arrays shaped [nz, ny, nx]; returns (params, keepalive).
     grad_eps [D][nz, ny, nx] and hess_eps [D(D+1)/2][nz, ny, nx] (upper triangle row by row)
     are the optional analytic porosity derivatives."""
@@ -355,6 +359,7 @@ def make_params(lattice: int, storage: int, eps: np.ndarray, kappa: np.ndarray,
     p.grad_eps = arr(grad_eps, (D,) + eps.shape)
     p.hess_eps = arr(hess_eps, (D * (D + 1) // 2,) + eps.shape)
     p.tiles = tiles
+    p.passes = passes
     return p, keep
 
 
@@ -385,7 +390,8 @@ class Solver:
 
     @classmethod
     def from_workload(cls, w, storage: int = LBM_F32, scheme: int = LBM_SCHEME_TWO_PASS,
-                      shift: int = LBM_SHIFT_WEIGHTS, tiles: int = LBM_TILES_AUTO, **kw):
+                      shift: int = LBM_SHIFT_WEIGHTS, tiles: int = LBM_TILES_AUTO,
+                      passes: int = LBM_PASSES_AUTO, **kw):
         p, keep = make_params(w.lattice, storage, w.eps, w.kappa, w.forch, w.mask, RT=w.RT,
                               nu_f=w.nu_f, nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow,
                               eta_eff=w.eta_eff, b=w.b, rho0=w.rho0, rho_init=w.rho_init,
@@ -399,7 +405,8 @@ class Solver:
                               picard_iters=getattr(w, "picard_iters", 0),
                               picard_omega=getattr(w, "picard_omega", 1.0),
                               grad_eps=getattr(w, "grad_eps", None),
-                              hess_eps=getattr(w, "hess_eps", None), tiles=tiles)
+                              hess_eps=getattr(w, "hess_eps", None), tiles=tiles,
+                              passes=passes)
         return cls(p, keep, **kw)
 
     def close(self):

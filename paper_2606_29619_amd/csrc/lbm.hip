@@ -76,6 +76,19 @@ hipError_t one_step(lbm_solver *h, hipEvent_t *ev) {
         h->cur = nx;
     } else {
         const int c = h->cur;
+        if (h->fused_vc) {
+            // velocity correction inside the collision pass (timed with it)
+            dispatch(h, MomentsPass{h, h->L.m1[c]});
+            if (ev) e = hipEventRecord(ev[0], h->stream);
+            if (ev && e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
+            dispatch(h, CollideVcPass{h, h->L.m1[c]});
+            if (ev && e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
+            h->have_prev = true;
+            if (e == hipSuccess) e = hipGetLastError();
+            h->phase ^= 1;
+            h->step += 1;
+            return e;
+        }
         // wet-node boundaries: outflow copies, boundary records and population rebuild around
         // the bulk passes (they are timed with the pass they follow)
         if (h->bc_outflow) dispatch(h, BcOutflowPass{h});
@@ -132,6 +145,8 @@ int validate_shape(const lbm_params *p, int *D, int *Q, size_t *sp, size_t *s, i
         return fail(LBM_ERR_INVALID_ARG, "grad_eps and hess_eps go together (both or neither)");
     if (p->tiles != LBM_TILES_AUTO && p->tiles != LBM_TILES_RECTANGULAR)
         return fail(LBM_ERR_INVALID_ARG, "tiles must be LBM_TILES_AUTO or LBM_TILES_RECTANGULAR, got %d", p->tiles);
+    if (p->passes != LBM_PASSES_AUTO && p->passes != LBM_PASSES_SEPARATE && p->passes != LBM_PASSES_FUSED)
+        return fail(LBM_ERR_INVALID_ARG, "passes must be LBM_PASSES_AUTO, _SEPARATE or _FUSED, got %d", p->passes);
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LBM_ERR_INVALID_ARG, "dimensions must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
     if (*D == 2 && p->nz != 1) return fail(LBM_ERR_INVALID_ARG, "D2Q9 needs nz = 1 (got %d)", p->nz);
@@ -426,6 +441,12 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->picard_iters = p->picard_iters;
     h->picard_omega = p->picard_omega;
     h->analytic = p->grad_eps != nullptr;
+    h->fused_vc = (p->passes == LBM_PASSES_FUSED ? (p->storage == LBM_F32 || p->storage == LBM_F64)
+                                                 : p->passes == LBM_PASSES_AUTO && p->storage == LBM_F32) &&
+                  D == 3 && !solids && nb == 0 &&
+                  p->picard_iters == 0 && !h->analytic && p->scheme == LBM_SCHEME_TWO_PASS &&
+                  p->nx % lbm::kZX == 0 && p->ny % lbm::kZY == 0;
+    if (h->fused_vc) h->ztiles = make_ztiling(p->nx, p->ny, p->nz);
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return fail(LBM_ERR_HIP, "hipGetDevice failed");
@@ -592,8 +613,12 @@ LBM_API int lbm_step_timed(lbm_solver *h, int64_t n, double kernel_ms[3]) {
         }
         for (int64_t k = 0; k < m; ++k)
             for (int j = 0; j < 3; ++j) {
+                // a two-pass step with the correction inside the collision pass has no
+                // correction kernel: its share is 0 and the collision's interval spans both
+                if (h->fused_vc && h->scheme == LBM_SCHEME_TWO_PASS && j == 1) continue;
+                const int j0 = h->fused_vc && h->scheme == LBM_SCHEME_TWO_PASS && j == 2 ? 1 : j;
                 float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, ev[3 * k + j], ev[3 * k + j + 1]);
+                (void)hipEventElapsedTime(&ms, ev[3 * k + j0], ev[3 * k + j + 1]);
                 acc[j] += ms;
             }
         done += m;

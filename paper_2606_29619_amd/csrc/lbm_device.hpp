@@ -768,21 +768,15 @@ __device__ __forceinline__ void accel_of(const P4<T> *__restrict__ mom,
 // Equilibrium and shifted-equilibrium arguments of one cell from the moment fields (rho, v):
 // acceleration (accel), Phi^ext (ex_corr), Phi^eta (eta_corr), then xi, P (xi_alpha_eq,
 // P_alpha_alpha_eq) and xi*, P* (xi_alpha_*, P_aa_*) with lambda = 1.  `own` is the cell's
-// record; the neighbour records come from `mom` (the same step's, or the previous step's in
-// the lagged scheme).
+// record and rec / fl its axis neighbours; `mom` (the same step's records, or the previous
+// step's in the lagged scheme) is read only for the one-sided stencils next to solids.
 template <int D, typename T, bool SOLIDS, typename E>
-__device__ __forceinline__ void forcing_args(const P4<T> *__restrict__ mom, const E &ev,
-                                             const T *__restrict__ eps,
-                                             const T *__restrict__ muD,
-                                             const T *__restrict__ muF,
-                                             const uint8_t *__restrict__ mask, const Grid &g,
-                                             const Phys<T> &ph, const Nbr<D> &nb,
-                                             const Rec<T> &own, const T ge[3], const T H[3][3],
-                                             const Visc<T> &vs, T xi[3], T P[3], T xs[3],
-                                             T Ps[3]) {
-    Rec<T> rec[3][2];
-    bool fl[3][2];
-    load_stencil<D, T, SOLIDS>(mom, ev, mask, g, nb, rec, fl);
+__device__ __forceinline__ void forcing_args_stencil(
+    const P4<T> *__restrict__ mom, const E &ev, const T *__restrict__ eps,
+    const T *__restrict__ muD, const T *__restrict__ muF, const uint8_t *__restrict__ mask,
+    const Grid &g, const Phys<T> &ph, const Nbr<D> &nb, const Rec<T> &own,
+    const Rec<T> rec[3][2], const bool fl[3][2], const T ge[3], const T H[3][3],
+    const Visc<T> &vs, T xi[3], T P[3], T xs[3], T Ps[3]) {
     T acc[3];
     accel_of<D, T, SOLIDS>(mom, eps, muD, muF, mask, g, ph, nb, own, rec, fl, ge, H, vs, acc);
     T phx[3];
@@ -813,6 +807,24 @@ __device__ __forceinline__ void forcing_args(const P4<T> *__restrict__ mom, cons
         xs[a] = dv(own.w[a] + acc[a], own.e);
         Ps[a] = (xs[a] * xs[a] + ph.RT) + ier * (phx[a] + pheta);
     }
+}
+
+// The same with the axis neighbours read from the records `mom`.
+template <int D, typename T, bool SOLIDS, typename E>
+__device__ __forceinline__ void forcing_args(const P4<T> *__restrict__ mom, const E &ev,
+                                             const T *__restrict__ eps,
+                                             const T *__restrict__ muD,
+                                             const T *__restrict__ muF,
+                                             const uint8_t *__restrict__ mask, const Grid &g,
+                                             const Phys<T> &ph, const Nbr<D> &nb,
+                                             const Rec<T> &own, const T ge[3], const T H[3][3],
+                                             const Visc<T> &vs, T xi[3], T P[3], T xs[3],
+                                             T Ps[3]) {
+    Rec<T> rec[3][2];
+    bool fl[3][2];
+    load_stencil<D, T, SOLIDS>(mom, ev, mask, g, nb, rec, fl);
+    forcing_args_stencil<D, T, SOLIDS>(mom, ev, eps, muD, muF, mask, g, ph, nb, own, rec, fl, ge,
+                                       H, vs, xi, P, xs, Ps);
 }
 
 // One-dimensional factors of eq. (1d_scaled_eq) for c = -1, 0, +1.
@@ -1159,29 +1171,20 @@ __device__ __forceinline__ void vcorrect_body(const P4<T> *__restrict__ own_src,
     store_rec<D>(m2_out, n, own.r, v);
 }
 
-// Pass two of the two-pass scheme: forcing from the (rho, v) records, collision, streaming.
-template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
-__device__ __forceinline__ void collide_body(P *__restrict__ f,
-                                                 const P4<T> *__restrict__ m2,
-                                                 const T *__restrict__ eps,
-                                                 const T *__restrict__ muD,
-                                                 const T *__restrict__ muF,
-                                                 const uint8_t *__restrict__ mask, Grid g,
-                                                 Tiling tl, Phys<T> ph, uint32_t wg) {
-    LBM_TILE_PROLOGUE(D, wg, (false))
-    if constexpr (SOLIDS) {
-        if (mask[n]) return;
-    }
-    const Rec<T> own = load_rec<D>(m2, n, ev.at(0, 0, 0));
-    const CellStatic<D, T> cs = cell_static<D, AD>(ev, ph, n, own.e);
-    ProductForm<D, T> peq, pst;
-    cell_equilibria<D, T, SOLIDS>(m2, ev, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
-    // The populations are loaded only now, after the forcing arguments, and in groups that are
-    // collided and stored before the next group is loaded: fewer registers are live, so more
-    // waves share each SIMD (16-bit storage: 3 -> 4 waves, 22 % faster).
+// Collision and streaming of the cell's populations with the equilibria peq, pst.  The
+// populations are loaded only after the forcing arguments, and in groups that are collided and
+// stored before the next group is loaded: fewer registers are live, so more waves share each
+// SIMD (16-bit storage: 3 -> 4 waves, 22 % faster).
+template <int D, typename T, typename P, bool SOLIDS, int PH, typename E>
+__device__ __forceinline__ void collide_populations(P *__restrict__ f,
+                                                    const uint8_t *__restrict__ mask,
+                                                    const Grid &g, const Phys<T> &ph,
+                                                    const E &ev, const Nbr<D> &nb, T beta,
+                                                    const ProductForm<D, T> &peq,
+                                                    const ProductForm<D, T> &pst) {
     __builtin_amdgcn_sched_barrier(0);
-    const T two_beta = T(2) * cs.vs.beta;
-    const T omb = T(1) - cs.vs.beta;
+    const T two_beta = T(2) * beta;
+    const T omb = T(1) - beta;
     const float base = own_base<P>(ev.at(0, 0, 0), ph);
     // Swapped phase: population addresses recomputed from an opaque copy of the neighbourhood
     // (16-bit storage 0.76 -> 0.68 ms on the 256^3 box, FP64 2 % faster).  FP32 storage keeps
@@ -1223,6 +1226,26 @@ __device__ __forceinline__ void collide_body(P *__restrict__ f,
         });
         __builtin_amdgcn_sched_barrier(0);
     });
+}
+
+// Pass two of the two-pass scheme: forcing from the (rho, v) records, collision, streaming.
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
+__device__ __forceinline__ void collide_body(P *__restrict__ f,
+                                                 const P4<T> *__restrict__ m2,
+                                                 const T *__restrict__ eps,
+                                                 const T *__restrict__ muD,
+                                                 const T *__restrict__ muF,
+                                                 const uint8_t *__restrict__ mask, Grid g,
+                                                 Tiling tl, Phys<T> ph, uint32_t wg) {
+    LBM_TILE_PROLOGUE(D, wg, (false))
+    if constexpr (SOLIDS) {
+        if (mask[n]) return;
+    }
+    const Rec<T> own = load_rec<D>(m2, n, ev.at(0, 0, 0));
+    const CellStatic<D, T> cs = cell_static<D, AD>(ev, ph, n, own.e);
+    ProductForm<D, T> peq, pst;
+    cell_equilibria<D, T, SOLIDS>(m2, ev, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
+    collide_populations<D, T, P, SOLIDS, PH>(f, mask, g, ph, ev, nb, cs.vs.beta, peq, pst);
 }
 
 // One pass of the lagged scheme: the cell's own moments, velocity correction and forcing are
@@ -1423,6 +1446,131 @@ void k_collide(P *__restrict__ f, const P4<T> *__restrict__ m2, const T *__restr
         }
     }
     collide_body<D, T, P, SOLIDS, PH, AD>(f, m2, eps, muD, muF, mask, g, tl, ph, blockIdx.x);
+}
+
+// ------------------------------------------------------------------------------------------
+// Two-pass step with the velocity correction fused into the collision pass (D3Q27, no solids,
+// differenced porosity derivatives, populations stored in the arithmetic type).  The collision
+// of a cell reads the corrected velocity of the cell and its six face neighbours, and the
+// correction of a cell reads the (rho, v^(1)) records of its own six face neighbours.  A
+// workgroup of 1024 threads owns a 64 x 8 tile of cells and marches it through a chunk of
+// z-planes.  Its first eight waves correct the velocity of the tile and its one-cell ring in x
+// and y (652 cells, from the records of the moment pass exactly as the separate correction
+// pass reads them) two planes ahead, into a ring of four planes in LDS, while its last eight
+// waves collide the current plane from the ring; one barrier per plane.  The corrected
+// velocities never go through HBM (the separate pass writes them and the collision reads them
+// back, 32 B per cell), at the price of correcting the ring cells (1.27x) and the chunk's end
+// planes again (256^3 box, FP32: 64 x 4 tiles with four and four waves 1.045 ms, 64 x 8 tiles
+// 1.012 ms, against 0.225 + 0.833 ms for the separate passes; fewer correcting waves were
+// slower, 1.22 and 1.38 ms with three and two).
+// With the two kinds of work in different waves, the correction's arithmetic and cached
+// gathers run beside the collision's HBM streams instead of between them.  Every expression
+// is the separate passes' own, so the results are bitwise the same.
+struct ZTiling {
+    int ntx, nty, nch;  // tiles along x (64 cells) and y (4 rows), chunks along z
+    int zc;             // planes per chunk
+    uint32_t per;       // workgroups per XCD (padded)
+};
+constexpr int kZX = 64, kZY = 8;
+constexpr int kZRX = kZX + 2, kZRY = kZY + 2, kZR = kZRX * kZRY;
+// threads of a fused workgroup: kZProd correct velocities, the kZX * kZY others collide
+constexpr int kZProd = 512, kZThreads = kZProd + kZX * kZY;
+
+template <typename T, int PH>
+__global__ __launch_bounds__(kZThreads) void k_collide_vc(T *__restrict__ f,
+                                                    const P4<T> *__restrict__ m1,
+                                                    const T *__restrict__ eps,
+                                                    const T *__restrict__ muD,
+                                                    const T *__restrict__ muF, Grid g,
+                                                    ZTiling zt, Phys<T> ph) {
+    constexpr int D = 3;
+    using L = Lat<D>;
+    // (rho, v) of four consecutive planes: the ring slot of plane z is (z - z0 + 4) mod 4
+    __shared__ P4<T> vr[4][kZR];
+    const uint32_t t = (blockIdx.x & 7u) * zt.per + (blockIdx.x >> 3);
+    if (t >= (uint32_t)zt.ntx * (uint32_t)zt.nty * (uint32_t)zt.nch) return;  // whole workgroup
+    const int x0 = (int)(t % (uint32_t)zt.ntx) * kZX;
+    const uint32_t r = t / (uint32_t)zt.ntx;
+    const int y0 = (int)(r % (uint32_t)zt.nty) * kZY;
+    const int z0 = (int)(r / (uint32_t)zt.nty) * zt.zc;
+    const int z1 = min(z0 + zt.zc, g.nz);
+    // the first kZProd threads correct velocities, the others collide (the branch is uniform
+    // per wave)
+    const bool producer = threadIdx.x < (uint32_t)kZProd;
+    const int tid = producer ? (int)threadIdx.x : (int)threadIdx.x - kZProd;
+    auto wrap = [](int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); };
+    auto slot = [&](int zz) { return (zz - z0 + 4) & 3; };
+
+    // corrected velocity of plane zz (z0 - 1 <= zz <= z1) on the tile and its ring
+    auto correct_plane = [&](int zz) {
+        P4<T> *dst = vr[slot(zz)];
+        const int zp = wrap(zz, g.nz);
+        for (int j = tid; j < kZR; j += kZProd) {
+            const int rx = j % kZRX, ry = j / kZRX;
+            if ((rx == 0 || rx == kZRX - 1) && (ry == 0 || ry == kZRY - 1)) continue;  // corners
+            Nbr<D> nb;
+            nb.init(g, wrap(x0 + rx - 1, g.nx), wrap(y0 + ry - 1, g.ny), zp);
+            const EpsGlobal<D, T> ev{eps, &nb};
+            const uint32_t c = nb.self();
+            const Rec<T> own = load_rec<D>(m1, c, ev.at(0, 0, 0));
+            const CellStatic<D, T> cs = cell_static<D, false>(ev, ph, c, own.e);
+            T v[3];
+            corrected_velocity<D, T, false>(m1, ev, eps, nullptr, g, nb, own, cs, v);
+            dst[j] = pack(own.r, v[0], v[1], v[2]);
+        }
+    };
+    auto rec_at = [](const P4<T> &q, T e) {
+        Rec<T> o;
+        o.r = q.x;
+        o.w[0] = q.y;
+        o.w[1] = q.z;
+        o.w[2] = q.w;
+        o.e = e;
+        return o;
+    };
+
+    if (producer) {
+        correct_plane(z0 - 1);
+        correct_plane(z0);
+        correct_plane(z0 + 1);
+    }
+    __syncthreads();
+    const int lx = tid & 63, ly = tid >> 6;
+    const int j = (ly + 1) * kZRX + lx + 1;
+    for (int zz = z0; zz < z1; ++zz) {
+        if (producer) {
+            // the plane after next, while the consumers collide this one
+            if (zz + 2 <= z1) correct_plane(zz + 2);
+        } else {
+            const P4<T> *vm = vr[slot(zz - 1)], *vc = vr[slot(zz)], *vp = vr[slot(zz + 1)];
+            Nbr<D> nb;
+            nb.init(g, x0 + lx, y0 + ly, zz);
+            const EpsGlobal<D, T> ev{eps, &nb};
+            const uint32_t n = nb.self();
+            const Rec<T> own = rec_at(vc[j], ev.at(0, 0, 0));
+            const CellStatic<D, T> cs = cell_static<D, false>(ev, ph, n, own.e);
+            Rec<T> rec[3][2];
+            bool fl[3][2];
+            rec[0][0] = rec_at(vc[j - 1], ev.at(-1, 0, 0));
+            rec[0][1] = rec_at(vc[j + 1], ev.at(1, 0, 0));
+            rec[1][0] = rec_at(vc[j - kZRX], ev.at(0, -1, 0));
+            rec[1][1] = rec_at(vc[j + kZRX], ev.at(0, 1, 0));
+            rec[2][0] = rec_at(vm[j], ev.at(0, 0, -1));
+            rec[2][1] = rec_at(vp[j], ev.at(0, 0, 1));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) fl[a][0] = fl[a][1] = true;
+            T xi[3], P[3], xs[3], Ps[3];
+            forcing_args_stencil<D, T, false>(nullptr, ev, eps, muD, muF, nullptr, g, ph, nb, own,
+                                              rec, fl, cs.ge, cs.H, cs.vs, xi, P, xs, Ps);
+            ProductForm<D, T> peq, pst;
+            const T er = own.e * own.r;
+            peq.init(er, xi, P);
+            pst.init(er, xs, Ps);
+            collide_populations<D, T, T, false, PH>(f, nullptr, g, ph, ev, nb, cs.vs.beta, peq,
+                                                    pst);
+        }
+        __syncthreads();
+    }
 }
 
 template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>

@@ -123,6 +123,8 @@ struct lbm_solver {
     double picard_omega;
     bool analytic;      // analytic porosity derivatives in L.deps
     lbm::Tiling tiles;  // 256-cell tiles, blocked, in XCD-contiguous ranges
+    bool fused_vc;      // velocity correction inside the collision pass (k_collide_vc)
+    lbm::ZTiling ztiles;
     int device;         // HIP device current at creation
 };
 
@@ -166,6 +168,19 @@ inline lbm::Grid grid_of(const lbm_solver *h) { return lbm::Grid{h->nx, h->ny, h
 
 
 inline dim3 flat_grid(int64_t total) { return dim3((unsigned)((total + 255) / 256)); }
+
+// Tiles of the fused correction-collision pass: 64 x 8 cells (nx % 64 == 0, ny % 8 == 0),
+// chunks of 32 z-planes, the eight XCDs taking contiguous ranges of the x-fastest, then y, then
+// chunk order (neighbouring tiles in y share their ring rows in the XCD's L2).
+inline lbm::ZTiling make_ztiling(int nx, int ny, int nz) {
+    lbm::ZTiling z{};
+    z.ntx = nx / lbm::kZX;
+    z.nty = ny / lbm::kZY;
+    z.zc = std::min(32, nz);
+    z.nch = (nz + z.zc - 1) / z.zc;
+    z.per = (uint32_t)(((int64_t)z.ntx * z.nty * z.nch + 7) / 8);
+    return z;
+}
 
 // Tiles of the cell passes.  Rectangular tiles (256 x 1, 128 x 2 or 64 x 4 cells) when the x
 // extent is a multiple of 64 or the kernels stage porosity in LDS (16-bit storage, which needs

@@ -54,6 +54,15 @@ void launch_collide(const lbm_solver *h, size_t m2) {
                        tsolid_ptr(h), grid_of(h), h->tiles, ph);
 }
 
+template <int D, typename T, typename P, bool S, int PH>
+void launch_collide_vc(const lbm_solver *h, size_t m1) {
+    if constexpr (D == 3 && std::is_same_v<T, P> && !S)
+        hipLaunchKernelGGL((lbm::k_collide_vc<T, PH>), dim3(8 * h->ztiles.per), dim3(lbm::kZThreads), 0,
+                           h->stream, ws_ptr<T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m1),
+                           ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
+                           ws_ptr<const T>(h, h->L.muF), grid_of(h), h->ztiles, phys_of<T>(h));
+}
+
 template <int D, typename T, typename P, bool S, int PH, bool AD>
 void launch_fused(const lbm_solver *h, int prev, int next) {
     auto ph = phys_of<T>(h);
@@ -235,6 +244,13 @@ struct CollidePass {
     size_t m2;
     template <int D, typename T, typename P, bool S, int PH, bool AD>
     void operator()() { launch_collide<D, T, P, S, PH, AD>(h, m2); }
+};
+struct CollideVcPass {  // only dispatched for runs with fused_vc (D3Q27, T = P, no solids)
+    static constexpr bool kDerivs = false;
+    const lbm_solver *h;
+    size_t m1;
+    template <int D, typename T, typename P, bool S, int PH>
+    void operator()() { launch_collide_vc<D, T, P, S, PH>(h, m1); }
 };
 struct PicardPass {
     static constexpr bool kDerivs = true;

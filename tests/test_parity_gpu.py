@@ -620,3 +620,48 @@ def test_analytic_derivatives_on_a_tile_multiple_box():
     errs = _field_errors(s, o)
     _print("analytic box:", errs)
     assert max(errs.values()) <= FP64_TOL, errs
+
+
+# --------------------------------------------------------------------------------------------
+# Velocity correction inside the collision pass (LBM_PASSES_AUTO)
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,opts", [((12, 8, 64), False), ((40, 16, 128), True),
+                                        ((3, 8, 64), True), ((17, 8, 192), False)])
+def test_fused_correction_pass_fp64(shape, opts):
+    """Shapes that take the fused correction-collision kernel (x a multiple of 64, y of 8, no
+    solids): one to three 64-cell tiles along x, y tiles whose ring wraps onto the tile itself,
+    z-chunks of 32 planes with a partial last one and a three-plane box, with and without every
+    forcing option (RT != 1/3, Phi^eta, nu_eff = nu_ref / eps): bitwise (1e-12) to the oracle
+    after 5 steps and after 8; the timed step reports no separate correction kernel."""
+    w = workloads.random_porosity_3d(shape=shape, seed=23, ell=3.0, nu=0.03, b=2e-4)
+    if opts:
+        w.RT = 0.36
+        w.eta_eff = 0.02
+        w.nu_eff_pow = -1
+    s = capi.Solver.from_workload(w, storage=capi.LBM_F64, passes=capi.LBM_PASSES_FUSED)
+    o = _oracle_for(w)
+    s.step(5)
+    o.step(5)
+    errs = _field_errors(s, o)
+    _print(f"fused {shape} opts={opts} t=5:", errs)
+    assert max(errs.values()) <= FP64_TOL, errs
+    ms = s.step_timed(3)
+    o.step(3)
+    assert ms[1] == 0.0 and ms[2] > 0.0, ms
+    errs = _field_errors(s, o)
+    _print(f"fused {shape} opts={opts} t=8:", errs)
+    assert max(errs.values()) <= FP64_TOL, errs
+
+
+def test_fused_and_separate_passes_are_bitwise_equal():
+    """FP32 storage: the fused correction-collision kernel and the separate correction pass
+    evaluate the same expressions, so 7 steps (both AA phases) give identical populations and
+    moments."""
+    w = workloads.random_porosity_3d(shape=(20, 16, 128), seed=3, ell=4.0)
+    a = capi.Solver.from_workload(w, storage=capi.LBM_F32)
+    b = capi.Solver.from_workload(w, storage=capi.LBM_F32, passes=capi.LBM_PASSES_SEPARATE)
+    ta, tb = a.step_timed(7), b.step_timed(7)
+    assert ta[1] == 0.0 and tb[1] > 0.0, (ta, tb)
+    assert torch.equal(a.populations(torch.float64), b.populations(torch.float64))
+    for x, y in zip(a.moments(torch.float64), b.moments(torch.float64)):
+        assert torch.equal(x, y)
