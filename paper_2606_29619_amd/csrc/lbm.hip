@@ -445,8 +445,11 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
                                                  : p->passes == LBM_PASSES_AUTO && p->storage == LBM_F32) &&
                   D == 3 && !solids && nb == 0 &&
                   p->picard_iters == 0 && !h->analytic && p->scheme == LBM_SCHEME_TWO_PASS &&
-                  p->nx % lbm::kZX == 0 && p->ny % lbm::kZY == 0;
-    if (h->fused_vc) h->ztiles = make_ztiling(p->nx, p->ny, p->nz);
+                  p->nx % 64 == 0 &&
+                  p->ny % (p->storage == LBM_F64 ? lbm::ZCfg<double>::kY : lbm::ZCfg<float>::kY) == 0;
+    if (h->fused_vc)
+        h->ztiles = make_ztiling(p->nx, p->ny, p->nz,
+                                 p->storage == LBM_F64 ? lbm::ZCfg<double>::kY : lbm::ZCfg<float>::kY);
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return fail(LBM_ERR_HIP, "hipGetDevice failed");

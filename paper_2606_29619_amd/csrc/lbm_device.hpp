@@ -877,18 +877,10 @@ __device__ __forceinline__ CellStatic<D, T> cell_static(const E &ev, const Phys<
     return c;
 }
 
-// Velocity correction (v_final): v = v^(1) + Delta_nu(rho v^(1) / eps) / (2 rho) from the
-// cell's own record (rho, v^(1)) and the neighbour records in `m1`.
-template <int D, typename T, bool SOLIDS, typename E>
-__device__ __forceinline__ void corrected_velocity(const P4<T> *__restrict__ m1, const E &ev,
-                                                   const T *__restrict__ eps,
-                                                   const uint8_t *__restrict__ mask,
-                                                   const Grid &g, const Nbr<D> &nb,
-                                                   const Rec<T> &own, const CellStatic<D, T> &cs,
-                                                   T v[3]) {
-    // Where eps is locally uniform (zero gradient and Hessian: free fluid, or the plateau of a
-    // porous region) every term of Delta_nu carries a factor of them and vanishes, and the
-    // stencil need not be read: v = v^(1) + 0.
+// Where eps is locally uniform (zero gradient and Hessian: free fluid, or the plateau of a
+// porous region) every term of Delta_nu carries a factor of them and vanishes.
+template <int D, typename T>
+__device__ __forceinline__ bool porosity_flat(const CellStatic<D, T> &cs) {
     bool flat = true;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -896,17 +888,43 @@ __device__ __forceinline__ void corrected_velocity(const P4<T> *__restrict__ m1,
 #pragma unroll
         for (int b = 0; b < D; ++b) flat = flat && cs.H[a][b] == T(0);
     }
+    return flat;
+}
+
+// Velocity correction (v_final) from the cell's record and its axis neighbours rec / fl:
+// v = v^(1) + Delta_nu(rho v^(1) / eps) / (2 rho); on flat porosity v = v^(1) + 0 (the value of
+// the full evaluation) and the stencil is not used.
+template <int D, typename T, bool SOLIDS>
+__device__ __forceinline__ void velocity_from_stencil(const P4<T> *__restrict__ m1,
+                                                      const T *__restrict__ eps,
+                                                      const uint8_t *__restrict__ mask,
+                                                      const Grid &g, const Nbr<D> &nb,
+                                                      const Rec<T> &own, const Rec<T> rec[3][2],
+                                                      const bool fl[3][2],
+                                                      const CellStatic<D, T> &cs, bool flat,
+                                                      T v[3]) {
     T dn[3] = {T(0), T(0), T(0)};
-    if (!flat) {
-        Rec<T> rec[3][2];
-        bool fl[3][2];
-        load_stencil<D, T, SOLIDS>(m1, ev, mask, g, nb, rec, fl);
-        delta_nu<D, T, SOLIDS>(m1, eps, mask, g, nb, own, rec, fl, cs.ge, cs.H, cs.vs, dn);
-    }
+    if (!flat) delta_nu<D, T, SOLIDS>(m1, eps, mask, g, nb, own, rec, fl, cs.ge, cs.H, cs.vs, dn);
 #pragma unroll
     for (int a = 0; a < 3; ++a) v[a] = T(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) v[a] = own.w[a] + dv(dn[a], T(2) * own.r);
+}
+
+// Velocity correction (v_final) from the cell's own record (rho, v^(1)) and the neighbour
+// records in `m1`, read only where the porosity is not flat.
+template <int D, typename T, bool SOLIDS, typename E>
+__device__ __forceinline__ void corrected_velocity(const P4<T> *__restrict__ m1, const E &ev,
+                                                   const T *__restrict__ eps,
+                                                   const uint8_t *__restrict__ mask,
+                                                   const Grid &g, const Nbr<D> &nb,
+                                                   const Rec<T> &own, const CellStatic<D, T> &cs,
+                                                   T v[3]) {
+    const bool flat = porosity_flat<D, T>(cs);
+    Rec<T> rec[3][2];
+    bool fl[3][2];
+    if (!flat) load_stencil<D, T, SOLIDS>(m1, ev, mask, g, nb, rec, fl);
+    velocity_from_stencil<D, T, SOLIDS>(m1, eps, mask, g, nb, own, rec, fl, cs, flat, v);
 }
 
 // Equilibria of the cell (prod_form) for the equilibrium and shifted-equilibrium arguments.
@@ -1471,22 +1489,45 @@ struct ZTiling {
     int zc;             // planes per chunk
     uint32_t per;       // workgroups per XCD (padded)
 };
-constexpr int kZX = 64, kZY = 8;
-constexpr int kZRX = kZX + 2, kZRY = kZY + 2, kZR = kZRX * kZRY;
-// threads of a fused workgroup: kZProd correct velocities, the kZX * kZY others collide
-constexpr int kZProd = 512, kZThreads = kZProd + kZX * kZY;
+// Shape of a fused workgroup for arithmetic type T: a kX x kY tile (kX * kY collision
+// threads, as many correcting threads), the ring of corrected velocities (kRX x kRY) and the
+// staged region of the correcting waves (the tile and two rings, kSX x kSY).  FP64 takes
+// 64 x 4 tiles: its LDS rings would not fit 160 KB at 64 x 8.
+template <typename T>
+struct ZCfg {
+    static constexpr int kX = 64, kY = sizeof(T) == 8 ? 4 : 8;
+    static constexpr int kRX = kX + 2, kRY = kY + 2, kR = kRX * kRY;
+    static constexpr int kSX = kX + 4, kSY = kY + 4, kS = kSX * kSY;
+    static constexpr int kProd = kX * kY, kThreads = 2 * kX * kY;
+};
+
+// Porosity of a cell's 3x3x3 neighbourhood from planes staged in LDS.
+template <typename T>
+struct EpsRing {
+    const T *p[3];  // the cell's own entry in the planes z - 1, z, z + 1
+    int row;
+    __device__ __forceinline__ T at(int dx, int dy, int dz) const {
+        return p[dz + 1][dy * row + dx];
+    }
+};
 
 template <typename T, int PH>
-__global__ __launch_bounds__(kZThreads) void k_collide_vc(T *__restrict__ f,
-                                                    const P4<T> *__restrict__ m1,
-                                                    const T *__restrict__ eps,
-                                                    const T *__restrict__ muD,
-                                                    const T *__restrict__ muF, Grid g,
-                                                    ZTiling zt, Phys<T> ph) {
+__global__ __launch_bounds__(ZCfg<T>::kThreads) void k_collide_vc(T *__restrict__ f,
+                                                          const P4<T> *__restrict__ m1,
+                                                          const T *__restrict__ eps,
+                                                          const T *__restrict__ muD,
+                                                          const T *__restrict__ muF, Grid g,
+                                                          ZTiling zt, Phys<T> ph) {
     constexpr int D = 3;
-    using L = Lat<D>;
-    // (rho, v) of four consecutive planes: the ring slot of plane z is (z - z0 + 4) mod 4
+    using C = ZCfg<T>;
+    constexpr int kZX = C::kX, kZY = C::kY, kZRX = C::kRX, kZRY = C::kRY, kZR = C::kR;
+    constexpr int kZSX = C::kSX, kZS = C::kS, kZProd = C::kProd;
+    // (rho, v) of four consecutive planes on the tile and its ring: slot of plane z (z - z0 + 4) & 3
     __shared__ P4<T> vr[4][kZR];
+    // (rho, v^(1)) records and porosity of four consecutive planes on the tile and two rings
+    // (kZSX x kZSY cells), the correcting waves' inputs: slot of plane z (z - z0 + 8) & 3
+    __shared__ P4<T> rs[4][kZS];
+    __shared__ T es[4][kZS];
     const uint32_t t = (blockIdx.x & 7u) * zt.per + (blockIdx.x >> 3);
     if (t >= (uint32_t)zt.ntx * (uint32_t)zt.nty * (uint32_t)zt.nch) return;  // whole workgroup
     const int x0 = (int)(t % (uint32_t)zt.ntx) * kZX;
@@ -1499,26 +1540,8 @@ __global__ __launch_bounds__(kZThreads) void k_collide_vc(T *__restrict__ f,
     const bool producer = threadIdx.x < (uint32_t)kZProd;
     const int tid = producer ? (int)threadIdx.x : (int)threadIdx.x - kZProd;
     auto wrap = [](int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); };
-    auto slot = [&](int zz) { return (zz - z0 + 4) & 3; };
-
-    // corrected velocity of plane zz (z0 - 1 <= zz <= z1) on the tile and its ring
-    auto correct_plane = [&](int zz) {
-        P4<T> *dst = vr[slot(zz)];
-        const int zp = wrap(zz, g.nz);
-        for (int j = tid; j < kZR; j += kZProd) {
-            const int rx = j % kZRX, ry = j / kZRX;
-            if ((rx == 0 || rx == kZRX - 1) && (ry == 0 || ry == kZRY - 1)) continue;  // corners
-            Nbr<D> nb;
-            nb.init(g, wrap(x0 + rx - 1, g.nx), wrap(y0 + ry - 1, g.ny), zp);
-            const EpsGlobal<D, T> ev{eps, &nb};
-            const uint32_t c = nb.self();
-            const Rec<T> own = load_rec<D>(m1, c, ev.at(0, 0, 0));
-            const CellStatic<D, T> cs = cell_static<D, false>(ev, ph, c, own.e);
-            T v[3];
-            corrected_velocity<D, T, false>(m1, ev, eps, nullptr, g, nb, own, cs, v);
-            dst[j] = pack(own.r, v[0], v[1], v[2]);
-        }
-    };
+    auto vslot = [&](int zz) { return (zz - z0 + 4) & 3; };
+    auto sslot = [&](int zz) { return (zz - z0 + 8) & 3; };
     auto rec_at = [](const P4<T> &q, T e) {
         Rec<T> o;
         o.r = q.x;
@@ -1529,20 +1552,107 @@ __global__ __launch_bounds__(kZThreads) void k_collide_vc(T *__restrict__ f,
         return o;
     };
 
+    // staging of plane zz (z0 - 2 <= zz <= z1 + 1): loads into registers, then LDS stores, so
+    // that the loads of the next plane are in flight while the current one is corrected
+    constexpr int kSt = (kZS + kZProd - 1) / kZProd;
+    P4<T> sr[kSt];
+    T se[kSt];
+    auto stage_load = [&](int zz) {
+        const int zp = wrap(zz, g.nz);
+#pragma unroll
+        for (int k = 0; k < kSt; ++k) {
+            const int e = tid + k * kZProd;
+            if (e < kZS) {
+                const int sx = e % kZSX, sy = e / kZSX;
+                const uint32_t c = (uint32_t)wrap(x0 - 2 + sx, g.nx) +
+                                   (uint32_t)g.nx * ((uint32_t)wrap(y0 - 2 + sy, g.ny) +
+                                                     (uint32_t)g.ny * (uint32_t)zp);
+                sr[k] = ld(m1, c);
+                se[k] = ld(eps, c);
+            }
+        }
+    };
+    auto stage_store = [&](int zz) {
+        const int sl = sslot(zz);
+#pragma unroll
+        for (int k = 0; k < kSt; ++k) {
+            const int e = tid + k * kZProd;
+            if (e < kZS) {
+                rs[sl][e] = sr[k];
+                es[sl][e] = se[k];
+            }
+        }
+    };
+    // corrected velocity of plane zz (z0 - 1 <= zz <= z1) on the tile and its ring, from the
+    // staged planes zz - 1, zz, zz + 1
+    auto correct_plane = [&](int zz) {
+        P4<T> *dst = vr[vslot(zz)];
+        const P4<T> *rm = rs[sslot(zz - 1)], *rc = rs[sslot(zz)], *rp = rs[sslot(zz + 1)];
+        for (int j = tid; j < kZR; j += kZProd) {
+            const int rx = j % kZRX, ry = j / kZRX;
+            if ((rx == 0 || rx == kZRX - 1) && (ry == 0 || ry == kZRY - 1)) continue;  // corners
+            const int q = (ry + 1) * kZSX + rx + 1;  // the cell in the staged region
+            const EpsRing<T> ev{{es[sslot(zz - 1)] + q, es[sslot(zz)] + q, es[sslot(zz + 1)] + q},
+                                kZSX};
+            const Rec<T> own = rec_at(rc[q], ev.at(0, 0, 0));
+            const CellStatic<D, T> cs = cell_static<D, false>(ev, ph, 0u, own.e);
+            const bool flat = porosity_flat<D, T>(cs);
+            Rec<T> rec[3][2];
+            bool fl[3][2];
+            if (!flat) {
+                rec[0][0] = rec_at(rc[q - 1], ev.at(-1, 0, 0));
+                rec[0][1] = rec_at(rc[q + 1], ev.at(1, 0, 0));
+                rec[1][0] = rec_at(rc[q - kZSX], ev.at(0, -1, 0));
+                rec[1][1] = rec_at(rc[q + kZSX], ev.at(0, 1, 0));
+                rec[2][0] = rec_at(rm[q], ev.at(0, 0, -1));
+                rec[2][1] = rec_at(rp[q], ev.at(0, 0, 1));
+#pragma unroll
+                for (int a = 0; a < 3; ++a) fl[a][0] = fl[a][1] = true;
+            }
+            T v[3];
+            const Nbr<D> none{};
+            velocity_from_stencil<D, T, false>(nullptr, nullptr, nullptr, g, none, own, rec, fl,
+                                               cs, flat, v);
+            dst[j] = pack(own.r, v[0], v[1], v[2]);
+        }
+    };
+
+    // prologue: planes z0 - 2 .. z0 + 1 staged, corrections of z0 - 1 and z0, then z0 + 2
+    // staged and z0 + 1 corrected while z0 + 3 is loaded
     if (producer) {
+        for (int zz = z0 - 2; zz <= z0 + 1; ++zz) {
+            stage_load(zz);
+            stage_store(zz);
+        }
+    }
+    __syncthreads();
+    if (producer) {
+        stage_load(z0 + 2);
         correct_plane(z0 - 1);
         correct_plane(z0);
+    }
+    __syncthreads();
+    if (producer) stage_store(z0 + 2);
+    __syncthreads();
+    if (producer) {
+        stage_load(z0 + 3);
         correct_plane(z0 + 1);
+        stage_store(z0 + 3);
     }
     __syncthreads();
     const int lx = tid & 63, ly = tid >> 6;
     const int j = (ly + 1) * kZRX + lx + 1;
     for (int zz = z0; zz < z1; ++zz) {
         if (producer) {
-            // the plane after next, while the consumers collide this one
-            if (zz + 2 <= z1) correct_plane(zz + 2);
+            // the plane after next from the staged planes zz + 1 .. zz + 3, while plane zz + 4
+            // is loaded into the slot of plane zz (which no correction reads any more)
+            if (zz + 2 <= z1) {
+                if (zz + 4 <= z1 + 1) stage_load(zz + 4);
+                correct_plane(zz + 2);
+                if (zz + 4 <= z1 + 1) stage_store(zz + 4);
+            }
         } else {
-            const P4<T> *vm = vr[slot(zz - 1)], *vc = vr[slot(zz)], *vp = vr[slot(zz + 1)];
+            const P4<T> *vm = vr[vslot(zz - 1)], *vc = vr[vslot(zz)], *vp = vr[vslot(zz + 1)];
             Nbr<D> nb;
             nb.init(g, x0 + lx, y0 + ly, zz);
             const EpsGlobal<D, T> ev{eps, &nb};

@@ -169,13 +169,13 @@ inline lbm::Grid grid_of(const lbm_solver *h) { return lbm::Grid{h->nx, h->ny, h
 
 inline dim3 flat_grid(int64_t total) { return dim3((unsigned)((total + 255) / 256)); }
 
-// Tiles of the fused correction-collision pass: 64 x 8 cells (nx % 64 == 0, ny % 8 == 0),
+// Tiles of the fused correction-collision pass: 64 x ty cells (nx % 64 == 0, ny % ty == 0),
 // chunks of 32 z-planes, the eight XCDs taking contiguous ranges of the x-fastest, then y, then
 // chunk order (neighbouring tiles in y share their ring rows in the XCD's L2).
-inline lbm::ZTiling make_ztiling(int nx, int ny, int nz) {
+inline lbm::ZTiling make_ztiling(int nx, int ny, int nz, int ty) {
     lbm::ZTiling z{};
-    z.ntx = nx / lbm::kZX;
-    z.nty = ny / lbm::kZY;
+    z.ntx = nx / 64;
+    z.nty = ny / ty;
     z.zc = std::min(32, nz);
     z.nch = (nz + z.zc - 1) / z.zc;
     z.per = (uint32_t)(((int64_t)z.ntx * z.nty * z.nch + 7) / 8);
