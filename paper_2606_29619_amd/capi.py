@@ -46,7 +46,7 @@ LBM_SCHEME_TWO_PASS = 0
 LBM_SCHEME_LAGGED = 1
 LBM_TILES_AUTO = 0
 LBM_TILES_RECTANGULAR = 1
-LBM_PASSES_AUTO = 0          # velocity correction inside the collision pass for FP32 runs
+LBM_PASSES_AUTO = 0          # velocity correction inside the collision pass for large runs
 LBM_PASSES_SEPARATE = 1
 LBM_PASSES_FUSED = 2           # fused wherever the kernel supports the run (FP32 and FP64)
 LBM_DTYPE_F64 = 0

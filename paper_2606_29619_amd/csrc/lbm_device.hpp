@@ -1478,9 +1478,13 @@ void k_collide(P *__restrict__ f, const P4<T> *__restrict__ m2, const T *__restr
 // waves collide the current plane from the ring; one barrier per plane.  The corrected
 // velocities never go through HBM (the separate pass writes them and the collision reads them
 // back, 32 B per cell), at the price of correcting the ring cells (1.27x) and the chunk's end
-// planes again (256^3 box, FP32: 64 x 4 tiles with four and four waves 1.045 ms, 64 x 8 tiles
-// 1.012 ms, against 0.225 + 0.833 ms for the separate passes; fewer correcting waves were
-// slower, 1.22 and 1.38 ms with three and two).
+// planes again.  The correcting waves read their records and porosity from planes staged in
+// LDS (loaded once per plane, coalesced, two planes ahead), and the colliding waves read their
+// porosity there too.  256^3 box, FP32, per step: the separate passes 0.225 + 0.833 ms; 64 x 4
+// tiles with four correcting and four colliding waves 1.045 ms (with three or two correcting
+// waves 1.22 and 1.38 ms); 64 x 8 tiles 1.012 ms; staged correction inputs 0.959 ms; staged
+// collision porosity 0.906 ms (chunks of 128 planes).  Loading the next plane's first pair
+// group before the barrier changed nothing (0.906 / 0.907 ms).
 // With the two kinds of work in different waves, the correction's arithmetic and cached
 // gathers run beside the collision's HBM streams instead of between them.  Every expression
 // is the separate passes' own, so the results are bitwise the same.
@@ -1524,10 +1528,11 @@ __global__ __launch_bounds__(ZCfg<T>::kThreads) void k_collide_vc(T *__restrict_
     constexpr int kZSX = C::kSX, kZS = C::kS, kZProd = C::kProd;
     // (rho, v) of four consecutive planes on the tile and its ring: slot of plane z (z - z0 + 4) & 3
     __shared__ P4<T> vr[4][kZR];
-    // (rho, v^(1)) records and porosity of four consecutive planes on the tile and two rings
-    // (kZSX x kZSY cells), the correcting waves' inputs: slot of plane z (z - z0 + 8) & 3
+    // (rho, v^(1)) records of four consecutive planes on the tile and two rings (kZSX x kZSY
+    // cells), the correcting waves' inputs: slot of plane z (z - z0 + 8) & 3; porosity of six
+    // (the colliding waves read the planes z - 1 .. z + 1 from it too): slot (z - z0 + 12) % 6
     __shared__ P4<T> rs[4][kZS];
-    __shared__ T es[4][kZS];
+    __shared__ T es[6][kZS];
     const uint32_t t = (blockIdx.x & 7u) * zt.per + (blockIdx.x >> 3);
     if (t >= (uint32_t)zt.ntx * (uint32_t)zt.nty * (uint32_t)zt.nch) return;  // whole workgroup
     const int x0 = (int)(t % (uint32_t)zt.ntx) * kZX;
@@ -1542,6 +1547,7 @@ __global__ __launch_bounds__(ZCfg<T>::kThreads) void k_collide_vc(T *__restrict_
     auto wrap = [](int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); };
     auto vslot = [&](int zz) { return (zz - z0 + 4) & 3; };
     auto sslot = [&](int zz) { return (zz - z0 + 8) & 3; };
+    auto eslot = [&](int zz) { return (zz - z0 + 12) % 6; };
     auto rec_at = [](const P4<T> &q, T e) {
         Rec<T> o;
         o.r = q.x;
@@ -1573,13 +1579,13 @@ __global__ __launch_bounds__(ZCfg<T>::kThreads) void k_collide_vc(T *__restrict_
         }
     };
     auto stage_store = [&](int zz) {
-        const int sl = sslot(zz);
+        const int sl = sslot(zz), el = eslot(zz);
 #pragma unroll
         for (int k = 0; k < kSt; ++k) {
             const int e = tid + k * kZProd;
             if (e < kZS) {
                 rs[sl][e] = sr[k];
-                es[sl][e] = se[k];
+                es[el][e] = se[k];
             }
         }
     };
@@ -1592,7 +1598,7 @@ __global__ __launch_bounds__(ZCfg<T>::kThreads) void k_collide_vc(T *__restrict_
             const int rx = j % kZRX, ry = j / kZRX;
             if ((rx == 0 || rx == kZRX - 1) && (ry == 0 || ry == kZRY - 1)) continue;  // corners
             const int q = (ry + 1) * kZSX + rx + 1;  // the cell in the staged region
-            const EpsRing<T> ev{{es[sslot(zz - 1)] + q, es[sslot(zz)] + q, es[sslot(zz + 1)] + q},
+            const EpsRing<T> ev{{es[eslot(zz - 1)] + q, es[eslot(zz)] + q, es[eslot(zz + 1)] + q},
                                 kZSX};
             const Rec<T> own = rec_at(rc[q], ev.at(0, 0, 0));
             const CellStatic<D, T> cs = cell_static<D, false>(ev, ph, 0u, own.e);
@@ -1655,7 +1661,9 @@ __global__ __launch_bounds__(ZCfg<T>::kThreads) void k_collide_vc(T *__restrict_
             const P4<T> *vm = vr[vslot(zz - 1)], *vc = vr[vslot(zz)], *vp = vr[vslot(zz + 1)];
             Nbr<D> nb;
             nb.init(g, x0 + lx, y0 + ly, zz);
-            const EpsGlobal<D, T> ev{eps, &nb};
+            const int qc = (ly + 2) * kZSX + lx + 2;  // the cell in the staged region
+            const EpsRing<T> ev{{es[eslot(zz - 1)] + qc, es[eslot(zz)] + qc, es[eslot(zz + 1)] + qc},
+                                kZSX};
             const uint32_t n = nb.self();
             const Rec<T> own = rec_at(vc[j], ev.at(0, 0, 0));
             const CellStatic<D, T> cs = cell_static<D, false>(ev, ph, n, own.e);
