@@ -223,9 +223,9 @@ typedef struct lbm_params {
     int tiles;
     /* Kernels of a two-pass step.  LBM_PASSES_FUSED corrects the velocity inside the
      * collision pass (two kernels per step, the corrected velocities shared through LDS)
-     * where the run allows it: D3Q27, FP32 or FP64 storage, no solid cells, no wet-node
-     * boundaries, no Picard iterations, no analytic porosity derivatives, nx a multiple of 64
-     * and ny of 8 (FP32) or 4 (FP64); LBM_PASSES_AUTO does so where, in addition, the grid is
+     * where the run allows it: D3Q27, no solid cells, no wet-node boundaries, no Picard
+     * iterations, no analytic porosity derivatives, nx a multiple of 64 and ny of 8 (4 for FP64
+     * storage); LBM_PASSES_AUTO does so where, in addition, the grid is
      * large enough for z-chunks of at least 16 planes (about 2^21 cells); every other run, and
      * LBM_PASSES_SEPARATE, uses the separate correction pass.  All give bitwise the same
      * results. */

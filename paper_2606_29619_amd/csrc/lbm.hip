@@ -442,12 +442,12 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
     h->picard_omega = p->picard_omega;
     h->analytic = p->grad_eps != nullptr;
     {
-        // the fused correction-collision kernel: D3Q27, populations in the arithmetic type, no
-        // solids, wet nodes, Picard iterations or analytic derivatives, whole tiles; AUTO takes
+        // the fused correction-collision kernel: D3Q27, any storage, no solids, wet nodes,
+        // Picard iterations or analytic derivatives, whole tiles; AUTO takes
         // it where the chunks are at least 16 planes long (shorter ones correct and stage too
         // many end planes again)
         const int ty = p->storage == LBM_F64 ? lbm::ZCfg<double>::kY : lbm::ZCfg<float>::kY;
-        const bool able = (p->storage == LBM_F32 || p->storage == LBM_F64) && D == 3 && !solids &&
+        const bool able = D == 3 && !solids &&
                           nb == 0 && p->picard_iters == 0 && !h->analytic &&
                           p->scheme == LBM_SCHEME_TWO_PASS && p->nx % 64 == 0 && p->ny % ty == 0;
         if (able) h->ztiles = make_ztiling(p->nx, p->ny, p->nz, ty);

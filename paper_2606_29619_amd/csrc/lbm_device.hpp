@@ -1468,7 +1468,8 @@ void k_collide(P *__restrict__ f, const P4<T> *__restrict__ m2, const T *__restr
 
 // ------------------------------------------------------------------------------------------
 // Two-pass step with the velocity correction fused into the collision pass (D3Q27, no solids,
-// differenced porosity derivatives, populations stored in the arithmetic type).  The collision
+// differenced porosity derivatives; populations in the arithmetic type or shifted 16-bit, whose
+// decode reads the porosity of each population's source cell from the staged planes).  The collision
 // of a cell reads the corrected velocity of the cell and its six face neighbours, and the
 // correction of a cell reads the (rho, v^(1)) records of its own six face neighbours.  A
 // workgroup of 1024 threads owns a 64 x 8 tile of cells and marches it through a chunk of
@@ -1515,8 +1516,8 @@ struct EpsRing {
     }
 };
 
-template <typename T, int PH>
-__global__ __launch_bounds__(ZCfg<T>::kThreads) void k_collide_vc(T *__restrict__ f,
+template <typename T, typename PS, int PH>
+__global__ __launch_bounds__(ZCfg<T>::kThreads) void k_collide_vc(PS *__restrict__ f,
                                                           const P4<T> *__restrict__ m1,
                                                           const T *__restrict__ eps,
                                                           const T *__restrict__ muD,
@@ -1684,8 +1685,8 @@ __global__ __launch_bounds__(ZCfg<T>::kThreads) void k_collide_vc(T *__restrict_
             const T er = own.e * own.r;
             peq.init(er, xi, P);
             pst.init(er, xs, Ps);
-            collide_populations<D, T, T, false, PH>(f, nullptr, g, ph, ev, nb, cs.vs.beta, peq,
-                                                    pst);
+            collide_populations<D, T, PS, false, PH>(f, nullptr, g, ph, ev, nb, cs.vs.beta, peq,
+                                                     pst);
         }
         __syncthreads();
     }

@@ -56,9 +56,9 @@ void launch_collide(const lbm_solver *h, size_t m2) {
 
 template <int D, typename T, typename P, bool S, int PH>
 void launch_collide_vc(const lbm_solver *h, size_t m1) {
-    if constexpr (D == 3 && std::is_same_v<T, P> && !S)
-        hipLaunchKernelGGL((lbm::k_collide_vc<T, PH>), dim3(8 * h->ztiles.per), dim3(lbm::ZCfg<T>::kThreads), 0,
-                           h->stream, ws_ptr<T>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m1),
+    if constexpr (D == 3 && !S)
+        hipLaunchKernelGGL((lbm::k_collide_vc<T, P, PH>), dim3(8 * h->ztiles.per), dim3(lbm::ZCfg<T>::kThreads), 0,
+                           h->stream, ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m1),
                            ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
                            ws_ptr<const T>(h, h->L.muF), grid_of(h), h->ztiles, phys_of<T>(h));
 }
@@ -245,7 +245,7 @@ struct CollidePass {
     template <int D, typename T, typename P, bool S, int PH, bool AD>
     void operator()() { launch_collide<D, T, P, S, PH, AD>(h, m2); }
 };
-struct CollideVcPass {  // only dispatched for runs with fused_vc (D3Q27, T = P, no solids)
+struct CollideVcPass {  // only dispatched for runs with fused_vc (D3Q27, no solids)
     static constexpr bool kDerivs = false;
     const lbm_solver *h;
     size_t m1;

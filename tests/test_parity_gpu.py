@@ -653,13 +653,17 @@ def test_fused_correction_pass_fp64(shape, opts):
     assert max(errs.values()) <= FP64_TOL, errs
 
 
-def test_fused_and_separate_passes_are_bitwise_equal():
-    """FP32 storage: the fused correction-collision kernel and the separate correction pass
-    evaluate the same expressions, so 7 steps (both AA phases) give identical populations and
-    moments (z-chunks of 8 planes, 3 of them in the 20-plane box)."""
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_fused_and_separate_passes_are_bitwise_equal(storage):
+    """FP32 and shifted 16-bit storage (porous shift): the fused correction-collision kernel
+    and the separate correction pass evaluate the same expressions, so 7 steps (both AA phases)
+    give identical populations and moments (z-chunks of 8 planes, 3 of them in the 20-plane
+    box)."""
     w = workloads.random_porosity_3d(shape=(20, 16, 128), seed=3, ell=4.0)
-    a = capi.Solver.from_workload(w, storage=capi.LBM_F32, passes=capi.LBM_PASSES_FUSED)
-    b = capi.Solver.from_workload(w, storage=capi.LBM_F32, passes=capi.LBM_PASSES_SEPARATE)
+    st = {"f32": capi.LBM_F32, "f16": capi.LBM_F16_SHIFTED, "bf16": capi.LBM_BF16_SHIFTED}[storage]
+    kw = dict(storage=st, shift=capi.LBM_SHIFT_POROUS)
+    a = capi.Solver.from_workload(w, passes=capi.LBM_PASSES_FUSED, **kw)
+    b = capi.Solver.from_workload(w, passes=capi.LBM_PASSES_SEPARATE, **kw)
     ta, tb = a.step_timed(7), b.step_timed(7)
     assert ta[1] == 0.0 and tb[1] > 0.0, (ta, tb)
     assert torch.equal(a.populations(torch.float64), b.populations(torch.float64))
