@@ -446,11 +446,17 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
         // Picard iterations or analytic derivatives, whole tiles; AUTO takes
         // it where the chunks are at least 16 planes long (shorter ones correct and stage too
         // many end planes again)
-        const int ty = p->storage == LBM_F64 ? lbm::ZCfg<double>::kY : lbm::ZCfg<float>::kY;
+        const bool half = p->storage == LBM_F16_SHIFTED || p->storage == LBM_BF16_SHIFTED;
+        const int tx = p->storage == LBM_F64 ? lbm::ZCfg<double>::kX
+                       : half               ? lbm::ZCfg<float, _Float16>::kX
+                                            : lbm::ZCfg<float>::kX;
+        const int ty = p->storage == LBM_F64 ? lbm::ZCfg<double>::kY
+                       : half               ? lbm::ZCfg<float, _Float16>::kY
+                                            : lbm::ZCfg<float>::kY;
         const bool able = D == 3 && !solids &&
                           nb == 0 && p->picard_iters == 0 && !h->analytic &&
-                          p->scheme == LBM_SCHEME_TWO_PASS && p->nx % 64 == 0 && p->ny % ty == 0;
-        if (able) h->ztiles = make_ztiling(p->nx, p->ny, p->nz, ty);
+                          p->scheme == LBM_SCHEME_TWO_PASS && p->nx % tx == 0 && p->ny % ty == 0;
+        if (able) h->ztiles = make_ztiling(p->nx, p->ny, p->nz, tx, ty);
         h->fused_vc = able && (p->passes == LBM_PASSES_FUSED ||
                                (p->passes == LBM_PASSES_AUTO && h->ztiles.zc >= 16));
     }

@@ -1494,13 +1494,17 @@ struct ZTiling {
     int zc;             // planes per chunk
     uint32_t per;       // workgroups per XCD (padded)
 };
-// Shape of a fused workgroup for arithmetic type T: a kX x kY tile (kX * kY collision
-// threads, as many correcting threads), the ring of corrected velocities (kRX x kRY) and the
-// staged region of the correcting waves (the tile and two rings, kSX x kSY).  FP64 takes
-// 64 x 4 tiles: its LDS rings would not fit 160 KB at 64 x 8.
-template <typename T>
+// Shape of a fused workgroup for arithmetic type T and population storage P: a kX x kY tile
+// (kX * kY collision threads, as many correcting threads), the ring of corrected velocities
+// (kRX x kRY) and the staged region of the correcting waves (the tile and two rings,
+// kSX x kSY).  FP32 takes 128 x 4 tiles: fewer tile edges in x, across which the swapped
+// phase's x-shifted accesses reach lines that another workgroup loads and stores (256^3 box:
+// 0.886 ms against 0.901 for 64 x 8, which corrects fewer ring cells); the 16-bit forms 64 x 8
+// (0.747 ms against 0.780); FP64 64 x 4, as its LDS rings would not fit 160 KB otherwise.
+template <typename T, typename P = T>
 struct ZCfg {
-    static constexpr int kX = 64, kY = sizeof(T) == 8 ? 4 : 8;
+    static constexpr bool kF64 = sizeof(T) == 8, kHalf = sizeof(P) == 2;
+    static constexpr int kX = kF64 || kHalf ? 64 : 128, kY = kF64 ? 4 : (kHalf ? 8 : 4);
     static constexpr int kRX = kX + 2, kRY = kY + 2, kR = kRX * kRY;
     static constexpr int kSX = kX + 4, kSY = kY + 4, kS = kSX * kSY;
     static constexpr int kProd = kX * kY, kThreads = 2 * kX * kY;
@@ -1517,14 +1521,14 @@ struct EpsRing {
 };
 
 template <typename T, typename PS, int PH>
-__global__ __launch_bounds__(ZCfg<T>::kThreads) void k_collide_vc(PS *__restrict__ f,
+__global__ __launch_bounds__((ZCfg<T, PS>::kThreads)) void k_collide_vc(PS *__restrict__ f,
                                                           const P4<T> *__restrict__ m1,
                                                           const T *__restrict__ eps,
                                                           const T *__restrict__ muD,
                                                           const T *__restrict__ muF, Grid g,
                                                           ZTiling zt, Phys<T> ph) {
     constexpr int D = 3;
-    using C = ZCfg<T>;
+    using C = ZCfg<T, PS>;
     constexpr int kZX = C::kX, kZY = C::kY, kZRX = C::kRX, kZRY = C::kRY, kZR = C::kR;
     constexpr int kZSX = C::kSX, kZS = C::kS, kZProd = C::kProd;
     // (rho, v) of four consecutive planes on the tile and its ring: slot of plane z (z - z0 + 4) & 3
@@ -1647,7 +1651,7 @@ __global__ __launch_bounds__(ZCfg<T>::kThreads) void k_collide_vc(PS *__restrict
         stage_store(z0 + 3);
     }
     __syncthreads();
-    const int lx = tid & 63, ly = tid >> 6;
+    const int lx = tid % kZX, ly = tid / kZX;
     const int j = (ly + 1) * kZRX + lx + 1;
     for (int zz = z0; zz < z1; ++zz) {
         if (producer) {

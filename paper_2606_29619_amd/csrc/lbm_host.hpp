@@ -169,16 +169,16 @@ inline lbm::Grid grid_of(const lbm_solver *h) { return lbm::Grid{h->nx, h->ny, h
 
 inline dim3 flat_grid(int64_t total) { return dim3((unsigned)((total + 255) / 256)); }
 
-// Tiles of the fused correction-collision pass: 64 x ty cells (nx % 64 == 0, ny % ty == 0),
+// Tiles of the fused correction-collision pass: tx x ty cells (nx % tx == 0, ny % ty == 0),
 // marched through chunks of zc z-planes, the eight XCDs taking contiguous ranges of the
 // x-fastest, then y, then chunk order (neighbouring tiles in y share their ring rows in the
 // XCD's L2).  One workgroup fills a CU (1024 threads in FP32, and LDS rings of 114 KB in FP32,
 // 146 KB in FP64), so the chunks are as long as 256 workgroups allow, between 8 and 128 planes:
 // long chunks correct and stage fewer end planes (256^3 box, FP32: chunks of 32, 64 and 128
 // planes 0.924, 0.936 and 0.906 ms).
-inline lbm::ZTiling make_ztiling(int nx, int ny, int nz, int ty) {
+inline lbm::ZTiling make_ztiling(int nx, int ny, int nz, int tx, int ty) {
     lbm::ZTiling z{};
-    z.ntx = nx / 64;
+    z.ntx = nx / tx;
     z.nty = ny / ty;
     const int64_t cols = (int64_t)z.ntx * z.nty;
     z.zc = (int)std::min<int64_t>(nz, std::max<int64_t>(8, std::min<int64_t>(128, cols * nz / 256)));

@@ -57,7 +57,7 @@ void launch_collide(const lbm_solver *h, size_t m2) {
 template <int D, typename T, typename P, bool S, int PH>
 void launch_collide_vc(const lbm_solver *h, size_t m1) {
     if constexpr (D == 3 && !S)
-        hipLaunchKernelGGL((lbm::k_collide_vc<T, P, PH>), dim3(8 * h->ztiles.per), dim3(lbm::ZCfg<T>::kThreads), 0,
+        hipLaunchKernelGGL((lbm::k_collide_vc<T, P, PH>), dim3(8 * h->ztiles.per), dim3(lbm::ZCfg<T, P>::kThreads), 0,
                            h->stream, ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m1),
                            ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
                            ws_ptr<const T>(h, h->L.muF), grid_of(h), h->ztiles, phys_of<T>(h));
