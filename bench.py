@@ -307,7 +307,7 @@ def main():
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary rows (other stored forms, schemes, the duct)")
     ap.add_argument("--secondary-steps", type=int, default=None,
-                    help="timed steps of each secondary row (default: --steps, at most 200)")
+                    help="timed steps of each secondary row (default: --steps within 100..200)")
     ap.add_argument("--serve-requests", type=int, default=12)
     ap.add_argument("--serve-max-steps", type=int, default=30000)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -362,8 +362,10 @@ def main():
         line["copy_probe_bytes"] = {"read": nb, "write": nb}
         del a, b
     if not args.no_secondary:
-        steps2 = args.secondary_steps or min(args.steps, 200)
-        warm2 = min(args.warmup, 20)
+        # at least 100 timed steps after 20 warm-up steps: a row of 20 steps reads several per
+        # cent low (clocks and caches still settling after the row's creation)
+        steps2 = args.secondary_steps or max(100, min(args.steps, 200))
+        warm2 = 20
         rows, cache = [], {}
         for kind, storage, shift, scheme in SECONDARY:
             if (kind, storage, scheme) == (args.workload, args.storage, args.scheme):
