@@ -94,8 +94,11 @@ extern "C" {
 #define LBM_SCHEME_LAGGED 1
 
 /*
- * Wet-node boundaries (Sec. 3.4), two-pass scheme.  A boundary node is a fluid cell whose
- * outward neighbour along each of its outward normals is solid (mask = 1).
+ * Wet-node boundaries (Sec. 3.4).  A boundary node is a fluid cell whose outward neighbour
+ * along each of its outward normals is solid (mask = 1).  Under LBM_SCHEME_LAGGED the boundary
+ * density and velocity come from the current step's moments, while the acceleration of the
+ * rebuild, like the bulk correction and forcing, takes its neighbours' values from the
+ * previous step; such a step runs as separate passes.
  *   Face nodes (one normal): the inward neighbour must be a bulk fluid cell.
  *   Edge and corner nodes (two or three normals, Sec. 3.4.1): velocity nodes only; the two
  *     cells x_b + d and x_b + 2d along the inward diagonal d = -(sum of the normals) must be

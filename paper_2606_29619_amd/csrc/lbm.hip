@@ -48,12 +48,16 @@ void boundary_records(lbm_solver *h, size_t m1) {
 
 // Moments of the current state into internal packed records; returns the offset of the
 // (rho, v) records.  Under the lagged scheme with a valid history the correction takes its
-// neighbour values from the previous step's records, which stay untouched.
+// neighbour values from the previous step's records, which stay untouched; wet-node
+// boundaries take their outflow copies and records as in the two-pass scheme.
 size_t current_moments(lbm_solver *h) {
     if (h->scheme == LBM_SCHEME_LAGGED && h->have_prev) {
         const int nx = h->cur ^ 1;
+        if (h->bc_outflow) dispatch(h, BcOutflowPass{h});
         dispatch(h, MomentsPass{h, h->L.m1[nx]});
+        boundary_records(h, h->L.m1[nx]);
         dispatch(h, VcorrectPass{h, h->L.m1[nx], h->L.m1[h->cur], h->L.m2[nx]});
+        if (h->bc_vp) dispatch(h, BcFixPass{h, h->L.m1[nx], h->L.m2[nx]});
         return h->L.m2[nx];
     }
     const int c = h->cur;
@@ -69,10 +73,26 @@ hipError_t one_step(lbm_solver *h, hipEvent_t *ev) {
     hipError_t e = hipSuccess;
     if (h->scheme == LBM_SCHEME_LAGGED && h->have_prev) {
         const int nx = h->cur ^ 1;
-        if (ev) e = hipEventRecord(ev[0], h->stream);
-        if (ev && e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
-        dispatch(h, FusedPass{h, h->cur, nx});
-        if (ev && e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
+        if (h->nb) {
+            // wet-node boundaries: the lagged step as separate passes around the boundary
+            // kernels; the correction, the boundary rebuild and the collision take their
+            // neighbours' records from the previous step (m1 / m2 of pair cur)
+            if (h->bc_outflow) dispatch(h, BcOutflowPass{h});
+            dispatch(h, MomentsPass{h, h->L.m1[nx]});
+            boundary_records(h, h->L.m1[nx]);
+            if (ev) e = hipEventRecord(ev[0], h->stream);
+            dispatch(h, VcorrectPass{h, h->L.m1[nx], h->L.m1[h->cur], h->L.m2[nx]});
+            if (h->bc_vp) dispatch(h, BcFixPass{h, h->L.m1[nx], h->L.m2[nx]});
+            if (ev && e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
+            if (h->bc_vp) dispatch(h, BcRebuildPass{h, h->L.m2[nx], h->L.m2[h->cur]});
+            dispatch(h, CollidePass{h, h->L.m2[nx], h->L.m2[h->cur]});
+            if (ev && e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
+        } else {
+            if (ev) e = hipEventRecord(ev[0], h->stream);
+            if (ev && e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
+            dispatch(h, FusedPass{h, h->cur, nx});
+            if (ev && e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
+        }
         h->cur = nx;
     } else {
         const int c = h->cur;
@@ -98,8 +118,8 @@ hipError_t one_step(lbm_solver *h, hipEvent_t *ev) {
         dispatch(h, VcorrectPass{h, h->L.m1[c], h->L.m1[c], h->L.m2[c]});
         const size_t mv = velocity_stage(h, h->L.m1[c], h->L.m2[c]);
         if (ev && e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
-        if (h->bc_vp) dispatch(h, BcRebuildPass{h, mv});
-        dispatch(h, CollidePass{h, mv});
+        if (h->bc_vp) dispatch(h, BcRebuildPass{h, mv, mv});
+        dispatch(h, CollidePass{h, mv, mv});
         if (ev && e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
         h->have_prev = true;  // this step's records are the next step's history
     }
@@ -200,8 +220,6 @@ int boundary_nodes(const lbm_params *p, int D, int64_t N, uint32_t *count, bool 
     *count = 0;
     *outflow = *vp = *visc = false;
     if (!p->bc_type) return LBM_OK;
-    if (p->scheme != LBM_SCHEME_TWO_PASS)
-        return fail(LBM_ERR_UNSUPPORTED, "wet-node boundaries need LBM_SCHEME_TWO_PASS");
     if (p->bc_scheme < LBM_BC_EQUILIBRIUM || p->bc_scheme > LBM_BC_TMS)
         return fail(LBM_ERR_INVALID_ARG, "bad bc_scheme %d", p->bc_scheme);
     if (p->bc_rho_rule != LBM_BC_RHO_CONTINUITY && p->bc_rho_rule != LBM_BC_RHO_BOUNCE_BACK)

@@ -304,9 +304,11 @@ __device__ __forceinline__ void eq_at(T e, T rho, const T w[3], T RT, ProductFor
     pf.init(e * rho, xi, P);
 }
 
-// Acceleration of cell nb from the (rho, v) records.
+// Acceleration of cell nb from the (rho, v) records: its own from m2, its stencil neighbours'
+// from nbr (the same buffer, or the previous step's in a lagged step).
 template <int D, typename T, bool SOLIDS, bool AD>
 __device__ __forceinline__ void node_accel(const P4<T> *__restrict__ m2,
+                                           const P4<T> *__restrict__ nbr,
                                            const T *__restrict__ eps, const T *__restrict__ muD,
                                            const T *__restrict__ muF,
                                            const uint8_t *__restrict__ mask, const Grid &g,
@@ -318,8 +320,8 @@ __device__ __forceinline__ void node_accel(const P4<T> *__restrict__ m2,
     vs = cs.vs;
     Rec<T> rec[3][2];
     bool fl[3][2];
-    load_stencil<D, T, SOLIDS>(m2, ev, mask, g, nb, rec, fl);
-    accel_of<D, T, SOLIDS>(m2, eps, muD, muF, mask, g, ph, nb, own, rec, fl, cs.ge, cs.H, cs.vs,
+    load_stencil<D, T, SOLIDS>(nbr, ev, mask, g, nb, rec, fl);
+    accel_of<D, T, SOLIDS>(nbr, eps, muD, muF, mask, g, ph, nb, own, rec, fl, cs.ge, cs.H, cs.vs,
                            acc);
 }
 
@@ -332,6 +334,7 @@ __device__ __forceinline__ void node_accel(const P4<T> *__restrict__ m2,
 template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
 __global__ __launch_bounds__(256) void k_bc_rebuild(P *__restrict__ f,
                                                     const P4<T> *__restrict__ m2,
+                                                    const P4<T> *__restrict__ nbr,
                                                     const T *__restrict__ eps,
                                                     const T *__restrict__ muD,
                                                     const T *__restrict__ muF,
@@ -354,7 +357,7 @@ __global__ __launch_bounds__(256) void k_bc_rebuild(P *__restrict__ f,
     Rec<T> own;
     Visc<T> vs;
     T acc[3];
-    node_accel<D, T, SOLIDS, AD>(m2, eps, muD, muF, mask, g, ph, nb, ev, own, vs, acc);
+    node_accel<D, T, SOLIDS, AD>(m2, nbr, eps, muD, muF, mask, g, ph, nb, ev, own, vs, acc);
     T vstar[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int a = 0; a < D; ++a) vstar[a] = own.w[a] + acc[a];
@@ -374,7 +377,8 @@ __global__ __launch_bounds__(256) void k_bc_rebuild(P *__restrict__ f,
         Rec<T> ownf;
         Visc<T> vsf;
         T accf[3];
-        node_accel<D, T, SOLIDS, AD>(m2, eps, muD, muF, mask, g, ph, nf, evf, ownf, vsf, accf);
+        node_accel<D, T, SOLIDS, AD>(m2, nbr, eps, muD, muF, mask, g, ph, nf, evf, ownf, vsf,
+                                     accf);
         T vfs[3] = {T(0), T(0), T(0)};
 #pragma unroll
         for (int a = 0; a < D; ++a) vfs[a] = ownf.w[a] + accf[a];

@@ -1247,9 +1247,12 @@ __device__ __forceinline__ void collide_populations(P *__restrict__ f,
 }
 
 // Pass two of the two-pass scheme: forcing from the (rho, v) records, collision, streaming.
+// The cell's own record comes from m2 and its stencil neighbours' from nbr: the same buffer in
+// the two-pass scheme, the previous step's records in a lagged step run as separate passes.
 template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
 __device__ __forceinline__ void collide_body(P *__restrict__ f,
                                                  const P4<T> *__restrict__ m2,
+                                                 const P4<T> *__restrict__ nbr,
                                                  const T *__restrict__ eps,
                                                  const T *__restrict__ muD,
                                                  const T *__restrict__ muF,
@@ -1262,7 +1265,7 @@ __device__ __forceinline__ void collide_body(P *__restrict__ f,
     const Rec<T> own = load_rec<D>(m2, n, ev.at(0, 0, 0));
     const CellStatic<D, T> cs = cell_static<D, AD>(ev, ph, n, own.e);
     ProductForm<D, T> peq, pst;
-    cell_equilibria<D, T, SOLIDS>(m2, ev, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
+    cell_equilibria<D, T, SOLIDS>(nbr, ev, eps, muD, muF, mask, g, ph, nb, own, cs, peq, pst);
     collide_populations<D, T, P, SOLIDS, PH>(f, mask, g, ph, ev, nb, cs.vs.beta, peq, pst);
 }
 
@@ -1452,18 +1455,19 @@ struct SolidAwareWaves {
 template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(SolidAwareWaves<D, T, P, SOLIDS, PH>::collide)))
-void k_collide(P *__restrict__ f, const P4<T> *__restrict__ m2, const T *__restrict__ eps,
-               const T *__restrict__ muD, const T *__restrict__ muF,
+void k_collide(P *__restrict__ f, const P4<T> *__restrict__ m2, const P4<T> *__restrict__ nbr,
+               const T *__restrict__ eps, const T *__restrict__ muD, const T *__restrict__ muF,
                const uint8_t *__restrict__ mask, const uint8_t *__restrict__ tsolid, Grid g,
                Tiling tl, Phys<T> ph) {
     if constexpr (SOLIDS) {
         if (tile_free(tsolid)) {
-            collide_body<D, T, P, false, PH, AD>(f, m2, eps, muD, muF, mask, g, tl, ph,
+            collide_body<D, T, P, false, PH, AD>(f, m2, nbr, eps, muD, muF, mask, g, tl, ph,
                                                  blockIdx.x);
             return;
         }
     }
-    collide_body<D, T, P, SOLIDS, PH, AD>(f, m2, eps, muD, muF, mask, g, tl, ph, blockIdx.x);
+    collide_body<D, T, P, SOLIDS, PH, AD>(f, m2, nbr, eps, muD, muF, mask, g, tl, ph,
+                                          blockIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -45,10 +45,11 @@ void launch_vcorrect(const lbm_solver *h, size_t own_src, size_t m1, size_t m2_o
 }
 
 template <int D, typename T, typename P, bool S, int PH, bool AD>
-void launch_collide(const lbm_solver *h, size_t m2) {
+void launch_collide(const lbm_solver *h, size_t m2, size_t nbr) {
     auto ph = phys_of<T>(h);
     hipLaunchKernelGGL((lbm::k_collide<D, T, P, S, PH, AD>), cell_tiles(h), dim3(256), 0, h->stream,
                        ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
+                       ws_ptr<const lbm::P4<T>>(h, nbr),
                        ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
                        tsolid_ptr(h), grid_of(h), h->tiles, ph);
@@ -159,15 +160,16 @@ struct BcFixPass {
                                bnodes_of<T>(h));
     }
 };
-struct BcRebuildPass {
+struct BcRebuildPass {  // own records m2, stencil neighbours' nbr
     static constexpr bool kDerivs = true;
     const lbm_solver *h;
-    size_t m2;
+    size_t m2, nbr;
     template <int D, typename T, typename P, bool S, int PH, bool AD>
     void operator()() {
         if constexpr (S)
             hipLaunchKernelGGL((lbm::k_bc_rebuild<D, T, P, S, PH, AD>), flat_grid(h->nb), dim3(256), 0,
                                h->stream, ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
+                               ws_ptr<const lbm::P4<T>>(h, nbr),
                                ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
                                ws_ptr<const T>(h, h->L.muF), mask_ptr(h), bnodes_of<T>(h),
                                grid_of(h), phys_of<T>(h), h->bc_scheme);
@@ -238,12 +240,12 @@ struct VcorrectPass {
     template <int D, typename T, typename P, bool S, int PH, bool AD>
     void operator()() { launch_vcorrect<D, T, S, AD>(h, own_src, m1, m2_out); }
 };
-struct CollidePass {
+struct CollidePass {  // own records m2, stencil neighbours' nbr (= m2 in the two-pass scheme)
     static constexpr bool kDerivs = true;
     const lbm_solver *h;
-    size_t m2;
+    size_t m2, nbr;
     template <int D, typename T, typename P, bool S, int PH, bool AD>
-    void operator()() { launch_collide<D, T, P, S, PH, AD>(h, m2); }
+    void operator()() { launch_collide<D, T, P, S, PH, AD>(h, m2, nbr); }
 };
 struct CollideVcPass {  // only dispatched for runs with fused_vc (D3Q27, no solids)
     static constexpr bool kDerivs = false;

@@ -25,13 +25,13 @@ def _gpu():
     torch.cuda.synchronize()
 
 
-def _oracle(w):
+def _oracle(w, lagged=0):
     return oracle.Oracle(oracle.OracleConfig(
         D=w.D, eps=w.eps, kappa=w.kappa, cf=w.forch, mask=w.mask, RT=w.RT, nu_f=w.nu_f,
         nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow, eta_eff=w.eta_eff, b=w.b,
         rho0=w.rho0, rho_init=w.rho_init, v_init=w.v_init, bc_type=w.bc_type,
         bc_normal=w.bc_normal, bc_vel=w.bc_velocity, bc_rho=w.bc_density,
-        bc_scheme=w.bc_scheme, bc_density=w.bc_rho_rule))
+        bc_scheme=w.bc_scheme, bc_density=w.bc_rho_rule, lagged=lagged))
 
 
 def _rel(a, b):
@@ -49,9 +49,11 @@ def _errors(s, o):
     return errs
 
 
-def _pair(w, chunks, storage=None):
-    s = capi.Solver.from_workload(w, storage=capi.LBM_F64 if storage is None else storage)
-    o = _oracle(w)
+def _pair(w, chunks, storage=None, lagged=0):
+    s = capi.Solver.from_workload(w, storage=capi.LBM_F64 if storage is None else storage,
+                                  scheme=capi.LBM_SCHEME_LAGGED if lagged else
+                                  capi.LBM_SCHEME_TWO_PASS)
+    o = _oracle(w, lagged)
     for n in chunks:
         s.step(n)
         o.step(n)
@@ -233,3 +235,47 @@ def test_pressure_driven_sphere_duct_matches_oracle():
     print("pressure sphere duct fp32:", errs, flush=True)
     assert errs["f"] < 5e-6 and errs["rho"] < 5e-6, errs
     assert max(errs[f"v{a}"] for a in range(3)) < 1e-3, errs
+
+
+# --------------------------------------------------------------------------------------------
+# Wet-node boundaries under the lagged scheme: the correction, the wall-normal acceleration of
+# the rebuild and the forcing take their neighbours' records from the previous step
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme,rule", [(0, 0), (1, 1), (2, 0)])
+def test_lagged_couette_walls_match_oracle(scheme, rule):
+    """Moving walls with gravity under the lagged scheme, against the oracle's lagged mode."""
+    w = workloads.couette_gravity_2d(H=24, scheme=scheme, rho_rule=rule)
+    s, o = _pair(w, (41, 40), lagged=1)
+    errs = _errors(s, o)
+    print(f"lagged couette scheme {scheme} rule {rule}:", errs, flush=True)
+    assert max(errs.values()) <= FP64_TOL, errs
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_lagged_corners_and_edges_match_oracle(D):
+    """Velocity inlet, pressure outlet, walls with edge and corner nodes and a porosity that
+    varies at every face (the viscous term), lagged scheme, both lattices."""
+    n = (20, 10, 1) if D == 2 else (12, 6, 5)
+    w = _porous(workloads.wet_box(D, n, faces={"x-": "inlet", "x+": "pressure"}, V=0.01,
+                                  nu=0.05, scheme=1 if D == 2 else 2, rho_rule=0))
+    s, o = _pair(w, (21, 20), lagged=1)
+    errs = _errors(s, o)
+    print(f"lagged box D{D}:", errs, flush=True)
+    assert max(errs.values()) <= FP64_TOL, errs
+
+
+def test_lagged_outflow_channel_matches_oracle():
+    """Pressure inlet and zero-gradient outflow on D3Q27 under the lagged scheme, with a
+    population export and import in between (the history restarts with a two-pass step)."""
+    w = workloads.pressure_channel(D=3, L=24, H=8, W=6, drho=2e-3, outflow=True, body=1e-5)
+    w.bc_scheme = 2
+    s, o = _pair(w, (17,), lagged=1)
+    f = s.populations(torch.float64).cpu().numpy()
+    s.set_populations(torch.from_numpy(f).cuda())
+    o.set_populations(f)
+    s.step(14)
+    o.step(14)
+    torch.cuda.synchronize()
+    errs = _errors(s, o)
+    print("lagged outflow channel:", errs, flush=True)
+    assert max(errs.values()) <= FP64_TOL, errs

@@ -256,10 +256,14 @@ def test_boundary_footprint_and_validation():
     (p0, keep0), _ = _bc_params(bc_type=None)
     nb = int((w.bc_type > 0).sum())
     assert capi.lbm_footprint(p) - capi.lbm_footprint(p0) >= nb * (4 + 4 + 32)
-    # lagged scheme: not supported with wet-node boundaries
+    # lagged scheme: accepted with wet-node boundaries, double-buffered records cost more
     p.scheme = capi.LBM_SCHEME_LAGGED
+    assert capi.lbm_footprint(p) > capi.lbm_footprint(p0)
+    # Picard iterations stay two-pass only
+    (p5, keep5), _ = _bc_params(picard_iters=2)
+    p5.scheme = capi.LBM_SCHEME_LAGGED
     with pytest.raises(capi.LbmError) as ei:
-        capi.lbm_footprint(p)
+        capi.lbm_footprint(p5)
     assert ei.value.code == capi.LBM_ERR_UNSUPPORTED
     # a boundary node whose outward neighbour is fluid
     bct = w.bc_type.copy()
