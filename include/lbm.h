@@ -421,10 +421,10 @@ LBM_API int lbm_server_create(void *dev_pool, size_t pool_bytes, int64_t check_e
  * and the 16-bit forms stay far above 1e-7); a run whose residual has made no new minimum (1 %
  * below the previous one) for floor_checks rounds retires as LBM_REQ_FLOOR with its residual
  * reported.  0 leaves the rule off.  *id receives the request id (ids count from 0 in
- * submission order).  Errors: those of lbm_footprint, LBM_ERR_INVALID_ARG, LBM_ERR_WORKSPACE
- * (the run can never fit in the pool), LBM_ERR_UNSUPPORTED for runs with wet-node boundaries
- * (bc_type), Picard iterations or analytic porosity derivatives, which lbm_create serves one
- * run at a time.
+ * submission order).  Runs with wet-node boundaries (bc_type), Picard iterations or analytic
+ * porosity derivatives are served too, each stepped with its own launches (as lbm_step) in
+ * every round instead of sharing the batched ones.  Errors: those of lbm_footprint,
+ * LBM_ERR_INVALID_ARG, LBM_ERR_WORKSPACE (the run can never fit in the pool).
  */
 LBM_API int lbm_server_submit(lbm_server *s, const lbm_params *p, double tol, int64_t max_steps,
                               int floor_checks, int64_t *id);

@@ -500,7 +500,9 @@ class Server:
                               bc_scheme=getattr(w, "bc_scheme", LBM_BC_NEEM),
                               bc_rho_rule=getattr(w, "bc_rho_rule", LBM_BC_RHO_CONTINUITY),
                               picard_iters=getattr(w, "picard_iters", 0),
-                              picard_omega=getattr(w, "picard_omega", 1.0))
+                              picard_omega=getattr(w, "picard_omega", 1.0),
+                              grad_eps=getattr(w, "grad_eps", None),
+                              hess_eps=getattr(w, "hess_eps", None))
         rid = self.submit_params(p, tol, max_steps, floor_checks)  # the library copies the arrays
         return rid
 

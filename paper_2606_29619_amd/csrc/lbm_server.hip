@@ -144,7 +144,11 @@ struct Request {
     int state = LBM_REQ_QUEUED;
     lbm_params p{};
     std::vector<double> eps, kappa, forch, rho_init, v_init;
-    std::vector<uint8_t> mask;
+    std::vector<double> bc_velocity, bc_density, grad_eps, hess_eps;
+    std::vector<uint8_t> mask, bc_type, bc_normal;
+    // stepped on its own (lbm_step) instead of in the batched launches: wet-node boundaries,
+    // Picard iterations or analytic porosity derivatives
+    bool solo = false;
     double tol = 0;
     int64_t max_steps = 0;
     int floor_checks = 0;       // rounds without a new minimum of the residual before retiring
@@ -405,11 +409,6 @@ LBM_API int lbm_server_submit(lbm_server *s, const lbm_params *p, double tol, in
     if (!(tol > 0) || max_steps < s->check_every)
         return fail(LBM_ERR_INVALID_ARG, "tol must be > 0 and max_steps >= check_every");
     if (floor_checks < 0) return fail(LBM_ERR_INVALID_ARG, "floor_checks must be >= 0");
-    if (p->bc_type || p->picard_iters || p->grad_eps || p->hess_eps)
-        return fail(LBM_ERR_UNSUPPORTED,
-                    "the server runs periodic / bounce-back runs with the one-shot velocity and "
-                    "differenced porosity derivatives (no bc_type, picard_iters = 0, no "
-                    "grad_eps / hess_eps)");
     size_t bytes = 0;
     rc = lbm_footprint(p, &bytes);
     if (rc) return rc;
@@ -439,6 +438,31 @@ LBM_API int lbm_server_submit(lbm_server *s, const lbm_params *p, double tol, in
         q->v_init.assign(p->v_init, p->v_init + (size_t)D * N);
         q->p.v_init = q->v_init.data();
     }
+    if (p->bc_type) {
+        q->bc_type.assign(p->bc_type, p->bc_type + N);
+        q->p.bc_type = q->bc_type.data();
+    }
+    if (p->bc_type && p->bc_normal) {
+        q->bc_normal.assign(p->bc_normal, p->bc_normal + N);
+        q->p.bc_normal = q->bc_normal.data();
+    }
+    if (p->bc_type && p->bc_velocity) {
+        q->bc_velocity.assign(p->bc_velocity, p->bc_velocity + (size_t)D * N);
+        q->p.bc_velocity = q->bc_velocity.data();
+    }
+    if (p->bc_type && p->bc_density) {
+        q->bc_density.assign(p->bc_density, p->bc_density + N);
+        q->p.bc_density = q->bc_density.data();
+    }
+    if (p->grad_eps) {
+        q->grad_eps.assign(p->grad_eps, p->grad_eps + (size_t)D * N);
+        q->p.grad_eps = q->grad_eps.data();
+    }
+    if (p->hess_eps) {
+        q->hess_eps.assign(p->hess_eps, p->hess_eps + (size_t)(D * (D + 1) / 2) * N);
+        q->p.hess_eps = q->hess_eps.data();
+    }
+    q->solo = p->bc_type || p->picard_iters || p->grad_eps || p->hess_eps;
     q->id = (int64_t)s->reqs.size();
     q->tol = tol;
     q->max_steps = max_steps;
@@ -467,10 +491,16 @@ LBM_API int lbm_server_progress(lbm_server *s, int64_t max_rounds, int64_t *fini
         rc = admit(s);
         if (rc) return fail(rc, "admission failed");
         if (s->active.empty()) break;
-        // groups of runs that share kernels
+        // groups of runs that share kernels; runs with per-run boundary kernels or iterations
+        // step on their own
         std::vector<Group> groups;
+        std::vector<Request *> solo;
         for (int64_t id : s->active) {
             Request *q = find_req(s, id);
+            if (q->solo) {
+                solo.push_back(q);
+                continue;
+            }
             const lbm_solver *h = q->h;
             const bool solids = h->solids;
             Group *g = nullptr;
@@ -491,11 +521,16 @@ LBM_API int lbm_server_progress(lbm_server *s, int64_t max_rounds, int64_t *fini
         for (int64_t k = 0; k < s->check_every; ++k)
             for (const auto &g : groups) group_dispatch(g, StepOp{s, g, k});
         LAUNCH_CHECK();
+        for (Request *q : solo) {  // advances the run's own step count, phase and records
+            rc = lbm_step(q->h, s->check_every);
+            if (rc) return rc;
+        }
         // statistics of every run, one synchronisation
         for (size_t r = 0; r < s->active.size(); ++r) {
             Request *q = find_req(s, s->active[r]);
             lbm_solver *h = q->h;
-            h->step += s->check_every;  // the round length is even: phase and records unchanged
+            if (!q->solo)  // the round length is even: phase and records unchanged
+                h->step += s->check_every;
             q->steps = h->step;
             s->cell_updates += (double)q->cells * (double)s->check_every;
             if (enqueue_stats(h) != LBM_OK) return LBM_ERR_HIP;

@@ -328,13 +328,20 @@ def test_edge_and_corner_node_validation():
     assert "diagonal" in str(ei.value) or "inward" in str(ei.value), str(ei.value)
 
 
-def test_server_rejects_boundary_runs():
-    (p, keep), _ = _bc_params()
+def test_server_queues_boundary_runs():
+    """Runs with wet-node boundaries are accepted (served on their own launches); a geometry
+    the solver would refuse is refused at submission."""
+    (p, keep), w = _bc_params()
     s = capi.lbm_server_create(_FAKE_POOL, 1 << 30, 100, 0, 0)
     try:
+        rid = capi.lbm_server_submit(s, p, 1e-7, 1000)
+        assert capi.lbm_server_info(s, rid).state == capi.LBM_REQ_QUEUED
+        bcn = w.bc_normal.copy()
+        bcn[0, 1, 0] = 4                   # -z on a D2Q9 grid
+        (p3, keep3), _ = _bc_params(bc_normal=bcn)
         with pytest.raises(capi.LbmError) as ei:
-            capi.lbm_server_submit(s, p, 1e-7, 1000)
-        assert ei.value.code == capi.LBM_ERR_UNSUPPORTED
+            capi.lbm_server_submit(s, p3, 1e-7, 1000)
+        assert ei.value.code == capi.LBM_ERR_INVALID_ARG
     finally:
         capi.lbm_server_destroy(s)
 
@@ -357,7 +364,7 @@ def test_picard_validation_and_footprint():
 
 def test_analytic_derivative_validation_and_footprint():
     """grad_eps and hess_eps go together, add D + D(D+1)/2 value planes to the workspace, must
-    be finite on fluid cells (solid cells are never read), and the server declines them."""
+    be finite on fluid cells (solid cells are never read), and the server queues such runs."""
     shape = (4, 5, 6)
     N = 120
     p, _k = _params(shape=shape)
@@ -385,9 +392,8 @@ def test_analytic_derivative_validation_and_footprint():
         assert expect in capi.lbm_last_error(), capi.lbm_last_error()
     srv = capi.lbm_server_create(_FAKE_POOL, 1 << 30, 100, 0, 0)
     try:
-        with pytest.raises(capi.LbmError) as ei:
-            capi.lbm_server_submit(srv, q, 1e-7, 1000)
-        assert ei.value.code == capi.LBM_ERR_UNSUPPORTED
+        rid = capi.lbm_server_submit(srv, q, 1e-7, 1000)
+        assert capi.lbm_server_info(srv, rid).state == capi.LBM_REQ_QUEUED
     finally:
         capi.lbm_server_destroy(srv)
 

@@ -229,3 +229,59 @@ def test_floor_rule_retires_runs_that_stop_improving():
     for rid in (r_floor, r_cap, r_64):
         srv.release(rid)
     srv.close()
+
+
+def test_served_boundary_runs_match_the_oracle():
+    """Runs with wet-node boundaries, Picard iterations or analytic porosity derivatives are
+    served on their own launches within the rounds of a batch: FP64 Couette walls (two-pass,
+    NEEM), an FP64 inlet/outlet box with corner nodes under the lagged scheme and an FP64
+    Picard run against the oracle within 1e-12; an FP32 pressure channel and an FP32 run with
+    analytic derivatives bitwise against the same runs stepped alone; all censored at 200
+    steps beside batched requests."""
+    import oracle
+    cw = workloads.couette_gravity_2d(H=24, scheme=1, rho_rule=0)
+    box = workloads.wet_box(2, (20, 10, 1), faces={"x-": "inlet", "x+": "pressure"}, V=0.01,
+                            nu=0.05, scheme=2, rho_rule=0)
+    pic = workloads.random_porosity_2d(nx=45, ny=33, seed=6, ell=3.0, nu=0.04, b=3e-4)
+    pic.picard_iters = 3
+    ch = workloads.pressure_channel(D=3, L=24, H=8, W=6, drho=2e-3, outflow=True, body=1e-5)
+    an = workloads.random_porosity_3d(shape=(10, 12, 40), seed=8, ell=3.0, nu=0.03, b=1e-5)
+    an.grad_eps = np.stack(np.gradient(an.eps, axis=(2, 1, 0)))   # any finite field will do
+    an.hess_eps = np.zeros((6,) + an.shape)
+    fill = _mix()
+    srv = capi.Server(pool_bytes=512 << 20, check_every=100)
+    ids = [srv.submit(w, storage=st, scheme=sc, tol=1e-300, max_steps=200)
+           for w, st, sc in fill[:4]]
+    cases = [(cw, capi.LBM_F64, capi.LBM_SCHEME_TWO_PASS, "oracle"),
+             (box, capi.LBM_F64, capi.LBM_SCHEME_LAGGED, "oracle"),
+             (pic, capi.LBM_F64, capi.LBM_SCHEME_TWO_PASS, "oracle"),
+             (ch, capi.LBM_F32, capi.LBM_SCHEME_TWO_PASS, "alone"),
+             (an, capi.LBM_F32, capi.LBM_SCHEME_TWO_PASS, "alone")]
+    rids = [srv.submit(w, storage=st, scheme=sc, tol=1e-300, max_steps=200)
+            for w, st, sc, _ in cases]
+    _drain(srv)
+    for rid, (w, st, sc, kind) in zip(rids, cases):
+        info = srv.info(rid)
+        assert info.state == capi.LBM_REQ_CENSORED and info.steps == 200, (rid, info.state)
+        if kind == "alone":
+            ok = _same(srv.solver(rid), _alone(w, st, sc, 200))
+            print(f"served request {rid} bitwise alone: {ok}", flush=True)
+            assert ok
+            continue
+        o = oracle.Oracle(oracle.OracleConfig(
+            D=w.D, eps=w.eps, kappa=w.kappa, cf=w.forch, mask=w.mask, RT=w.RT, nu_f=w.nu_f,
+            nu_eff_ref=w.nu_eff_ref, nu_eff_pow=w.nu_eff_pow, eta_eff=w.eta_eff, b=w.b,
+            rho0=w.rho0, rho_init=w.rho_init, v_init=w.v_init,
+            bc_type=getattr(w, "bc_type", None), bc_normal=getattr(w, "bc_normal", None),
+            bc_vel=getattr(w, "bc_velocity", None), bc_rho=getattr(w, "bc_density", None),
+            bc_scheme=getattr(w, "bc_scheme", 1), bc_density=getattr(w, "bc_rho_rule", 0),
+            picard_iters=getattr(w, "picard_iters", 0),
+            lagged=int(sc == capi.LBM_SCHEME_LAGGED)))
+        o.step(200)
+        errs = _field_err(srv.solver(rid), o)
+        print(f"served request {rid} vs oracle:",
+              " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+        assert max(errs.values()) <= 1e-12, errs
+    for rid in ids + rids:
+        srv.release(rid)
+    srv.close()
