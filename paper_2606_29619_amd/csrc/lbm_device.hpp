@@ -1189,17 +1189,38 @@ __device__ __forceinline__ void vcorrect_body(const P4<T> *__restrict__ own_src,
     store_rec<D>(m2_out, n, own.r, v);
 }
 
+// Loads of pair group K of a cell's populations in the arithmetic type (FP32 / FP64 storage).
+template <int D, bool SOLIDS, int PH, int K, typename T, typename P, typename E>
+__device__ __forceinline__ void load_pair_group(const P *__restrict__ f,
+                                                const uint8_t *__restrict__ mask, const Grid &g,
+                                                const Phys<T> &ph, const E &ev, const Nbr<D> &nb,
+                                                T (&fa)[Lat<D>::Q]) {
+    static_assert(!PopFmt<P>::shifted, "16-bit storage decodes after its loads");
+    unroll<PairGroups<D>::begin(K), PairGroups<D>::begin(K + 1)>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        fa[i] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
+    });
+}
+
 // Collision and streaming of the cell's populations with the equilibria peq, pst.  The
-// populations are loaded only after the forcing arguments, and in groups that are collided and
-// stored before the next group is loaded: fewer registers are live, so more waves share each
-// SIMD (16-bit storage: 3 -> 4 waves, 22 % faster).
-template <int D, typename T, typename P, bool SOLIDS, int PH, typename E>
+// populations are loaded only after the forcing arguments (FP32 / FP64 storage: except pair
+// groups [0, FIRST), which the caller loaded into fa), in pair groups, so that fewer registers
+// are live and more waves share each SIMD (16-bit storage: 3 -> 4 waves, 22 % faster).  With
+// FP32 / FP64 storage the loads of group k + 1 are issued before the stores of group k, which
+// can only reach slots that group k's own loads read (the AA pattern's slot of a population is
+// read and written by the same cell, and a group holds whole opposite pairs): 256^3 box, FP32
+// fused correction-collision kernel 0.885 -> 0.846 ms, FP64 2.05 -> 1.96 ms; the 16-bit forms
+// load, decode, collide and store one group after the other (pipelined, their fused kernel
+// spills: 0.75 -> 0.83 ms).
+template <int D, typename T, typename P, bool SOLIDS, int PH, int FIRST = 0, typename E>
 __device__ __forceinline__ void collide_populations(P *__restrict__ f,
                                                     const uint8_t *__restrict__ mask,
                                                     const Grid &g, const Phys<T> &ph,
                                                     const E &ev, const Nbr<D> &nb, T beta,
                                                     const ProductForm<D, T> &peq,
-                                                    const ProductForm<D, T> &pst) {
+                                                    const ProductForm<D, T> &pst,
+                                                    T (&fa)[Lat<D>::Q]) {
+    static_assert(FIRST == 0 || !PopFmt<P>::shifted, "preloaded groups: FP32 / FP64 storage");
     __builtin_amdgcn_sched_barrier(0);
     const T two_beta = T(2) * beta;
     const T omb = T(1) - beta;
@@ -1210,11 +1231,21 @@ __device__ __forceinline__ void collide_populations(P *__restrict__ f,
     // fast as before, and the recomputation cost 1 %.
     constexpr bool kOpaque = PH == 1 && sizeof(P) != 4;
     const Nbr<D> nbp = kOpaque ? nb.opaque() : nb;
-    unroll<0, PairGroups<D>::n>([&](auto gg) {
+    auto collide_store = [&](auto gg) {
         constexpr int k = decltype(gg)::value;
         constexpr int g0 = PairGroups<D>::begin(k), g1 = PairGroups<D>::begin(k + 1);
-        T fi[g1 - g0];
-        if constexpr (PopFmt<P>::shifted) {
+        unroll<g0, g1>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            const T feq = peq.template at<i>();
+            const T fst = pst.template at<i>();
+            const T fpc = (fa[i] + two_beta * (feq - fa[i])) + omb * (fst - feq);
+            store_pop<D, SOLIDS, PH, i>(f, mask, g, nbp, fpc, base);
+        });
+    };
+    if constexpr (PopFmt<P>::shifted) {
+        unroll<0, PairGroups<D>::n>([&](auto gg) {
+            constexpr int k = decltype(gg)::value;
+            constexpr int g0 = PairGroups<D>::begin(k), g1 = PairGroups<D>::begin(k + 1);
             // Every load of the group is issued before the first decode.  With the decode next
             // to its load the scheduler kept one BF16 load in flight at a time (256^3 box:
             // BF16 collision 0.835 -> 0.601 ms, FP16 0.630 -> 0.601 ms; same results).
@@ -1224,26 +1255,44 @@ __device__ __forceinline__ void collide_populations(P *__restrict__ f,
                 raw[i - g0] = load_raw<D, SOLIDS, PH, i>(f, mask, g, nbp);
             });
             __builtin_amdgcn_sched_barrier(0);
+            T fi[g1 - g0];
             unroll<g0, g1>([&](auto ii) {
                 constexpr int i = decltype(ii)::value;
                 fi[i - g0] = decode<D, i, T>(raw[i - g0],
                                              load_sigma<D, SOLIDS, i, P>(mask, ev, ph, nbp));
             });
-        } else {
             unroll<g0, g1>([&](auto ii) {
                 constexpr int i = decltype(ii)::value;
-                fi[i - g0] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nbp);
+                const T feq = peq.template at<i>();
+                const T fst = pst.template at<i>();
+                const T fpc = (fi[i - g0] + two_beta * (feq - fi[i - g0])) + omb * (fst - feq);
+                store_pop<D, SOLIDS, PH, i>(f, mask, g, nbp, fpc, base);
             });
-        }
-        unroll<g0, g1>([&](auto ii) {
-            constexpr int i = decltype(ii)::value;
-            const T feq = peq.template at<i>();
-            const T fst = pst.template at<i>();
-            const T fpc = (fi[i - g0] + two_beta * (feq - fi[i - g0])) + omb * (fst - feq);
-            store_pop<D, SOLIDS, PH, i>(f, mask, g, nbp, fpc, base);
+            __builtin_amdgcn_sched_barrier(0);
         });
-        __builtin_amdgcn_sched_barrier(0);
-    });
+    } else {
+        if constexpr (FIRST == 0)
+            load_pair_group<D, SOLIDS, PH, 0>(f, mask, g, ph, ev, nbp, fa);
+        unroll<0, PairGroups<D>::n>([&](auto gg) {
+            constexpr int k = decltype(gg)::value;
+            if constexpr (k + 1 < PairGroups<D>::n && k + 1 >= FIRST)
+                load_pair_group<D, SOLIDS, PH, k + 1>(f, mask, g, ph, ev, nbp, fa);
+            __builtin_amdgcn_sched_barrier(0);
+            collide_store(gg);
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    }
+}
+
+template <int D, typename T, typename P, bool SOLIDS, int PH, typename E>
+__device__ __forceinline__ void collide_populations(P *__restrict__ f,
+                                                    const uint8_t *__restrict__ mask,
+                                                    const Grid &g, const Phys<T> &ph,
+                                                    const E &ev, const Nbr<D> &nb, T beta,
+                                                    const ProductForm<D, T> &peq,
+                                                    const ProductForm<D, T> &pst) {
+    T fa[Lat<D>::Q];
+    collide_populations<D, T, P, SOLIDS, PH, 0>(f, mask, g, ph, ev, nb, beta, peq, pst, fa);
 }
 
 // Pass two of the two-pass scheme: forcing from the (rho, v) records, collision, streaming.
@@ -1395,8 +1444,14 @@ __global__ __launch_bounds__(256) void k_moments(const P *__restrict__ f,
             return;
         }
     }
-    moments_body<D, T, P, SOLIDS, PH, AD>(f, eps, muD, muF, mask, m1_out, m0_out, g, tl, ph,
-                                          blockIdx.x);
+    // FP32 storage without solids walks the tiles in their linear order rather than in one
+    // range per XCD: all XCDs then stream neighbouring rows at once (256^3 box 0.445 -> 0.435
+    // ms; FP64 and the 16-bit forms were 1-2 % slower so): workgroup w takes tile w, passed as
+    // the index (w % per) * 8 + w / per that the XCD mapping of tile_cell sends to w.
+    const uint32_t wt = !SOLIDS && std::is_same_v<P, float>
+                            ? (blockIdx.x % tl.per) * 8u + blockIdx.x / tl.per
+                            : blockIdx.x;
+    moments_body<D, T, P, SOLIDS, PH, AD>(f, eps, muD, muF, mask, m1_out, m0_out, g, tl, ph, wt);
 }
 
 // Velocity correction of a tile whose every cell has a uniform porosity neighbourhood: Delta_nu
@@ -1674,6 +1729,11 @@ __global__ __launch_bounds__((ZCfg<T, PS>::kThreads)) void k_collide_vc(PS *__re
             const EpsRing<T> ev{{es[eslot(zz - 1)] + qc, es[eslot(zz)] + qc, es[eslot(zz + 1)] + qc},
                                 kZSX};
             const uint32_t n = nb.self();
+            // FP32 / FP64: the first pair group's loads are in flight during the forcing
+            // (256^3 box, FP32 0.849 -> 0.822 ms, FP64 1.98 -> 1.89 ms)
+            T fa[27];
+            if constexpr (!PopFmt<PS>::shifted)
+                load_pair_group<D, false, PH, 0>(f, nullptr, g, ph, ev, nb, fa);
             const Rec<T> own = rec_at(vc[j], ev.at(0, 0, 0));
             const CellStatic<D, T> cs = cell_static<D, false>(ev, ph, n, own.e);
             Rec<T> rec[3][2];
@@ -1693,8 +1753,8 @@ __global__ __launch_bounds__((ZCfg<T, PS>::kThreads)) void k_collide_vc(PS *__re
             const T er = own.e * own.r;
             peq.init(er, xi, P);
             pst.init(er, xs, Ps);
-            collide_populations<D, T, PS, false, PH>(f, nullptr, g, ph, ev, nb, cs.vs.beta, peq,
-                                                     pst);
+            collide_populations<D, T, PS, false, PH, (PopFmt<PS>::shifted ? 0 : 1)>(
+                f, nullptr, g, ph, ev, nb, cs.vs.beta, peq, pst, fa);
         }
         __syncthreads();
     }
