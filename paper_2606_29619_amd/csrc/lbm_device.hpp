@@ -410,13 +410,14 @@ __device__ __forceinline__ uint32_t source_cell(const uint8_t *__restrict__ mask
 }
 
 // Raw slot holding f_I of cell n (AA pattern, halfway bounce-back in phase 1).
-template <int D, bool SOLIDS, int PH, int I, typename P>
+// FNT: non-temporal loads in the swapped phase too (the natural phase always uses them).
+template <int D, bool SOLIDS, int PH, int I, bool FNT = false, typename P>
 __device__ __forceinline__ P load_raw(const P *__restrict__ f, const uint8_t *__restrict__ mask,
                                       const Grid &g, const Nbr<D> &nb) {
     using L = Lat<D>;
     constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
     const uint32_t n = nb.self();
-    constexpr bool NT = PH == 0;
+    constexpr bool NT = PH == 0 || FNT;
     if constexpr (PH == 0 || (cx == 0 && cy == 0 && cz == 0)) {
         return ld_pop<NT>(plane(f, I, g.N), n);
     } else {
@@ -445,11 +446,11 @@ __device__ __forceinline__ float load_sigma(const uint8_t *__restrict__ mask, co
     }
 }
 
-template <int D, bool SOLIDS, int PH, int I, typename T, typename P, typename E>
+template <int D, bool SOLIDS, int PH, int I, bool FNT = false, typename T, typename P, typename E>
 __device__ __forceinline__ T load_pop(const P *__restrict__ f, const uint8_t *__restrict__ mask,
                                       const E &ev, const Phys<T> &ph, const Grid &g,
                                       const Nbr<D> &nb) {
-    const P raw = load_raw<D, SOLIDS, PH, I>(f, mask, g, nb);
+    const P raw = load_raw<D, SOLIDS, PH, I, FNT>(f, mask, g, nb);
     return decode<D, I, T>(raw, load_sigma<D, SOLIDS, I, P>(mask, ev, ph, nb));
 }
 
@@ -1154,10 +1155,12 @@ __device__ __forceinline__ void moments_body(const P *__restrict__ f,
             return;
         }
     }
+    // non-temporal loads in both phases (the pass reads each population line once): 256^3
+    // box, FP32 0.433 -> 0.423 ms, FP64 0.886 -> 0.870 ms
     T fi[L::Q];
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
+        fi[i] = load_pop<D, SOLIDS, PH, i, true>(f, mask, ev, ph, g, nb);
     });
     T v0[3];
     const Rec<T> q = cell_moments<D, AD>(fi, ev, muD, muF, nb, ph, m0_out ? v0 : nullptr);
