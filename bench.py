@@ -104,6 +104,8 @@ def cpu_baseline(budget_s=10.0, workload="box"):
         what = "the sphere-duct recipe at 1/8 scale (96 x 48 x 48, radius 12, bump m = 8)"
 
     def timed(threads):
+        print(f"[bench] cpu baseline: oracle on {threads or 'all'} thread(s), about "
+              f"{budget_s:.0f} s", file=sys.stderr, flush=True)
         prev = oracle.set_threads(threads)
         used = oracle.set_threads(0) if threads == 0 else threads
         try:
@@ -166,7 +168,8 @@ def serving_sample(n_requests, max_steps):
                      f"{serving.FLOOR_CHECKS} rounds for FP32/FP16; open run at 1.0x the "
                      f"closed-batch capacity of each storage form",
            "cells_total": int(sum(int(np.prod(q["shape"])) for q in stream))}
-    res = serving.serve_storages(stream, ["f64", "f32", "f16"], 1e-7, max_steps)
+    # progress lines every 10 s of serving (a long quiet stretch reads as a hung run)
+    res = serving.serve_storages(stream, ["f64", "f32", "f16"], 1e-7, max_steps, log=sys.stderr)
     for name, entry in res.items():
         c = entry["closed"]
         print(f"[bench] serving {name}: closed {c['served_MLUPS']} MLUPS, converged "
