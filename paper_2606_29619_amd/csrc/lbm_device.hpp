@@ -1534,20 +1534,21 @@ void k_collide(P *__restrict__ f, const P4<T> *__restrict__ m2, const P4<T> *__r
 // decode reads the porosity of each population's source cell from the staged planes).  The collision
 // of a cell reads the corrected velocity of the cell and its six face neighbours, and the
 // correction of a cell reads the (rho, v^(1)) records of its own six face neighbours.  A
-// workgroup of 1024 threads owns a 64 x 8 tile of cells and marches it through a chunk of
-// z-planes.  Its first eight waves correct the velocity of the tile and its one-cell ring in x
-// and y (652 cells, from the records of the moment pass exactly as the separate correction
-// pass reads them) two planes ahead, into a ring of four planes in LDS, while its last eight
-// waves collide the current plane from the ring; one barrier per plane.  The corrected
-// velocities never go through HBM (the separate pass writes them and the collision reads them
-// back, 32 B per cell), at the price of correcting the ring cells (1.27x) and the chunk's end
-// planes again.  The correcting waves read their records and porosity from planes staged in
+// workgroup owns a tile of cells (ZCfg: 128 x 4 in FP32) and marches it through a chunk of
+// z-planes.  Its first waves correct the velocity of the tile and its one-cell ring in x and y
+// (776 cells at 128 x 4, from the records of the moment pass exactly as the separate
+// correction pass reads them) two planes ahead, into a ring of four planes in LDS, while its
+// other waves (one thread per tile cell) collide the current plane from the ring; one barrier
+// per plane.  The corrected velocities never go through HBM (the separate pass writes them
+// and the collision reads them back, 32 B per cell), at the price of correcting the ring cells
+// (1.52x at 128 x 4) and the chunk's end planes again.  The correcting waves read their records and porosity from planes staged in
 // LDS (loaded once per plane, coalesced, two planes ahead), and the colliding waves read their
 // porosity there too.  256^3 box, FP32, per step: the separate passes 0.225 + 0.833 ms; 64 x 4
 // tiles with four correcting and four colliding waves 1.045 ms (with three or two correcting
 // waves 1.22 and 1.38 ms); 64 x 8 tiles 1.012 ms; staged correction inputs 0.959 ms; staged
-// collision porosity 0.906 ms (chunks of 128 planes).  Loading the next plane's first pair
-// group before the barrier changed nothing (0.906 / 0.907 ms).
+// collision porosity 0.906 ms (chunks of 128 planes); the shapes and thread counts of ZCfg and
+// the loads of collide_populations brought it to 0.815 ms.  Loading the next plane's first
+// pair group before the barrier did not pay (0.824 -> 0.844 ms).
 // With the two kinds of work in different waves, the correction's arithmetic and cached
 // gathers run beside the collision's HBM streams instead of between them.  Every expression
 // is the separate passes' own, so the results are bitwise the same.
@@ -1557,19 +1558,23 @@ struct ZTiling {
     uint32_t per;       // workgroups per XCD (padded)
 };
 // Shape of a fused workgroup for arithmetic type T and population storage P: a kX x kY tile
-// (kX * kY collision threads, as many correcting threads), the ring of corrected velocities
+// (kX * kY collision threads and kProd correcting threads), the ring of corrected velocities
 // (kRX x kRY) and the staged region of the correcting waves (the tile and two rings,
 // kSX x kSY).  FP32 takes 128 x 4 tiles: fewer tile edges in x, across which the swapped
 // phase's x-shifted accesses reach lines that another workgroup loads and stores (256^3 box:
 // 0.886 ms against 0.901 for 64 x 8, which corrects fewer ring cells); the 16-bit forms 64 x 8
 // (0.747 ms against 0.780); FP64 64 x 4, as its LDS rings would not fit 160 KB otherwise.
+// FP32 and the 16-bit forms correct with half as many threads as they collide with: 768
+// threads per workgroup leave each thread up to 168 registers instead of 128, which ends the
+// 16-bit collision's spills (FP16 0.763 -> 0.700 ms, FP32 0.828 -> 0.815 ms; a quarter as
+// many correcting threads made the 16-bit kernel correction-bound, 1.08 ms).
 template <typename T, typename P = T>
 struct ZCfg {
     static constexpr bool kF64 = sizeof(T) == 8, kHalf = sizeof(P) == 2;
     static constexpr int kX = kF64 || kHalf ? 64 : 128, kY = kF64 ? 4 : (kHalf ? 8 : 4);
     static constexpr int kRX = kX + 2, kRY = kY + 2, kR = kRX * kRY;
     static constexpr int kSX = kX + 4, kSY = kY + 4, kS = kSX * kSY;
-    static constexpr int kProd = kX * kY, kThreads = 2 * kX * kY;
+    static constexpr int kProd = kF64 ? kX * kY : kX * kY / 2, kThreads = kProd + kX * kY;
 };
 
 // Porosity of a cell's 3x3x3 neighbourhood from planes staged in LDS.
