@@ -1553,7 +1553,7 @@ void k_collide(P *__restrict__ f, const P4<T> *__restrict__ m2, const P4<T> *__r
 // gathers run beside the collision's HBM streams instead of between them.  Every expression
 // is the separate passes' own, so the results are bitwise the same.
 struct ZTiling {
-    int ntx, nty, nch;  // tiles along x (64 cells) and y (4 rows), chunks along z
+    int ntx, nty, nch;  // tiles along x (ZCfg::kX cells) and y (ZCfg::kY rows), chunks along z
     int zc;             // planes per chunk
     uint32_t per;       // workgroups per XCD (padded)
 };

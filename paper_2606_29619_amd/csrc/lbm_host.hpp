@@ -172,10 +172,10 @@ inline dim3 flat_grid(int64_t total) { return dim3((unsigned)((total + 255) / 25
 // Tiles of the fused correction-collision pass: tx x ty cells (nx % tx == 0, ny % ty == 0),
 // marched through chunks of zc z-planes, the eight XCDs taking contiguous ranges of the
 // x-fastest, then y, then chunk order (neighbouring tiles in y share their ring rows in the
-// XCD's L2).  One workgroup fills a CU (1024 threads in FP32, and LDS rings of 114 KB in FP32,
-// 146 KB in FP64), so the chunks are as long as 256 workgroups allow, between 8 and 128 planes:
-// long chunks correct and stage fewer end planes (256^3 box, FP32: chunks of 32, 64 and 128
-// planes 0.924, 0.936 and 0.906 ms).
+// XCD's L2).  One workgroup fills a CU (LDS rings of 143 KB in FP32, 114 KB for the 16-bit
+// forms, 146 KB in FP64), so the chunks are as long as 256 workgroups allow, between 8 and 128
+// planes: long chunks correct and stage fewer end planes (256^3 box, FP32, an earlier version
+// of the kernel: chunks of 32, 64 and 128 planes 0.924, 0.936 and 0.906 ms).
 inline lbm::ZTiling make_ztiling(int nx, int ny, int nz, int tx, int ty) {
     lbm::ZTiling z{};
     z.ntx = nx / tx;
