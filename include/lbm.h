@@ -219,7 +219,8 @@ typedef struct lbm_params {
     const double *grad_eps;
     const double *hess_eps;
     /* Workgroup tiles of the cell passes: LBM_TILES_AUTO picks rows of 256, 128 or 64 cells and,
-     * for FP64/FP32 storage with an x extent that is not a multiple of 64, packed rows (256
+     * for an x extent that is not a multiple of 64 (16-bit storage: D3Q27 runs whose rows would
+     * leave at least 30 % of the lanes idle), packed rows (256
      * consecutive cells of a plane, wrapping from row to row); LBM_TILES_RECTANGULAR never
      * packs.  The tiles decide only which thread updates which cell: results are bitwise the
      * same. */

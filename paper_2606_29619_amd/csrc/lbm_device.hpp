@@ -1137,9 +1137,10 @@ __device__ __forceinline__ void collide_stream(P *__restrict__ f,
     });
 }
 
-// Pass one of the two-pass scheme: the record (rho, v^(1)) of every cell.
-template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
-__device__ __forceinline__ void moments_body(const P *__restrict__ f,
+// Pass one of the two-pass scheme: the record (rho, v^(1)) of every cell.  STAGE: the porosity
+// of the tile and its halo is staged in LDS (16-bit storage on rectangular tiles).
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD, bool STAGE>
+__device__ __forceinline__ void moments_body_s(const P *__restrict__ f,
                                                  const T *__restrict__ eps,
                                                  const T *__restrict__ muD,
                                                  const T *__restrict__ muF,
@@ -1147,7 +1148,7 @@ __device__ __forceinline__ void moments_body(const P *__restrict__ f,
                                                  P4<T> *__restrict__ m1_out,
                                                  P4<T> *__restrict__ m0_out, Grid g, Tiling tl,
                                                  Phys<T> ph, uint32_t wg) {
-    LBM_TILE_PROLOGUE(D, wg, (PopFmt<P>::shifted))
+    LBM_TILE_PROLOGUE(D, wg, (STAGE))
     using L = Lat<D>;
     if constexpr (SOLIDS) {
         if (mask[n]) {
@@ -1326,8 +1327,8 @@ __device__ __forceinline__ void collide_body(P *__restrict__ f,
 // Phi^eta are the previous step's records (m1p: rho, v^(1); m2p: rho, v).  The cell's new
 // records go to m1n / m2n for the next step.  A steady state of this scheme is a steady state
 // of the two-pass scheme.
-template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
-__device__ __forceinline__ void fused_body(P *__restrict__ f, const P4<T> *__restrict__ m1p,
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD, bool STAGE>
+__device__ __forceinline__ void fused_body_s(P *__restrict__ f, const P4<T> *__restrict__ m1p,
                                                const P4<T> *__restrict__ m2p,
                                                P4<T> *__restrict__ m1n, P4<T> *__restrict__ m2n,
                                                const T *__restrict__ eps,
@@ -1335,7 +1336,7 @@ __device__ __forceinline__ void fused_body(P *__restrict__ f, const P4<T> *__res
                                                const T *__restrict__ muF,
                                                const uint8_t *__restrict__ mask, Grid g,
                                                Tiling tl, Phys<T> ph, uint32_t wg) {
-    LBM_TILE_PROLOGUE(D, wg, (PopFmt<P>::shifted))
+    LBM_TILE_PROLOGUE(D, wg, (STAGE))
     using L = Lat<D>;
     if constexpr (SOLIDS) {
         if (mask[n]) {
@@ -1418,6 +1419,44 @@ __global__ __launch_bounds__(256) void k_picard(const P4<T> *__restrict__ vin,
                                                 P4<T> *__restrict__ vout, Grid g, Tiling tl,
                                                 Phys<T> ph, T omega) {
     picard_body<D, T, SOLIDS, AD>(vin, m0, eps, muD, muF, mask, vout, g, tl, ph, omega, blockIdx.x);
+}
+
+// The moment and lagged passes of a tile: 16-bit storage stages the porosity its decode reads
+// in LDS on rectangular tiles and reads it through the caches on packed rows (ragged x extents),
+// whose tiles have no rectangular halo.  Same values either way.
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
+__device__ __forceinline__ void moments_body(const P *__restrict__ f, const T *__restrict__ eps,
+                                             const T *__restrict__ muD, const T *__restrict__ muF,
+                                             const uint8_t *__restrict__ mask,
+                                             P4<T> *__restrict__ m1_out, P4<T> *__restrict__ m0_out,
+                                             Grid g, Tiling tl, Phys<T> ph, uint32_t wg) {
+    if constexpr (PopFmt<P>::shifted) {
+        if (tl.packed) {
+            moments_body_s<D, T, P, SOLIDS, PH, AD, false>(f, eps, muD, muF, mask, m1_out, m0_out,
+                                                           g, tl, ph, wg);
+            return;
+        }
+    }
+    moments_body_s<D, T, P, SOLIDS, PH, AD, PopFmt<P>::shifted>(f, eps, muD, muF, mask, m1_out,
+                                                                 m0_out, g, tl, ph, wg);
+}
+
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
+__device__ __forceinline__ void fused_body(P *__restrict__ f, const P4<T> *__restrict__ m1p,
+                                           const P4<T> *__restrict__ m2p, P4<T> *__restrict__ m1n,
+                                           P4<T> *__restrict__ m2n, const T *__restrict__ eps,
+                                           const T *__restrict__ muD, const T *__restrict__ muF,
+                                           const uint8_t *__restrict__ mask, Grid g, Tiling tl,
+                                           Phys<T> ph, uint32_t wg) {
+    if constexpr (PopFmt<P>::shifted) {
+        if (tl.packed) {
+            fused_body_s<D, T, P, SOLIDS, PH, AD, false>(f, m1p, m2p, m1n, m2n, eps, muD, muF,
+                                                         mask, g, tl, ph, wg);
+            return;
+        }
+    }
+    fused_body_s<D, T, P, SOLIDS, PH, AD, PopFmt<P>::shifted>(f, m1p, m2p, m1n, m2n, eps, muD,
+                                                               muF, mask, g, tl, ph, wg);
 }
 
 // Single-run kernels: workgroup w handles tile w of the run.

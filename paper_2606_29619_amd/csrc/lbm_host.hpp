@@ -188,9 +188,11 @@ inline lbm::ZTiling make_ztiling(int nx, int ny, int nz, int tx, int ty) {
 }
 
 // Tiles of the cell passes.  Rectangular tiles (256 x 1, 128 x 2 or 64 x 4 cells) when the x
-// extent is a multiple of 64 or the kernels stage porosity in LDS (16-bit storage, which needs
-// rectangular halos); packed rows otherwise, so that rows of, say, 70 cells do not leave most
-// of a second wave idle.
+// extent is a multiple of 64 (or the caller asks for them); packed rows otherwise, so that rows
+// of, say, 70 cells do not leave most of a second wave idle.
+// Width of the rectangular row tiles for an x extent nx.
+inline int rect_tile_x(int nx) { return nx >= 192 ? 256 : (nx >= 96 ? 128 : 64); }
+
 inline lbm::Tiling make_tiling(int nx, int ny, int nz, bool packed_ok = false) {
     lbm::Tiling t{};
     if (packed_ok && nx % 64 != 0) {
@@ -203,7 +205,7 @@ inline lbm::Tiling make_tiling(int nx, int ny, int nz, bool packed_ok = false) {
         t.nty = (int)((t.pn + 255u) / 256u);
         t.mnx = nx >= 2 ? ~uint64_t(0) / (uint64_t)nx + 1 : 0;
     } else {
-        t.tx = nx >= 192 ? 256 : (nx >= 96 ? 128 : 64);
+        t.tx = rect_tile_x(nx);
         t.ltx = t.tx == 256 ? 8 : (t.tx == 128 ? 7 : 6);
         t.ty = 256 / t.tx;
         t.ntx = (nx + t.tx - 1) / t.tx;

@@ -244,17 +244,23 @@ def test_solid_free_tiles_match_oracle(D, lagged, storage):
         assert errs["f"] < 1e-4 and errs["rho"] < 1e-4, errs
 
 
-@pytest.mark.parametrize("storage,lagged", [("f64", False), ("f32", False), ("f32", True)])
+@pytest.mark.parametrize("storage,lagged", [("f64", False), ("f32", False), ("f32", True),
+                                            ("f16", False), ("f16", True), ("bf16", False),
+                                            ("bf16", True)])
 def test_packed_rows_match_rectangular_tiles(storage, lagged):
-    """Runs whose x extent is not a multiple of 64 use packed-row tiles (FP32/FP64); the tile
-    mapping decides only which thread updates which cell, so the result is bitwise that of the
-    rectangular tiles (ragged 70 x 13 x 9 with solid blocks, both AA phases)."""
+    """Runs whose x extent is not a multiple of 64 use packed-row tiles; the tile mapping
+    decides only which thread updates which cell, so the result is bitwise that of the
+    rectangular tiles (ragged 70 x 13 x 9 with solid blocks, both AA phases).  The 16-bit forms
+    (porous shift) read the porosity of their decode through the caches on packed rows and from
+    LDS on rectangular tiles (45 % of the lanes of 70-cell rows idle: packed)."""
     w = _solids_3d(shape=(9, 13, 70))
-    st = capi.LBM_F64 if storage == "f64" else capi.LBM_F32
+    st = {"f64": capi.LBM_F64, "f32": capi.LBM_F32, "f16": capi.LBM_F16_SHIFTED,
+          "bf16": capi.LBM_BF16_SHIFTED}[storage]
     scheme = capi.LBM_SCHEME_LAGGED if lagged else capi.LBM_SCHEME_TWO_PASS
     out = []
     for tiles in (capi.LBM_TILES_AUTO, capi.LBM_TILES_RECTANGULAR):
-        s = capi.Solver.from_workload(w, storage=st, scheme=scheme, tiles=tiles)
+        s = capi.Solver.from_workload(w, storage=st, scheme=scheme, tiles=tiles,
+                                      shift=capi.LBM_SHIFT_POROUS)
         s.step(21)
         f = s.populations(torch.float64).cpu().numpy()
         rho, v = (t.cpu().numpy() for t in s.moments(torch.float64))
