@@ -44,6 +44,7 @@ def _mix():
         (b, capi.LBM_F32, capi.LBM_SCHEME_TWO_PASS),
         (a, capi.LBM_F64, capi.LBM_SCHEME_LAGGED),
         (c, capi.LBM_F32, capi.LBM_SCHEME_LAGGED),
+        (c, capi.LBM_F16_SHIFTED, capi.LBM_SCHEME_TWO_PASS),   # 16-bit on packed rows
     ]
 
 
@@ -72,7 +73,7 @@ def _drain(srv, max_rounds=10000):
 
 
 def test_each_result_is_bitwise_the_same_alone_and_in_the_mix():
-    """Eight runs of every kind share the batched launches for 300 steps (censored: the
+    """Nine runs of every kind share the batched launches for 300 steps (censored: the
     tolerance is unreachable); each run's populations and moments equal, bit for bit, those
     of the same run stepped alone with lbm_step."""
     srv = capi.Server(pool_bytes=512 << 20, check_every=100)
