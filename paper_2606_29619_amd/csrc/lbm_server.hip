@@ -72,8 +72,8 @@ __global__ __launch_bounds__(256) void kb_collide(const RunDesc<T, P> *__restric
                                                   const uint32_t *__restrict__ starts, int nrun) {
     const int r = find_run(starts, nrun, blockIdx.x);
     const RunDesc<T, P> &d = runs[r];
-    collide_body<D, T, P, S, PH, false>(d.f, d.m2[0], d.m2[0], d.eps, d.muD, d.muF, d.mask, d.g, d.tl, d.ph,
-                                 blockIdx.x - starts[r]);
+    collide_body<D, T, P, S, PH, false>(d.f, d.m2[0], d.m2[0], d.eps, d.muD, d.muF, d.mask, d.g,
+                                        d.tl, d.ph, blockIdx.x - starts[r]);
 }
 
 // parity: the step's position in the round (mod 2); the previous records alternate with it.
