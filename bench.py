@@ -234,7 +234,10 @@ def measure(w, desc, storage, shift, scheme, steps, warmup, src, kind="box", n=2
     del solver
     torch.cuda.empty_cache()
     Q, D = 27, 3
-    if lagged:
+    # a lagged step with wet-node boundaries runs as separate passes (moment, correction and
+    # collision kernels timed apart), whose bytes are those of the two-pass kernels
+    separate_lagged = lagged and (kms[0] > 0.0 or kms[1] > 0.0)
+    if lagged and not separate_lagged:
         kb = {"fused": lagged_bytes_per_cell(Q, D, sp_bytes, s_bytes, msk)}
         avg_ms = {"fused": kms[2] / steps}
     else:
@@ -260,8 +263,9 @@ def measure(w, desc, storage, shift, scheme, steps, warmup, src, kind="box", n=2
         "ms_per_step": round(wall / steps * 1e3, 4),
         "dtype": "f64" if storage == "f64" else "f32",
         "config": {"workload": desc, "lattice": "D3Q27", "cells": N,
-                   "scheme": scheme if lagged or "collide" in avg_ms
-                   else "two-pass, velocity correction inside the collision pass",
+                   "scheme": ("lagged, separate passes (wet-node boundaries)" if separate_lagged
+                              else scheme if lagged or "collide" in avg_ms
+                              else "two-pass, velocity correction inside the collision pass"),
                    "storage": storage if sp_bytes != 2 else f"{storage} shifted ({shift})"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",

@@ -509,6 +509,9 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
         return cleanup(fail(LBM_ERR_HIP, "upload of mask failed: %s", hipGetErrorString(e)));
     if (solids) {
         uint8_t *ts = reinterpret_cast<uint8_t *>(h->ws + L.tsolid);
+        // padding workgroups past the last tile write no flag
+        if ((e = hipMemsetAsync(ts, 0, 8 * (size_t)h->tiles.per, h->stream)) != hipSuccess)
+            return cleanup(fail(LBM_ERR_HIP, "tile-flag clear failed: %s", hipGetErrorString(e)));
         if (D == 2) hipLaunchKernelGGL(lbm::k_tile_solid<2>, cell_tiles(h), dim3(256), 0, h->stream, mask_ptr(h), grid_of(h), h->tiles, ts);
         else hipLaunchKernelGGL(lbm::k_tile_solid<3>, cell_tiles(h), dim3(256), 0, h->stream, mask_ptr(h), grid_of(h), h->tiles, ts);
         if ((e = hipGetLastError()) != hipSuccess)
@@ -615,6 +618,17 @@ LBM_API int lbm_create(const lbm_params *p, void *dev_workspace, size_t workspac
         return cleanup(fail(LBM_ERR_HIP, "snapshot clear failed: %s", hipGetErrorString(e)));
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess)
         return cleanup(fail(LBM_ERR_HIP, "initialisation failed: %s", hipGetErrorString(e)));
+    if (solids) {
+        // share of solid-aware tiles, which decides the occupancy request of the kernels
+        std::vector<uint8_t> flags(8 * (size_t)h->tiles.per);
+        if ((e = hipMemcpyAsync(flags.data(), h->ws + L.tsolid, flags.size(),
+                                hipMemcpyDeviceToHost, h->stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+            return cleanup(fail(LBM_ERR_HIP, "tile-flag read failed: %s", hipGetErrorString(e)));
+        size_t aware = 0;
+        for (uint8_t v : flags) aware += v != 0;
+        h->solid_occ = 4 * aware < flags.size();
+    }
     *out = h;
     return LBM_OK;
 }

@@ -1540,18 +1540,22 @@ __global__ __launch_bounds__(256) void k_vcorrect(const P4<T> *__restrict__ own_
 // occupancy of the solid-free code is requested and the solid-aware code spills a few values
 // instead (D3Q27 sphere duct, 768 x 384 x 384: 16-bit collision 5.24 -> 4.62 ms, 16-bit lagged
 // pass 9.47 -> 8.29 ms, FP64 swapped-phase collision 12.13 -> 11.89 ms; the same for FP32 cost
-// 2 %, so FP32 requests nothing).  1 requests nothing.
-template <int D, typename T, typename P, bool SOLIDS, int PH>
+// 2 %, so FP32 requests nothing).  That holds where few tiles are solid-aware (4 % in that
+// duct); where most are (the pressure-driven duct's solid x faces make two of every row's three
+// tiles solid-aware) the spills cost more than the occupancy gains (FP16 collision 12.70 ->
+// 8.55 ms without the request), so the host launches the requesting instantiation (OCC) only
+// for runs whose tiles are less than a quarter solid-aware.  1 requests nothing.
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool OCC = true>
 struct SolidAwareWaves {
-    static constexpr bool on = SOLIDS && D == 3;
+    static constexpr bool on = SOLIDS && D == 3 && OCC;
     static constexpr bool half = sizeof(P) == 2, fp64 = sizeof(T) == 8;
     static constexpr int collide = !on ? 1 : half ? (PH == 1 ? 5 : 6) : (fp64 && PH == 1 ? 3 : 1);
     static constexpr int fused = on && half && PH == 0 ? 3 : 1;
 };
 
-template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD, bool OCC>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(SolidAwareWaves<D, T, P, SOLIDS, PH>::collide)))
+__attribute__((amdgpu_waves_per_eu(SolidAwareWaves<D, T, P, SOLIDS, PH, OCC>::collide)))
 void k_collide(P *__restrict__ f, const P4<T> *__restrict__ m2, const P4<T> *__restrict__ nbr,
                const T *__restrict__ eps, const T *__restrict__ muD, const T *__restrict__ muF,
                const uint8_t *__restrict__ mask, const uint8_t *__restrict__ tsolid, Grid g,
@@ -1807,9 +1811,9 @@ __global__ __launch_bounds__((ZCfg<T, PS>::kThreads)) void k_collide_vc(PS *__re
     }
 }
 
-template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD>
+template <int D, typename T, typename P, bool SOLIDS, int PH, bool AD, bool OCC>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(SolidAwareWaves<D, T, P, SOLIDS, PH>::fused)))
+__attribute__((amdgpu_waves_per_eu(SolidAwareWaves<D, T, P, SOLIDS, PH, OCC>::fused)))
 void k_fused(P *__restrict__ f, const P4<T> *__restrict__ m1p, const P4<T> *__restrict__ m2p,
              P4<T> *__restrict__ m1n, P4<T> *__restrict__ m2n, const T *__restrict__ eps,
              const T *__restrict__ muD, const T *__restrict__ muF,

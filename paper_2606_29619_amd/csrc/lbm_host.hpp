@@ -124,6 +124,7 @@ struct lbm_solver {
     bool analytic;      // analytic porosity derivatives in L.deps
     lbm::Tiling tiles;  // 256-cell tiles, blocked, in XCD-contiguous ranges
     bool fused_vc;      // velocity correction inside the collision pass (k_collide_vc)
+    bool solid_occ;     // runs with solids: under a quarter of the tiles solid-aware
     lbm::ZTiling ztiles;
     int device;         // HIP device current at creation
 };

@@ -44,15 +44,28 @@ void launch_vcorrect(const lbm_solver *h, size_t own_src, size_t m1, size_t m2_o
                        ws_ptr<lbm::P4<T>>(h, m2_out), grid_of(h), h->tiles, ph);
 }
 
-template <int D, typename T, typename P, bool S, int PH, bool AD>
-void launch_collide(const lbm_solver *h, size_t m2, size_t nbr) {
+template <int D, typename T, typename P, bool S, int PH, bool AD, bool OCC>
+void launch_collide_occ(const lbm_solver *h, size_t m2, size_t nbr) {
     auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_collide<D, T, P, S, PH, AD>), cell_tiles(h), dim3(256), 0, h->stream,
-                       ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
+    hipLaunchKernelGGL((lbm::k_collide<D, T, P, S, PH, AD, OCC>), cell_tiles(h), dim3(256), 0,
+                       h->stream, ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, m2),
                        ws_ptr<const lbm::P4<T>>(h, nbr),
                        ws_ptr<const T>(h, h->L.eps),
                        ws_ptr<const T>(h, h->L.muD), ws_ptr<const T>(h, h->L.muF), mask_ptr(h),
                        tsolid_ptr(h), grid_of(h), h->tiles, ph);
+}
+
+// Runs with solids take the instantiation that requests the occupancy of the solid-free code
+// where few of their tiles are solid-aware (lbm_solver::solid_occ).
+template <int D, typename T, typename P, bool S, int PH, bool AD>
+void launch_collide(const lbm_solver *h, size_t m2, size_t nbr) {
+    if constexpr (S) {
+        if (h->solid_occ) {
+            launch_collide_occ<D, T, P, S, PH, AD, true>(h, m2, nbr);
+            return;
+        }
+    }
+    launch_collide_occ<D, T, P, S, PH, AD, false>(h, m2, nbr);
 }
 
 template <int D, typename T, typename P, bool S, int PH>
@@ -64,16 +77,27 @@ void launch_collide_vc(const lbm_solver *h, size_t m1) {
                            ws_ptr<const T>(h, h->L.muF), grid_of(h), h->ztiles, phys_of<T>(h));
 }
 
-template <int D, typename T, typename P, bool S, int PH, bool AD>
-void launch_fused(const lbm_solver *h, int prev, int next) {
+template <int D, typename T, typename P, bool S, int PH, bool AD, bool OCC>
+void launch_fused_occ(const lbm_solver *h, int prev, int next) {
     auto ph = phys_of<T>(h);
-    hipLaunchKernelGGL((lbm::k_fused<D, T, P, S, PH, AD>), cell_tiles(h), dim3(256), 0, h->stream,
+    hipLaunchKernelGGL((lbm::k_fused<D, T, P, S, PH, AD, OCC>), cell_tiles(h), dim3(256), 0, h->stream,
                        ws_ptr<P>(h, h->L.f), ws_ptr<const lbm::P4<T>>(h, h->L.m1[prev]),
                        ws_ptr<const lbm::P4<T>>(h, h->L.m2[prev]),
                        ws_ptr<lbm::P4<T>>(h, h->L.m1[next]), ws_ptr<lbm::P4<T>>(h, h->L.m2[next]),
                        ws_ptr<const T>(h, h->L.eps), ws_ptr<const T>(h, h->L.muD),
                        ws_ptr<const T>(h, h->L.muF), mask_ptr(h), tsolid_ptr(h), grid_of(h),
                        h->tiles, ph);
+}
+
+template <int D, typename T, typename P, bool S, int PH, bool AD>
+void launch_fused(const lbm_solver *h, int prev, int next) {
+    if constexpr (S) {
+        if (h->solid_occ) {
+            launch_fused_occ<D, T, P, S, PH, AD, true>(h, prev, next);
+            return;
+        }
+    }
+    launch_fused_occ<D, T, P, S, PH, AD, false>(h, prev, next);
 }
 
 template <int D, typename T, typename P, bool S, bool AD>
