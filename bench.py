@@ -236,7 +236,8 @@ def measure(w, desc, storage, shift, scheme, steps, warmup, src, kind="box", n=2
     Q, D = 27, 3
     # a lagged step with wet-node boundaries runs as separate passes (moment, correction and
     # collision kernels timed apart), whose bytes are those of the two-pass kernels
-    separate_lagged = lagged and (kms[0] > 0.0 or kms[1] > 0.0)
+    bct = getattr(w, "bc_type", None)
+    separate_lagged = lagged and bct is not None and bool((np.asarray(bct) > 0).any())
     if lagged and not separate_lagged:
         kb = {"fused": lagged_bytes_per_cell(Q, D, sp_bytes, s_bytes, msk)}
         avg_ms = {"fused": kms[2] / steps}
