@@ -128,8 +128,10 @@ __device__ __forceinline__ T ld(const T *base, uint32_t idx) {
 
 // Populations stream through once per kernel.  In the natural-layout phase each thread touches
 // only its own cell, and the accesses are non-temporal (the caches are left to the reused
-// moment and porosity fields).  In the swapped phase the x-shifted accesses of neighbouring
-// lanes share cache lines, so they go through the caches normally.
+// moment and porosity fields).  In the swapped phase the x-shifted accesses (c_x != 0) of
+// neighbouring lanes and waves share cache lines, so they go through the caches normally, while
+// those with c_x = 0 cover whole lines of one wave and stay non-temporal (256^3 box: FP32 step
+// 1.236 -> 1.227 ms, FP32 lagged pass 1.050 -> 1.026 ms).
 template <bool NT, typename T>
 __device__ __forceinline__ T ld_pop(const T *base, uint32_t idx) {
     if constexpr (NT) return __builtin_nontemporal_load(at(base, idx));
@@ -417,7 +419,7 @@ __device__ __forceinline__ P load_raw(const P *__restrict__ f, const uint8_t *__
     using L = Lat<D>;
     constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
     const uint32_t n = nb.self();
-    constexpr bool NT = PH == 0 || FNT;
+    constexpr bool NT = PH == 0 || FNT || cx == 0;
     if constexpr (PH == 0 || (cx == 0 && cy == 0 && cz == 0)) {
         return ld_pop<NT>(plane(f, I, g.N), n);
     } else {
@@ -462,7 +464,7 @@ __device__ __forceinline__ void store_pop(P *__restrict__ f, const uint8_t *__re
     using L = Lat<D>;
     constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
     const uint32_t n = nb.self();
-    constexpr bool NT = PH == 0;
+    constexpr bool NT = PH == 0 || cx == 0;
     const P raw = encode<D, I, P>(val, base * weight<D, I>());
     if constexpr (PH == 0 || (cx == 0 && cy == 0 && cz == 0)) {
         st_pop<NT>(plane(f, L::opp[I], g.N), n, raw);
