@@ -131,7 +131,8 @@ __device__ __forceinline__ T ld(const T *base, uint32_t idx) {
 // moment and porosity fields).  In the swapped phase the x-shifted accesses (c_x != 0) of
 // neighbouring lanes and waves share cache lines, so they go through the caches normally, while
 // those with c_x = 0 cover whole lines of one wave and stay non-temporal (256^3 box: FP32 step
-// 1.236 -> 1.227 ms, FP32 lagged pass 1.050 -> 1.026 ms).
+// 1.236 -> 1.218 ms, FP32 lagged pass 1.050 -> 1.026 ms; the moment pass with every load of the
+// swapped phase non-temporal was 0.6 % slower than with this rule).
 template <bool NT, typename T>
 __device__ __forceinline__ T ld_pop(const T *base, uint32_t idx) {
     if constexpr (NT) return __builtin_nontemporal_load(at(base, idx));
@@ -412,14 +413,13 @@ __device__ __forceinline__ uint32_t source_cell(const uint8_t *__restrict__ mask
 }
 
 // Raw slot holding f_I of cell n (AA pattern, halfway bounce-back in phase 1).
-// FNT: non-temporal loads in the swapped phase too (the natural phase always uses them).
-template <int D, bool SOLIDS, int PH, int I, bool FNT = false, typename P>
+template <int D, bool SOLIDS, int PH, int I, typename P>
 __device__ __forceinline__ P load_raw(const P *__restrict__ f, const uint8_t *__restrict__ mask,
                                       const Grid &g, const Nbr<D> &nb) {
     using L = Lat<D>;
     constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
     const uint32_t n = nb.self();
-    constexpr bool NT = PH == 0 || FNT || cx == 0;
+    constexpr bool NT = PH == 0 || cx == 0;
     if constexpr (PH == 0 || (cx == 0 && cy == 0 && cz == 0)) {
         return ld_pop<NT>(plane(f, I, g.N), n);
     } else {
@@ -448,11 +448,11 @@ __device__ __forceinline__ float load_sigma(const uint8_t *__restrict__ mask, co
     }
 }
 
-template <int D, bool SOLIDS, int PH, int I, bool FNT = false, typename T, typename P, typename E>
+template <int D, bool SOLIDS, int PH, int I, typename T, typename P, typename E>
 __device__ __forceinline__ T load_pop(const P *__restrict__ f, const uint8_t *__restrict__ mask,
                                       const E &ev, const Phys<T> &ph, const Grid &g,
                                       const Nbr<D> &nb) {
-    const P raw = load_raw<D, SOLIDS, PH, I, FNT>(f, mask, g, nb);
+    const P raw = load_raw<D, SOLIDS, PH, I>(f, mask, g, nb);
     return decode<D, I, T>(raw, load_sigma<D, SOLIDS, I, P>(mask, ev, ph, nb));
 }
 
@@ -1158,12 +1158,10 @@ __device__ __forceinline__ void moments_body_s(const P *__restrict__ f,
             return;
         }
     }
-    // non-temporal loads in both phases (the pass reads each population line once): 256^3
-    // box, FP32 0.433 -> 0.423 ms, FP64 0.886 -> 0.870 ms
     T fi[L::Q];
     unroll<0, L::Q>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        fi[i] = load_pop<D, SOLIDS, PH, i, true>(f, mask, ev, ph, g, nb);
+        fi[i] = load_pop<D, SOLIDS, PH, i>(f, mask, ev, ph, g, nb);
     });
     T v0[3];
     const Rec<T> q = cell_moments<D, AD>(fi, ev, muD, muF, nb, ph, m0_out ? v0 : nullptr);
